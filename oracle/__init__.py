@@ -1,0 +1,291 @@
+"""CPU oracle for all-pairs shortest paths -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The HIP library never imports, links or
+calls it, and it imports nothing from the HIP library: the two share no code.
+
+Contents
+  fw(W)                 classic Floyd-Warshall (paper Sect. 2.2, Algorithm 1,
+                        strict update test), int64 when every finite weight is an
+                        integer, else float64.  Returns (D, P).
+  dijkstra_rows(W, src) per-source Dijkstra with lexicographic labels
+                        (length, largest interior vertex): rows of D and of the
+                        canonical P without the cubic loop.
+  brute_force(W)        enumeration of every simple path, n <= 8: the definition
+                        of (D, P) written out.
+  backward_pathwalk     dL/dW from dL/dD by walking each pair's shortest path.
+  reconstruct(P, i, j)  vertex list of the path P encodes.
+  check_invariants      D[i][i] = 0, D <= W, triangle inequality, P never names
+                        an endpoint, and every encoded path exists, sums to D and
+                        is canonical.
+
+Parity status of each function and the pins that fix it are listed in the design doc.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fw_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+I64_INF = np.iinfo(np.int64).max
+
+
+def build(src: str = _SRC, out: str = _LIB) -> str:
+    """Compile the C oracle with gcc (-O2, OpenMP, no fast-math)."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", "-Wall", "-o", out, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out
+
+
+def load(path: str = _LIB):
+    """Load a compiled oracle library (default: the in-tree one, building it if absent)."""
+    global _lib
+    if path == _LIB and _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        if path != _LIB:
+            raise FileNotFoundError(path)
+        build()
+    lib = ctypes.CDLL(path)
+    i64, i32p, vp = ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p
+    lib.oracle_fw_f64.argtypes = [i64, vp, vp, ctypes.c_int]
+    lib.oracle_fw_i64.argtypes = [i64, vp, vp, ctypes.c_int]
+    lib.oracle_dijkstra_rows_f64.argtypes = [i64, vp, i64, vp, vp, vp, ctypes.c_int]
+    lib.oracle_dijkstra_rows_i64.argtypes = [i64, vp, i64, vp, vp, vp, ctypes.c_int]
+    lib.oracle_backward_pathwalk_f64.argtypes = [i64, vp, vp, vp, vp]
+    lib.oracle_backward_pathwalk_f64.restype = ctypes.c_int
+    lib.oracle_reconstruct.argtypes = [i64, vp, i64, i64, vp, i64]
+    lib.oracle_reconstruct.restype = i64
+    lib.oracle_max_threads.restype = ctypes.c_int
+    if path == _LIB:
+        _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def is_integer_valued(W: np.ndarray) -> bool:
+    """True when every finite entry of W is an integer small enough for int64 sums."""
+    W = np.asarray(W)
+    if W.dtype.kind in "iu":
+        return True
+    fin = np.isfinite(W)
+    v = W[fin]
+    return bool(np.all(v == np.floor(v)) and (v.size == 0 or np.abs(v).max() < 2.0**52))
+
+
+def to_i64(W: np.ndarray) -> np.ndarray:
+    """Integer-valued weights (+inf = no edge) -> int64 with the oracle's sentinel."""
+    W = np.asarray(W)
+    if W.dtype.kind in "iu":
+        return np.ascontiguousarray(W, dtype=np.int64)
+    out = np.full(W.shape, I64_INF, dtype=np.int64)
+    fin = np.isfinite(W)
+    out[fin] = W[fin].astype(np.int64)
+    return out
+
+
+def from_i64(D: np.ndarray) -> np.ndarray:
+    """int64 distances (sentinel = unreachable) -> float64 with +inf."""
+    out = D.astype(np.float64)
+    out[D == I64_INF] = np.inf
+    return out
+
+
+def _check_input(W: np.ndarray):
+    W = np.asarray(W)
+    if W.ndim != 2 or W.shape[0] != W.shape[1]:
+        raise ValueError("W must be square")
+    if W.dtype.kind == "f" and np.isnan(W).any():
+        raise ValueError("W contains NaN")
+    d = np.diagonal(W)
+    if not np.all(d == 0):
+        raise ValueError("oracle input contract: W[i][i] must be 0")
+
+
+def fw(W: np.ndarray, exact: bool | None = None, threads: int = 0):
+    """Classic Floyd-Warshall of W -> (D, P).
+
+    exact=True forces the int64 loop (W must be integer-valued), exact=False the
+    float64 loop; None picks int64 when W is integer-valued.  D comes back as
+    float64 with +inf for unreachable pairs in both cases; P as int32 (-1 = none).
+    """
+    _check_input(W)
+    lib = load()
+    n = W.shape[0]
+    if exact is None:
+        exact = is_integer_valued(W)
+    P = np.empty((n, n), dtype=np.int32)
+    if exact:
+        D = to_i64(W).copy()
+        lib.oracle_fw_i64(n, _ptr(D), _ptr(P), threads)
+        return from_i64(D), P
+    D = np.ascontiguousarray(W, dtype=np.float64).copy()
+    lib.oracle_fw_f64(n, _ptr(D), _ptr(P), threads)
+    return D, P
+
+
+def dijkstra_rows(W: np.ndarray, srcs, exact: bool | None = None, threads: int = 0):
+    """Rows srcs of (D, P) by lexicographic Dijkstra. Returns (Drows float64, Prows int32)."""
+    _check_input(W)
+    lib = load()
+    n = W.shape[0]
+    srcs = np.ascontiguousarray(np.asarray(srcs, dtype=np.int64))
+    if exact is None:
+        exact = is_integer_valued(W)
+    P = np.empty((srcs.size, n), dtype=np.int32)
+    if exact:
+        Wi = to_i64(W)
+        D = np.empty((srcs.size, n), dtype=np.int64)
+        lib.oracle_dijkstra_rows_i64(n, _ptr(Wi), srcs.size, _ptr(srcs), _ptr(D), _ptr(P), threads)
+        return from_i64(D), P
+    Wd = np.ascontiguousarray(W, dtype=np.float64)
+    D = np.empty((srcs.size, n), dtype=np.float64)
+    lib.oracle_dijkstra_rows_f64(n, _ptr(Wd), srcs.size, _ptr(srcs), _ptr(D), _ptr(P), threads)
+    return D, P
+
+
+def backward_pathwalk(D: np.ndarray, P: np.ndarray, G: np.ndarray) -> np.ndarray:
+    """dL/dW (float64) given forward (D, P) and G = dL/dD, by walking every encoded path."""
+    lib = load()
+    n = D.shape[0]
+    Dd = np.ascontiguousarray(D, dtype=np.float64)
+    Pc = np.ascontiguousarray(P, dtype=np.int32)
+    Gd = np.ascontiguousarray(G, dtype=np.float64)
+    gW = np.empty((n, n), dtype=np.float64)
+    rc = lib.oracle_backward_pathwalk_f64(n, _ptr(Dd), _ptr(Pc), _ptr(Gd), _ptr(gW))
+    if rc != 0:
+        raise ValueError("P is not a valid path encoding")
+    return gW
+
+
+def reconstruct(P: np.ndarray, i: int, j: int):
+    """Vertex list i .. j of the path P encodes (None if the encoding is invalid)."""
+    lib = load()
+    n = P.shape[0]
+    Pc = np.ascontiguousarray(P, dtype=np.int32)
+    out = np.empty(n + 1, dtype=np.int64)
+    m = lib.oracle_reconstruct(n, _ptr(Pc), i, j, _ptr(out), n + 1)
+    if m < 0:
+        return None
+    return out[:m].tolist()
+
+
+def brute_force(W: np.ndarray):
+    """Definition of (D, P) by exhaustive search over simple paths (n <= 8).
+
+    D[i][j] = smallest total weight over all simple i->j paths (0 for i == j,
+    +inf if none); P[i][j] = smallest "largest interior vertex" among the paths
+    that attain D[i][j], -1 when i == j, when there is no path, or when the
+    direct edge attains it (a path with no interior vertex).  Path length is
+    summed left to right in float64 (exact for integer weights).
+    """
+    W = np.asarray(W, dtype=np.float64)
+    n = W.shape[0]
+    if n > 8:
+        raise ValueError("brute force is limited to n <= 8")
+    D = np.full((n, n), np.inf)
+    P = np.full((n, n), -1, dtype=np.int32)
+    for i in range(n):
+        D[i, i] = 0.0
+        best = {}
+        stack = [(i, 0.0, -1, (i,))]
+        while stack:
+            v, length, maxint, path = stack.pop()
+            for w in range(n):
+                if w in path or not np.isfinite(W[v, w]):
+                    continue
+                L = length + W[v, w]
+                key = (L, maxint)  # interior vertices of path+w are path[1:]
+                if w not in best or key < best[w]:
+                    best[w] = key
+                stack.append((w, L, max(maxint, w), path + (w,)))
+        for j, (L, m) in best.items():
+            if j != i:
+                D[i, j] = L
+                P[i, j] = m
+    return D, P
+
+
+def check_invariants(W, D, P, exact: bool, sample=None, rtol: float = 0.0, nsample: int = 2000,
+                     seed: int = 0):
+    """Assert the properties every correct (D, P) has; raises AssertionError on the first failure.
+
+    Always: D[i][i] = 0, P[i][i] = -1, D <= W, the triangle inequality
+    D[i][j] <= D[i][k] + D[k][j] (every k for n <= 1024, else 64 sampled k),
+    P in [-1, n), P[i][j] never i or j, P = -1 on unreachable pairs.
+
+    exact (integer weights): for every pair, P[i][j] = -1 means D[i][j] = W[i][j]
+    (the direct edge is shortest), and P[i][j] = k >= 0 means
+    D[i][j] = D[i][k] + D[k][j] with P[i][k] < k and P[k][j] < k.  By induction on
+    k these make every encoded path exist, end at j, sum exactly to D[i][j], and
+    have k as its largest interior vertex -- i.e. P is the canonical path matrix.
+
+    Both: sampled pairs are reconstructed explicitly and summed (within rtol for
+    real weights).
+    """
+    W = np.asarray(W, dtype=np.float64)
+    D = np.asarray(D, dtype=np.float64)
+    P = np.asarray(P)
+    n = W.shape[0]
+    assert np.all(np.diagonal(D) == 0), "D[i][i] != 0"
+    assert np.all(np.diagonal(P) == -1), "P[i][i] != -1"
+    assert np.all(D <= W), "D exceeds W"
+    finD = np.isfinite(D)
+    ks = range(n) if n <= 1024 else np.random.default_rng(seed).choice(n, 64, replace=False)
+    for k in ks:
+        via = D[:, k:k + 1] + D[k:k + 1, :]
+        tol = rtol * np.where(np.isfinite(via), via, 0)
+        assert np.all(D <= via + tol), f"triangle inequality broken through k={k}"
+    assert np.all((P >= -1) & (P < n)), "P out of range"
+    idx = np.arange(n)
+    off = ~np.eye(n, dtype=bool)
+    assert not np.any((P == idx[:, None]) & off), "P[i][j] == i"
+    assert not np.any((P == idx[None, :]) & off), "P[i][j] == j"
+    assert np.all(P[~finD] == -1), "P set on an unreachable pair"
+    direct = (P == -1) & finD & off
+    if exact:
+        assert np.all(D[direct] == W[direct]), "P = -1 but D differs from the direct edge"
+        I, J = np.nonzero(P >= 0)
+        K = P[I, J].astype(np.int64)
+        assert np.all(D[I, K] + D[K, J] == D[I, J]), "D[i][j] != D[i][k] + D[k][j] for k = P[i][j]"
+        assert np.all(P[I, K] < K), "P[i][P[i][j]] >= P[i][j] (not canonical)"
+        assert np.all(P[K, J] < K), "P[P[i][j]][j] >= P[i][j] (not canonical)"
+    else:
+        dd = D[direct]
+        assert np.all(np.abs(dd - W[direct]) <= rtol * dd), "P = -1 but D differs from the direct edge"
+    if sample is None:
+        rng = np.random.default_rng(seed)
+        I, J = np.nonzero(finD & off)
+        if I.size > nsample:
+            pick = rng.choice(I.size, nsample, replace=False)
+            I, J = I[pick], J[pick]
+        sample = list(zip(I.tolist(), J.tolist()))
+    for (i, j) in sample:
+        if not finD[i, j]:
+            continue
+        path = reconstruct(P, i, j)
+        assert path is not None, f"invalid path encoding at ({i},{j})"
+        assert path[0] == i and path[-1] == j
+        assert len(set(path)) == len(path), f"path for ({i},{j}) repeats a vertex"
+        s = 0.0
+        for a, b in zip(path[:-1], path[1:]):
+            assert np.isfinite(W[a, b]), f"path ({i},{j}) uses a missing edge {a}->{b}"
+            s += W[a, b]
+        if exact:
+            assert s == D[i, j], f"path ({i},{j}) sums to {s} != D {D[i, j]}"
+            if len(path) > 2:
+                assert max(path[1:-1]) == P[i, j], "P is not the largest interior vertex"
+        else:
+            assert abs(s - D[i, j]) <= rtol * max(abs(D[i, j]), 1e-30) * len(path), \
+                f"path ({i},{j}) sums to {s} vs D {D[i, j]}"
