@@ -1,0 +1,130 @@
+/*
+ * fw_apsp.h -- C ABI of the MI355X (gfx950) blocked Floyd-Warshall library.
+ *
+ * Problem (paper Sect. 2.2, "FW Algorithm"): a dense n x n distance matrix D
+ * (D[i][j] = weight of edge i->j, +infinity when there is no edge, 0 on the
+ * diagonal) is replaced by the all-pairs shortest distances, and a path matrix
+ * P records, for every pair, the intermediate vertex of a shortest path.  The
+ * library computes it with the blocked three-phase method of the same section
+ * ("Blocked FW Algorithm": diagonal block, then its row and column panels, then
+ * every remaining block, for each block of k).
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are row-major with leading dimension n (element (i, j) at i*n + j).
+ *   - dist, path, grad_* are DEVICE pointers (hipMalloc'd or torch tensors) owned
+ *     by the caller.  Host arrays are marked "host" below.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).  Calls are
+ *     asynchronous: results are ready when the stream reaches this point.
+ *     Argument errors are reported synchronously before anything is enqueued.
+ *   - Input contract: dist[i][i] = 0; off-diagonal weights >= 0 or +inf; no NaN.
+ *     Negative weights or cycles are outside the contract (results undefined).
+ *   - path[i][j] = -1 when i == j, when j is unreachable from i, or when the direct
+ *     edge is a shortest path; otherwise the largest interior vertex of a shortest
+ *     path, chosen as the smallest such value over all shortest paths.  This is
+ *     what the classic loop with a strict update test stores, and does not depend
+ *     on the block size.  For real-valued weights, rounding may resolve
+ *     near-ties differently from a float64 computation.
+ *   - Return value: FW_OK or a negative fw_status_t; nothing throws.  The text of
+ *     the last failure on the calling thread is available from fw_last_error().
+ *   - The library allocates stream-ordered scratch (hipMallocAsync) only where an
+ *     entry point says so, and frees it on the same stream before returning.
+ */
+#ifndef FW_APSP_H
+#define FW_APSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { FW_F32 = 0, FW_F64 = 1 } fw_dtype_t;
+
+typedef enum {
+    FW_OK = 0,
+    FW_EINVAL = -1,       /* bad argument (size, pointer, dtype, layout)         */
+    FW_ENOMEM = -2,       /* scratch allocation failed                           */
+    FW_EHIP = -3,         /* a HIP runtime call failed (no device, launch error) */
+    FW_EUNSUPPORTED = -4  /* valid but not supported by this build               */
+} fw_status_t;
+
+/*
+ * All-pairs shortest paths of one graph, in place (paper Sect. 2.2, Algorithm 1
+ * and the blocked method).
+ *   dt    FW_F32 (float) or FW_F64 (double): element type of dist.
+ *   n     vertex count, 1 <= n <= 2^20.
+ *   dist  device, n*n elements: W on entry, shortest distances on exit.
+ *   path  device, n*n int32: receives P; NULL computes distances only.
+ * When n is not a multiple of the block size or dist is not 16-byte aligned, the
+ * call copies the matrices into padded stream-ordered scratch (padding vertices
+ * are isolated, so they change nothing) and back.
+ */
+fw_status_t fw_apsp(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, void *stream);
+
+/*
+ * Tile configuration of fw_apsp, for tuning and for the tests that show results
+ * do not depend on it.  block = round depth (the paper's TB) in {32, 64};
+ * tile = edge of the square output tile one workgroup updates in the last phase,
+ * in {64, 128} and a multiple of block.  Fields set to 0 keep the library's
+ * choice; reserved fields must be 0.
+ */
+typedef struct { int32_t block; int32_t tile; int32_t reserved0; int32_t reserved1; } fw_config_t;
+
+/* fw_apsp with an explicit configuration (cfg may be NULL = library choice).
+ * FW_EUNSUPPORTED if the combination is not compiled in. */
+fw_status_t fw_apsp_config(fw_dtype_t dt, int64_t n, void *dist, int32_t *path,
+                           const fw_config_t *cfg, void *stream);
+
+/*
+ * Many independent graphs of uneven size in one persistent launch.
+ *   batch      number of graphs, >= 1.
+ *   n_host     host [batch]: vertex count of each graph, 1 <= n <= 4096.
+ *   off_host   host [batch]: element offset of graph b's matrix in dist/path
+ *              (graph b occupies n_b*n_b elements from there, row-major).
+ *   dist, path device, ragged concatenation; path may be NULL.
+ * Same per-graph semantics and results as fw_apsp on each graph.  Allocates a
+ * small stream-ordered job table.
+ */
+fw_status_t fw_apsp_batched(fw_dtype_t dt, int32_t batch, const int32_t *n_host,
+                            const int64_t *off_host, void *dist, int32_t *path, void *stream);
+
+/*
+ * Gradient of a loss L(D) with respect to the weights W, given the forward
+ * outputs.  D is piecewise linear in W: dD[i][j]/dW[u][v] = 1 when edge u->v is
+ * on the path P encodes for (i, j), else 0 (the subgradient along that path at
+ * ties).  Hence grad_w[u][v] = sum of grad_dist[i][j] over the pairs whose path
+ * uses u->v, computed per source i as subtree sums over its shortest-path tree.
+ *   n, batch   batch >= 1 graphs of n vertices each, contiguous with stride n*n.
+ *   dist, path forward outputs (device); path must not be NULL.
+ *   grad_dist  device, dL/dD (same layout/type as dist).
+ *   grad_w     device, output dL/dW (same layout/type), overwritten.
+ * Diagonal and unused edges get 0.  Requires positive off-diagonal weights.
+ */
+fw_status_t fw_apsp_backward(fw_dtype_t dt, int64_t n, int32_t batch, const void *dist,
+                             const int32_t *path, const void *grad_dist, void *grad_w,
+                             void *stream);
+
+/* Static description of a status code. */
+const char *fw_status_string(int status);
+
+/* Text of the last failure on the calling thread ("" if none). */
+const char *fw_last_error(void);
+
+/* Library version string. */
+const char *fw_version(void);
+
+/*
+ * Timing hooks for benchmarks.  While enabled, every launch of the last-phase
+ * kernel (the register-blocked min-plus tile update) is bracketed by two HIP
+ * events recorded on the stream it runs on.  fw_prof_read waits for the recorded
+ * events and returns the number of bracketed launches and their summed duration
+ * in milliseconds since the last reset (reset != 0 starts a new window).
+ */
+void fw_prof_enable(int on);
+int fw_prof_read(int64_t *count, double *total_ms, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FW_APSP_H */

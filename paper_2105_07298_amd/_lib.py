@@ -1,0 +1,107 @@
+"""ctypes binding of libfwapsp.so: the C ABI of include/fw_apsp.h, same names.
+
+Argument marshalling only.  Every step of the computation runs in the HIP
+library; if the library is missing this module raises instead of falling back.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfwapsp.so")
+
+FW_F32, FW_F64 = 0, 1
+FW_OK, FW_EINVAL, FW_ENOMEM, FW_EHIP, FW_EUNSUPPORTED = 0, -1, -2, -3, -4
+
+EXPORTS = ("fw_apsp", "fw_apsp_config", "fw_apsp_batched", "fw_apsp_backward",
+           "fw_status_string", "fw_last_error", "fw_version", "fw_prof_enable", "fw_prof_read")
+
+
+class FwConfig(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+
+
+class FwError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where} failed with status {status}: {detail}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    L.fw_apsp.argtypes = [ctypes.c_int, i64, vp, vp, vp]
+    L.fw_apsp_config.argtypes = [ctypes.c_int, i64, vp, vp, ctypes.POINTER(FwConfig), vp]
+    L.fw_apsp_batched.argtypes = [ctypes.c_int, i32, vp, vp, vp, vp, vp]
+    L.fw_apsp_backward.argtypes = [ctypes.c_int, i64, i32, vp, vp, vp, vp, vp]
+    for f in ("fw_apsp", "fw_apsp_config", "fw_apsp_batched", "fw_apsp_backward"):
+        getattr(L, f).restype = ctypes.c_int
+    L.fw_status_string.argtypes = [ctypes.c_int]
+    L.fw_status_string.restype = ctypes.c_char_p
+    L.fw_last_error.restype = ctypes.c_char_p
+    L.fw_version.restype = ctypes.c_char_p
+    L.fw_prof_enable.argtypes = [ctypes.c_int]
+    L.fw_prof_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+    L.fw_prof_read.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(st: int, where: str):
+    if st != FW_OK:
+        L = lib()
+        raise FwError(st, where, f"{L.fw_status_string(st).decode()}: {L.fw_last_error().decode()}")
+
+
+def fw_apsp(dt: int, n: int, dist: int, path: int | None, stream: int | None = None):
+    _check(lib().fw_apsp(dt, n, dist, path, stream), "fw_apsp")
+
+
+def fw_apsp_config(dt, n, dist, path, block=0, tile=0, stream=None):
+    cfg = FwConfig(block, tile, 0, 0)
+    _check(lib().fw_apsp_config(dt, n, dist, path, ctypes.byref(cfg), stream), "fw_apsp_config")
+
+
+def fw_apsp_batched(dt, batch, n_host, off_host, dist, path, stream=None):
+    """n_host / off_host: host pointers (e.g. numpy .ctypes.data)."""
+    _check(lib().fw_apsp_batched(dt, batch, n_host, off_host, dist, path, stream), "fw_apsp_batched")
+
+
+def fw_apsp_backward(dt, n, batch, dist, path, grad_dist, grad_w, stream=None):
+    _check(lib().fw_apsp_backward(dt, n, batch, dist, path, grad_dist, grad_w, stream), "fw_apsp_backward")
+
+
+def fw_status_string(st: int) -> str:
+    return lib().fw_status_string(st).decode()
+
+
+def fw_last_error() -> str:
+    return lib().fw_last_error().decode()
+
+
+def fw_version() -> str:
+    return lib().fw_version().decode()
+
+
+def fw_prof_enable(on: bool):
+    lib().fw_prof_enable(1 if on else 0)
+
+
+def fw_prof_read(reset: bool = True):
+    """(count, total_ms) of bracketed last-phase launches since the last reset."""
+    c = ctypes.c_int64(0)
+    t = ctypes.c_double(0.0)
+    _check(lib().fw_prof_read(ctypes.byref(c), ctypes.byref(t), 1 if reset else 0), "fw_prof_read")
+    return int(c.value), float(t.value)

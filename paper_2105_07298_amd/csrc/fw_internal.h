@@ -1,0 +1,40 @@
+// fw_internal.h -- declarations shared by the host runtime and the kernel file.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fw {
+
+// Compiled round depths (the paper's TB) and last-phase tile edges.
+struct TileCfg {
+    int block;  // round depth TB
+    int tile;   // last-phase output tile edge (multiple of block)
+};
+
+// One round of the blocked method, enqueued on `s`.  D, P are the padded
+// matrices (leading dimension ld, a multiple of cfg.tile); P may be null.
+// Returns hipSuccess or the launch error.
+template <typename T>
+hipError_t launch_round(T *D, int32_t *P, int64_t ld, int r, TileCfg cfg, hipStream_t s);
+
+// Supported (block, tile) pairs for element type T.
+template <typename T>
+bool config_supported(TileCfg cfg);
+
+// Fill n int32 with v.
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+
+// Copy a user matrix (n x n, leading dim n) into a padded one (npad x npad);
+// padding entries become +inf off the diagonal and 0 on it.
+template <typename T>
+hipError_t launch_pad_in(const T *src, int64_t n, T *dst, int64_t npad, hipStream_t s);
+
+// Copy the leading n x n block of a padded matrix back (T = float, double, int32_t).
+template <typename T>
+hipError_t launch_pad_out(const T *src, int64_t npad, T *dst, int64_t n, hipStream_t s);
+
+// Kernel-class timing hooks (events around the last-phase launches).
+void prof_begin_p4(hipStream_t s);
+void prof_end_p4(hipStream_t s);
+
+}  // namespace fw

@@ -1,0 +1,204 @@
+// fw_runtime.cpp -- host side of the C ABI: argument checks, padding, the round
+// loop of the blocked method (paper Sect. 2.2; one round per block of k, three
+// dependent launches per round as in Sect. 3.2), status codes and timing hooks.
+#include <hip/hip_runtime.h>
+
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "../../include/fw_apsp.h"
+#include "fw_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+fw_status_t fail(fw_status_t st, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+fw_status_t hip_fail(hipError_t e, const char *what) {
+    return fail(FW_EHIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+// ---- last-phase timing hooks ------------------------------------------------
+// When enabled, each last-phase launch is bracketed by two events on its
+// stream; fw_prof_read() synchronizes them and returns the count and summed time.
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<hipEvent_t> g_ev_pool;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_ev_used;
+hipEvent_t g_pending = nullptr;
+
+hipEvent_t take_event() {
+    if (!g_ev_pool.empty()) {
+        hipEvent_t e = g_ev_pool.back();
+        g_ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+constexpr int64_t kMaxN = int64_t(1) << 20;
+
+fw::TileCfg default_cfg(fw_dtype_t dt, int64_t n) {
+    if (dt == FW_F64) return {64, 64};
+    return n >= 512 ? fw::TileCfg{64, 128} : fw::TileCfg{64, 64};
+}
+
+template <typename T>
+fw_status_t run_apsp(int64_t n, T *dist, int32_t *path, fw::TileCfg cfg, hipStream_t s) {
+    if (!fw::config_supported<T>(cfg)) return fail(FW_EUNSUPPORTED, "block %d / tile %d not compiled in", cfg.block, cfg.tile);
+    const int64_t unit = cfg.tile;
+    const int64_t npad = (n + unit - 1) / unit * unit;
+    const bool aligned = ((uintptr_t)dist % 16 == 0) && (path == nullptr || (uintptr_t)path % 16 == 0);
+    hipError_t e;
+    T *D = dist;
+    int32_t *P = path;
+    void *scratch = nullptr;
+    if (npad != n || !aligned) {
+        const size_t dbytes = (size_t)(npad * npad) * sizeof(T);
+        const size_t pbytes = path ? (size_t)(npad * npad) * sizeof(int32_t) : 0;
+        e = hipMallocAsync(&scratch, dbytes + pbytes, s);
+        if (e != hipSuccess) return fail(FW_ENOMEM, "scratch of %zu bytes: %s", dbytes + pbytes, hipGetErrorString(e));
+        D = (T *)scratch;
+        P = path ? (int32_t *)((char *)scratch + dbytes) : nullptr;
+        if ((e = fw::launch_pad_in<T>(dist, n, D, npad, s)) != hipSuccess) return hip_fail(e, "pad");
+    }
+    if (P && (e = fw::launch_fill_i32(P, npad * npad, -1, s)) != hipSuccess) return hip_fail(e, "path init");
+    const int R = (int)(npad / cfg.block);
+    for (int r = 0; r < R; ++r)
+        if ((e = fw::launch_round<T>(D, P, npad, r, cfg, s)) != hipSuccess) return hip_fail(e, "round launch");
+    if (scratch) {
+        if ((e = fw::launch_pad_out<T>(D, npad, dist, n, s)) != hipSuccess) return hip_fail(e, "unpad");
+        if (path && (e = fw::launch_pad_out<int32_t>(P, npad, path, n, s)) != hipSuccess) return hip_fail(e, "unpad P");
+        if ((e = hipFreeAsync(scratch, s)) != hipSuccess) return hip_fail(e, "scratch free");
+    }
+    return FW_OK;
+}
+
+fw_status_t check_common(fw_dtype_t dt, int64_t n, const void *dist) {
+    if (dt != FW_F32 && dt != FW_F64) return fail(FW_EINVAL, "unknown dtype %d", (int)dt);
+    if (n < 1 || n > kMaxN) return fail(FW_EINVAL, "n = %lld outside [1, %lld]", (long long)n, (long long)kMaxN);
+    if (dist == nullptr) return fail(FW_EINVAL, "dist is NULL");
+    return FW_OK;
+}
+
+}  // namespace
+
+namespace fw {
+void prof_begin_p4(hipStream_t s) {
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_pending = take_event();
+    if (g_pending) (void)hipEventRecord(g_pending, s);
+}
+void prof_end_p4(hipStream_t s) {
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_pending) return;
+    hipEvent_t e = take_event();
+    if (!e) return;
+    (void)hipEventRecord(e, s);
+    g_ev_used.push_back({g_pending, e});
+    g_pending = nullptr;
+}
+}  // namespace fw
+
+extern "C" {
+
+fw_status_t fw_apsp_config(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, const fw_config_t *cfg, void *stream) {
+    g_err[0] = 0;
+    fw_status_t st = check_common(dt, n, dist);
+    if (st != FW_OK) return st;
+    fw::TileCfg tc = default_cfg(dt, n);
+    if (cfg) {
+        if (cfg->reserved0 || cfg->reserved1) return fail(FW_EINVAL, "reserved config fields must be 0");
+        if (cfg->block) tc.block = cfg->block;
+        if (cfg->tile) tc.tile = cfg->tile;
+        if (tc.block <= 0 || tc.tile <= 0 || tc.tile % tc.block) return fail(FW_EINVAL, "tile must be a multiple of block");
+    }
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    if (dt == FW_F32) return run_apsp<float>(n, (float *)dist, path, tc, s);
+    return run_apsp<double>(n, (double *)dist, path, tc, s);
+}
+
+fw_status_t fw_apsp(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, void *stream) {
+    return fw_apsp_config(dt, n, dist, path, nullptr, stream);
+}
+
+fw_status_t fw_apsp_batched(fw_dtype_t dt, int32_t batch, const int32_t *n_host, const int64_t *off_host, void *dist,
+                            int32_t *path, void *stream) {
+    (void)dt; (void)batch; (void)n_host; (void)off_host; (void)dist; (void)path; (void)stream;
+    g_err[0] = 0;
+    return fail(FW_EUNSUPPORTED, "fw_apsp_batched is not built yet");
+}
+
+fw_status_t fw_apsp_backward(fw_dtype_t dt, int64_t n, int32_t batch, const void *dist, const int32_t *path,
+                             const void *grad_dist, void *grad_w, void *stream) {
+    (void)dt; (void)n; (void)batch; (void)dist; (void)path; (void)grad_dist; (void)grad_w; (void)stream;
+    g_err[0] = 0;
+    return fail(FW_EUNSUPPORTED, "fw_apsp_backward is not built yet");
+}
+
+const char *fw_status_string(int st) {
+    switch (st) {
+    case FW_OK: return "ok";
+    case FW_EINVAL: return "invalid argument";
+    case FW_ENOMEM: return "out of device memory";
+    case FW_EHIP: return "HIP runtime error";
+    case FW_EUNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *fw_last_error(void) { return g_err; }
+
+const char *fw_version(void) { return "fwapsp 0.1 gfx950"; }
+
+// Timing hooks for the benchmark: enable/disable bracketing of last-phase
+// launches with events, and read (count, summed milliseconds) since the last
+// reset.  fw_prof_read synchronizes on the recorded events.
+void fw_prof_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+}
+
+int fw_prof_read(int64_t *count, double *total_ms, int reset) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    double tot = 0.0;
+    int64_t cnt = 0;
+    for (auto &pr : g_ev_used) {
+        if (hipEventSynchronize(pr.second) != hipSuccess) return FW_EHIP;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, pr.first, pr.second) != hipSuccess) return FW_EHIP;
+        tot += ms;
+        ++cnt;
+    }
+    if (count) *count = cnt;
+    if (total_ms) *total_ms = tot;
+    if (reset) {
+        for (auto &pr : g_ev_used) {
+            g_ev_pool.push_back(pr.first);
+            g_ev_pool.push_back(pr.second);
+        }
+        g_ev_used.clear();
+    }
+    return FW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+"""The C-ABI library: loads, exports every declared symbol, rejects bad arguments
+before touching a device.  CPU-only (no kernel is launched)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "fw_apsp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fw_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def fw():
+    import paper_2105_07298_amd as fw
+    fw.lib()
+    return fw
+
+
+def test_every_declared_symbol_is_exported(fw):
+    names = declared_functions()
+    assert "fw_apsp" in names and "fw_apsp_batched" in names and "fw_apsp_backward" in names
+    L = ctypes.CDLL(fw._lib.LIB_PATH)
+    for name in names:
+        assert hasattr(L, name), f"{name} declared in fw_apsp.h but not exported"
+    assert set(names) == set(fw._lib.EXPORTS)
+
+
+def test_status_strings(fw):
+    assert fw.fw_status_string(0) == "ok"
+    for st in (-1, -2, -3, -4):
+        assert fw.fw_status_string(st) not in ("ok", "unknown status")
+    assert fw.fw_status_string(17) == "unknown status"
+    assert "gfx950" in fw.fw_version()
+
+
+def call_raw(fw, *args):
+    return fw.lib().fw_apsp(*args)
+
+
+@pytest.mark.parametrize("args", [
+    (0, 0, 4096, None, None),          # n = 0
+    (0, -5, 4096, None, None),         # n < 0
+    (0, (1 << 20) + 1, 4096, None, None),  # n too large
+    (0, 16, None, None, None),         # null dist
+    (7, 16, 4096, None, None),         # unknown dtype
+])
+def test_invalid_arguments(fw, args):
+    st = call_raw(fw, *args)
+    assert st == fw.FW_EINVAL
+    assert fw.fw_last_error() != ""
+
+
+def test_invalid_config(fw):
+    L = fw.lib()
+    cfg = fw._lib.FwConfig(64, 96, 0, 0)  # tile not a multiple of block
+    assert L.fw_apsp_config(0, 128, 4096, None, ctypes.byref(cfg), None) == fw.FW_EINVAL
+    cfg = fw._lib.FwConfig(64, 128, 1, 0)  # reserved field set
+    assert L.fw_apsp_config(0, 128, 4096, None, ctypes.byref(cfg), None) == fw.FW_EINVAL
+
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="a GPU is present: would launch on a bogus pointer")
+def test_no_device_reports_hip_error(fw):
+    st = call_raw(fw, 0, 16, 4096, None, None)
+    assert st == fw.FW_EHIP
+    assert fw.fw_last_error()
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    import paper_2105_07298_amd._lib as L
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(ImportError):
+        L.lib()

@@ -1,0 +1,136 @@
+"""A slow NumPy model of the blocked method the HIP kernels implement (test code,
+not the oracle), checked against the oracle.
+
+Model (paper Sect. 2.2, "Blocked FW Algorithm"): D is cut into TB x TB blocks;
+round r takes the k-block K = [r*TB, (r+1)*TB) through
+  phase 1  the diagonal block, sequential k-steps (classic loop inside K),
+  phase 2  the row panel D[K, J]   <- lexmin(D[K, J], D*[K, K] (x) D_old[K, J]),
+  phase 3  the column panel D[I, K] <- lexmin(D[I, K], D_old[I, K] (x) D*[K, K]),
+  phase 4  every other block D[I, J] <- lexmin(D[I, J], D[I, K] (x) D[K, J]),
+where (x) is the min-plus product and every candidate through k carries the
+label (length, max(P[i][k], k, P[k][j])).  Phase 4 is taken in two passes
+(minimum length first, then the smallest label among the k that reach it),
+exactly as the GPU kernel does.  For integer weights the result must equal the
+classic loop bit for bit, whatever TB and the padding are.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+
+def lex_update(d, p, s, m):
+    better = (s < d) | ((s == d) & (m < p))
+    return np.where(better, s, d), np.where(better, m, p)
+
+
+def product_lex(DA, PA, DB, PB, k_ids, Dc, Pc):
+    """lexmin over k of (DA[:,k] + DB[k,:], max(PA[:,k], k, PB[k,:])) folded into (Dc, Pc)."""
+    for t, k in enumerate(k_ids):
+        s = DA[:, t:t + 1] + DB[t:t + 1, :]
+        m = np.maximum(np.maximum(PA[:, t:t + 1], k), PB[t:t + 1, :])
+        Dc, Pc = lex_update(Dc, Pc, s, m)
+    return Dc, Pc
+
+
+def product_two_pass(DA, PA, DB, PB, k_ids, Dc, Pc):
+    S = np.full(Dc.shape, np.inf)
+    for t in range(len(k_ids)):
+        S = np.minimum(S, DA[:, t:t + 1] + DB[t:t + 1, :])
+    marked = (S <= Dc) & np.isfinite(S)
+    BIG = np.iinfo(np.int64).max
+    M = np.full(Dc.shape, BIG, dtype=np.int64)
+    for t, k in enumerate(k_ids):
+        s = DA[:, t:t + 1] + DB[t:t + 1, :]
+        m = np.maximum(np.maximum(PA[:, t:t + 1], k), PB[t:t + 1, :])
+        M = np.where(marked & (s == S), np.minimum(M, m), M)
+    improve = marked & (S < Dc)
+    tie = marked & (S == Dc)
+    Pn = np.where(improve, M, np.where(tie, np.minimum(Pc, M), Pc))
+    return np.where(improve, S, Dc), Pn
+
+
+def blocked_model(W, TB, two_pass=True):
+    n = W.shape[0]
+    npad = -(-n // TB) * TB
+    D = np.full((npad, npad), np.inf)
+    np.fill_diagonal(D, 0.0)
+    D[:n, :n] = W
+    P = np.full((npad, npad), -1, dtype=np.int64)
+    R = npad // TB
+    for r in range(R):
+        K = np.arange(r * TB, (r + 1) * TB)
+        ks = slice(r * TB, (r + 1) * TB)
+        # phase 1: sequential closure of the diagonal block
+        for k in K:
+            s = D[ks, k:k + 1] + D[k:k + 1, ks]
+            m = np.maximum(np.maximum(P[ks, k:k + 1], k), P[k:k + 1, ks])
+            D[ks, ks], P[ks, ks] = lex_update(D[ks, ks], P[ks, ks], s, m)
+        Dkk, Pkk = D[ks, ks].copy(), P[ks, ks].copy()
+        others = [b for b in range(R) if b != r]
+        # phases 2 and 3 read the old panels and the closed diagonal block
+        for b in others:
+            js = slice(b * TB, (b + 1) * TB)
+            D[ks, js], P[ks, js] = product_lex(Dkk, Pkk, D[ks, js].copy(), P[ks, js].copy(), K,
+                                               D[ks, js], P[ks, js])
+            D[js, ks], P[js, ks] = product_lex(D[js, ks].copy(), P[js, ks].copy(), Dkk, Pkk, K,
+                                               D[js, ks], P[js, ks])
+        # phase 4 reads the final panels of this round
+        for bi in others:
+            for bj in others:
+                is_, js = slice(bi * TB, (bi + 1) * TB), slice(bj * TB, (bj + 1) * TB)
+                f = product_two_pass if two_pass else product_lex
+                D[is_, js], P[is_, js] = f(D[is_, ks], P[is_, ks], D[ks, js], P[ks, js], K,
+                                           D[is_, js], P[is_, js])
+    return D[:n, :n], P[:n, :n].astype(np.int32)
+
+
+@pytest.mark.parametrize("TB", [1, 2, 3, 4, 8, 16])
+@pytest.mark.parametrize("seed", range(4))
+def test_model_equals_classic_tie_heavy(TB, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(5, 40))
+    W = workloads.int_graph(n=n, p=float(rng.uniform(0.05, 0.6)), wmax=int(rng.integers(1, 4)), seed=seed + 70)
+    D, P = oracle.fw(W)
+    Dm, Pm = blocked_model(W.astype(np.float64), TB)
+    np.testing.assert_array_equal(Dm, D)
+    np.testing.assert_array_equal(Pm, P)
+
+
+@pytest.mark.parametrize("two_pass", [True, False])
+def test_model_c1_like(two_pass):
+    W = workloads.int_graph(n=96, p=0.5, wmax=1000, seed=1)
+    D, P = oracle.fw(W)
+    Dm, Pm = blocked_model(W.astype(np.float64), 16, two_pass=two_pass)
+    np.testing.assert_array_equal(Dm, D)
+    np.testing.assert_array_equal(Pm, P)
+
+
+def test_naive_p_rule_differs():
+    """Storing k on strict improvement (no lexicographic label) is tile dependent: the
+    model with that rule disagrees with the classic P on a tie-heavy graph."""
+    W = workloads.int_graph(n=40, p=0.3, wmax=2, seed=3).astype(np.float64)
+    D, P = oracle.fw(W)
+
+    def naive_update(d, p, s, m):
+        better = s < d
+        return np.where(better, s, d), np.where(better, m, p)
+
+    global lex_update
+    saved = lex_update
+    try:
+        lex_update = naive_update
+        Dm, Pm = blocked_model(W, 4, two_pass=False)
+    finally:
+        lex_update = saved
+    np.testing.assert_array_equal(Dm, D)
+    assert not np.array_equal(Pm, P)
+
+
+def test_model_real_weights_tolerance():
+    W = workloads.unit_complete(64, dtype=np.float64, seed=2)
+    D, _ = oracle.fw(W)
+    Dm, Pm = blocked_model(W, 8)
+    np.testing.assert_allclose(Dm, D, rtol=1e-14)
+    oracle.check_invariants(W, Dm, Pm, exact=False, rtol=1e-12)

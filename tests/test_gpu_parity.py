@@ -1,0 +1,193 @@
+"""GPU parity: fw_apsp (through the C ABI) against the CPU oracle on the same
+seeded inputs.
+
+Integer-valued weights: distances and path matrix bit-exact (every sum is an
+integer below 2^24, so float32 is exact and the lexicographic path rule gives the
+canonical P whatever the block size).  Real weights: max relative error 1e-5
+(float32) / 1e-12 (float64) against the float64 oracle on the same weight bits,
+identical +inf pattern, and the path matrix checked by its invariants.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+CONFIGS = {np.float32: [(32, 64), (64, 64), (64, 128)], np.float64: [(32, 64), (64, 64)]}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a GPU"
+    import paper_2105_07298_amd as fw
+    fw.lib()
+    return torch.device("cuda:0")
+
+
+def run_gpu(W, dev, path=True, block=0, tile=0, case=""):
+    import torch
+    import paper_2105_07298_amd as fw
+    print(f"[gpu] fw_apsp {case} n={W.shape[0]} dtype={W.dtype} path={path} block={block} tile={tile}",
+          flush=True)
+    D, P = fw.apsp(torch.from_numpy(np.ascontiguousarray(W)).to(dev), path=path, block=block, tile=tile)
+    torch.cuda.synchronize()
+    return D.cpu().numpy(), (P.cpu().numpy() if P is not None else None)
+
+
+def assert_exact(W, Dg, Pg, Do=None, Po=None):
+    if Do is None:
+        Do, Po = oracle.fw(W)
+    np.testing.assert_array_equal(Dg.astype(np.float64), Do)
+    if Pg is not None:
+        np.testing.assert_array_equal(Pg, Po)
+
+
+def rel_err(Dg, Do):
+    fin = np.isfinite(Do)
+    assert np.array_equal(np.isfinite(Dg), fin), "+inf pattern differs"
+    d = Dg[fin].astype(np.float64)
+    o = Do[fin]
+    nz = o != 0
+    assert np.all(d[~nz] == 0), "zero distance mismatch"
+    return float(np.max(np.abs(d[nz] - o[nz]) / o[nz])) if nz.any() else 0.0
+
+
+# ------------------------------------------------------------------ integer weights: bit-exact
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("path", [True, False])
+def test_c1_bit_exact(dev, dtype, path):
+    """n = 512, edge probability 0.5, integer weights in [1, 1000]."""
+    W = workloads.int_graph(n=512, p=0.5, wmax=1000, seed=1, dtype=dtype)
+    Dg, Pg = run_gpu(W, dev, path=path, case="C1")
+    assert_exact(W, Dg, Pg)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_block_and_tile_invariance_tie_heavy(dev, dtype):
+    """Weights in [1, 3] at low density: many equal-length paths.  Every compiled
+    (block, tile) gives the oracle's D and canonical P exactly."""
+    W = workloads.int_graph(n=448, p=0.02, wmax=3, seed=21, dtype=dtype)
+    Do, Po = oracle.fw(W)
+    assert (Po >= 0).mean() > 0.5
+    for block, tile in CONFIGS[dtype]:
+        Dg, Pg = run_gpu(W, dev, block=block, tile=tile, case="tie-heavy")
+        assert_exact(W, Dg, Pg, Do, Po)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 31, 63, 64, 65, 127, 129, 200, 333])
+def test_ragged_sizes(dev, dtype, n):
+    W = workloads.int_graph(n=n, p=0.3, wmax=50, seed=100 + n, dtype=dtype)
+    Dg, Pg = run_gpu(W, dev, case="ragged")
+    assert_exact(W, Dg, Pg)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_no_edges(dev, dtype):
+    n = 130
+    W = np.full((n, n), np.inf, dtype=dtype)
+    np.fill_diagonal(W, 0)
+    Dg, Pg = run_gpu(W, dev, case="no-edges")
+    np.testing.assert_array_equal(Dg, W)
+    assert np.all(Pg == -1)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_complete_one_two_is_fixed_point(dev, dtype):
+    """Weights in [1, 2): every two-hop path is >= 2 > any edge, so D = W and P = -1."""
+    W, _ = workloads.grad_graph(n=320, seed=5)
+    W = W.astype(dtype)
+    Dg, Pg = run_gpu(W, dev, case="complete[1,2)")
+    np.testing.assert_array_equal(Dg, W)
+    assert np.all(Pg == -1)
+
+
+def test_directed_path_graph(dev):
+    n = 300
+    rng = np.random.default_rng(3)
+    W = np.full((n, n), np.inf, dtype=np.float32)
+    np.fill_diagonal(W, 0)
+    W[np.arange(n - 1), np.arange(1, n)] = rng.integers(1, 20, n - 1)
+    Dg, Pg = run_gpu(W, dev, case="path-graph")
+    assert_exact(W, Dg, Pg)
+    j = np.arange(n)
+    assert np.all(Pg[0, 2:] == j[2:] - 1)
+
+
+def test_disconnected_blocks(dev):
+    A = workloads.int_graph(n=150, p=0.1, wmax=9, seed=41)
+    B = workloads.int_graph(n=170, p=0.1, wmax=9, seed=42)
+    W = np.full((320, 320), np.inf, dtype=np.float32)
+    W[:150, :150] = A
+    W[150:, 150:] = B
+    Dg, Pg = run_gpu(W, dev, case="disconnected")
+    assert_exact(W, Dg, Pg)
+    assert np.all(np.isinf(Dg[:150, 150:])) and np.all(Pg[:150, 150:] == -1)
+
+
+def test_distance_only_matches_path_mode(dev):
+    W = workloads.unit_complete(640, dtype=np.float32, seed=2)
+    D1, _ = run_gpu(W, dev, path=False, case="dist-only")
+    D2, _ = run_gpu(W, dev, path=True, case="path")
+    np.testing.assert_array_equal(D1, D2)
+
+
+def test_misaligned_and_nondefault_stream(dev):
+    """A tensor view that is not 16-byte aligned goes through the padded copy; the call
+    runs on the caller's current (non-default) stream."""
+    import torch
+    import paper_2105_07298_amd as fw
+    n = 256
+    W = workloads.int_graph(n=n, p=0.2, wmax=100, seed=7)
+    buf = torch.empty(n * n + 1, dtype=torch.float32, device=dev)
+    D = buf[1:].view(n, n)
+    assert D.data_ptr() % 16 != 0
+    D.copy_(torch.from_numpy(W))
+    P = torch.empty((n, n), dtype=torch.int32, device=dev)
+    s = torch.cuda.Stream(dev)
+    with torch.cuda.stream(s):
+        print("[gpu] fw_apsp misaligned view on a side stream", flush=True)
+        fw.apsp_(D, P)
+    s.synchronize()
+    assert_exact(W, D.cpu().numpy(), P.cpu().numpy())
+
+
+# ------------------------------------------------------------------ real weights: tolerance
+
+@pytest.mark.parametrize("dtype,tol", [(np.float32, 1e-5), (np.float64, 1e-12)])
+def test_c2_4096_full_matrix(dev, dtype, tol):
+    """Complete graph, weights strictly inside (0, 1), n = 4096: every entry vs the
+    float64 oracle on the same weight bits."""
+    W = workloads.unit_complete(4096, dtype=dtype, seed=2)
+    Dg, Pg = run_gpu(W, dev, case="C2")
+    print("[cpu] oracle n=4096", flush=True)
+    Do, _ = oracle.fw(W, exact=False)
+    err = rel_err(Dg, Do)
+    print(f"max relative error {err:.3e}", flush=True)
+    assert err <= tol
+    oracle.check_invariants(W, Dg, Pg, exact=False, rtol=max(tol, 1e-7), nsample=3000)
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float32, 1e-5), (np.float64, 1e-12)])
+def test_c2_16384_dijkstra_rows(dev, dtype, tol):
+    """n = 16384 (the benchmark size): 64 seeded source rows vs Dijkstra in float64."""
+    n = 16384
+    W = workloads.unit_complete(n, dtype=dtype, seed=2)
+    Dg, Pg = run_gpu(W, dev, case="C2-16384")
+    srcs = workloads.sample_sources(n, 64)
+    print("[cpu] dijkstra 64 rows", flush=True)
+    Dr, _ = oracle.dijkstra_rows(W, srcs, exact=False)
+    err = rel_err(Dg[srcs], Dr)
+    print(f"max relative error {err:.3e}", flush=True)
+    assert err <= tol
+    # path matrix on the sampled rows: encoded paths exist and sum to D
+    pairs = [(int(i), int(j)) for i in srcs[:8] for j in range(0, n, 97) if i != j]
+    for (i, j) in pairs:
+        pth = oracle.reconstruct(Pg, i, j)
+        assert pth is not None and pth[0] == i and pth[-1] == j
+        s = sum(float(W[a, b]) for a, b in zip(pth[:-1], pth[1:]))
+        assert abs(s - float(Dg[i, j])) <= 1e-5 * float(Dg[i, j]) * len(pth)
