@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Benchmark of the blocked Floyd-Warshall APSP library on one MI355X.
+
+Headline: GFLOPS = 2 n^3 / t (paper Sect. 4.2, Eq. 1) at n = 16384 in float32 with
+the path matrix -- the full output of Algorithm 1 -- on a complete directed graph
+with weights uniform in (0, 1).  One step = D <- W (device copy), P <- -1, and
+all rounds of the blocked method: one whole fw_apsp call.  Inputs are resident in
+HBM before the timed region.  Timing: W untimed warm-up steps, then K steps
+between device synchronizations, timed with events on the stream the library
+runs on; the paper averages 15 repetitions (Sect. 4.1).
+
+Also reported:
+  roofline      the last-phase kernel (the min-plus tile update, >98% of the
+                work): algorithmic flops per launch / its mean launch duration
+                (events around every launch during the timed steps) against the
+                vector-ALU bound of its instruction mix.
+  cpu_baseline  the CPU oracle (classic triple loop, float64) on the same
+                matrix, a bounded prefix of its outer iterations, on all cores.
+  secondary     float64, distances-only, and (when built) batched and backward
+                figures on the same GPU.
+
+Prints one JSON line.  --gpus above 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "APSP GFLOPS=2n³/t at n=16384 FP32/FP64; batched graphs/s; fwd+bwd vs fwd"
+
+# Vector-ALU bound of the last-phase kernel, in 2-flop updates: 256 CUs x 4 SIMD x
+# 16 lanes x 2.4 GHz = 3.93e13 lane-instructions/s; float32 spends 1.5
+# instructions per update (2 v_add_f32 + 1 v_min3_f32 per two updates), float64 2
+# (v_add_f64 + v_min_f64).
+LANE_INSTR_PER_S = 256 * 64 * 2.4e9
+PEAK_TFLOPS = {"f32": LANE_INSTR_PER_S / 1.5 * 2 / 1e12, "f64": LANE_INSTR_PER_S / 2.0 * 2 / 1e12}
+CONFIG = {"f32": (64, 128), "f64": (64, 64)}  # (block, tile) used by the library by default
+KERNEL_SRC = os.path.join(ROOT, "paper_2105_07298_amd", "csrc", "fw_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def gflops(n, seconds):
+    return 2.0 * n ** 3 / seconds / 1e9
+
+
+def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False):
+    """Mean seconds per fw_apsp step (D <- W, P <- -1, all rounds) and last-phase stats."""
+    import numpy as np
+    import workloads
+    npdt = np.float32 if dtype == "f32" else np.float64
+    block, tile = CONFIG[dtype]
+    Wd = torch.from_numpy(workloads.unit_complete(n, dtype=npdt, seed=2)).cuda()
+    D = torch.empty_like(Wd)
+    P = torch.empty((n, n), dtype=torch.int32, device=Wd.device) if path else None
+
+    def step():
+        D.copy_(Wd)
+        fw.apsp_(D, P, block=block, tile=tile)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    if prof:
+        fw.fw_prof_read(reset=True)
+        fw.fw_prof_enable(True)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    sec = t0.elapsed_time(t1) / 1e3 / steps
+    stats = None
+    if prof:
+        fw.fw_prof_enable(False)
+        cnt, tot_ms = fw.fw_prof_read(reset=True)
+        stats = {"launches": cnt, "mean_ms": tot_ms / max(cnt, 1), "block": block, "tile": tile}
+    del Wd, D, P
+    torch.cuda.empty_cache()
+    return sec, stats
+
+
+def roofline(n, dtype, stats):
+    block = stats["block"]
+    upd = (n - block) ** 2 * block  # algorithmic updates of one last-phase launch
+    achieved = 2.0 * upd / (stats["mean_ms"] / 1e3) / 1e12
+    peak = PEAK_TFLOPS[dtype]
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        key = f"{dtype}_n{n}_path"
+        if t.get("kernel_hash") == kernel_hash() and key in t:
+            traffic = t[key]["bytes_per_launch"]
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": traffic,
+            "kernel": "k_phase4 (min-plus tile update)", "launches": stats["launches"],
+            "mean_launch_ms": round(stats["mean_ms"], 4), "flops_per_launch": 2 * upd}
+
+
+def cpu_baseline(n, budget_s=15.0):
+    """Oracle (float64 classic loop) on the same n x n matrix: a prefix of its outer
+    iterations on all host cores, scaled to GFLOPS (each iteration is n^2 updates)."""
+    import numpy as np
+    import oracle
+    import workloads
+    W = workloads.unit_complete(n, dtype=np.float32, seed=2)
+    D = W.astype(np.float64)
+    del W
+    P = np.full((n, n), -1, dtype=np.int32)
+    cores = oracle.max_threads()
+    t = time.perf_counter()
+    k = 4
+    oracle.fw_steps(D, P, 0, k)
+    dt = time.perf_counter() - t
+    per = dt / k
+    k2 = int(max(1, min(n - k, budget_s / max(per, 1e-9))))
+    t = time.perf_counter()
+    oracle.fw_steps(D, P, k, k + k2)
+    dt = time.perf_counter() - t
+    total_k = k2
+    g = 2.0 * n * n * total_k / dt / 1e9
+    return {"value": round(g, 3), "unit": "GFLOPS", "cores": cores, "kind": "oracle",
+            "sample": f"outer iterations {k}..{k + k2 - 1} of {n} of the float64 classic loop on the same "
+                      f"n={n} matrix ({dt:.1f} s, {total_k * n * n:.3e} updates)",
+            "extrapolated_full_run_s": round(dt / total_k * n, 1)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--no-path", action="store_true", help="distances only (P = NULL)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after timing, one device copy of this many MiB (HBM counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(f"bench.py: --gpus {args.gpus} requested, but this library runs on one GPU; "
+              "multi-GPU runs are not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2105_07298_amd as fw
+    assert torch.cuda.is_available(), "no GPU"
+    torch.cuda.set_device(0)
+    fw.lib()
+
+    path = not args.no_path
+    print(f"[bench] n={args.n} {args.dtype} path={path} warmup={args.warmup} steps={args.steps}",
+          file=sys.stderr, flush=True)
+    sec, stats = time_apsp(fw, torch, args.n, args.dtype, path, args.steps, args.warmup, prof=True)
+    value = gflops(args.n, sec)
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GFLOPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": f"complete directed graph n={args.n}, weights uniform real in (0,1), "
+                               f"{'float32' if args.dtype == 'f32' else 'float64'}, "
+                               f"{'distances + path matrix' if path else 'distances only'}",
+                   "n": args.n, "path": path, "block": stats["block"], "tile": stats["tile"],
+                   "parallelism": "single GPU"},
+        "roofline": roofline(args.n, args.dtype, stats),
+    }
+    if args.calib_copy_mib:
+        nb = args.calib_copy_mib * (1 << 20)
+        a = torch.empty(nb // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = nb
+    if not args.no_secondary:
+        sec_out = {}
+        for dt_, pth in (("f64", True), ("f32", False), ("f64", False)):
+            if dt_ == args.dtype and pth == path:
+                continue
+            print(f"[bench] secondary n={args.n} {dt_} path={pth}", file=sys.stderr, flush=True)
+            s, st = time_apsp(fw, torch, args.n, dt_, pth, 2, 1, prof=True)
+            key = f"{dt_}_{'path' if pth else 'dist'}"
+            sec_out[key] = {"gflops": round(gflops(args.n, s), 2), "ms_per_step": round(s * 1e3, 2),
+                            "roofline_frac": roofline(args.n, dt_, st)["frac"]}
+        out["secondary"] = sec_out
+    out["paper_context"] = {"note": "best measured GFLOPS over N in {4096..65536}, other hardware",
+                            "f32": {"Xeon Phi KNL 7230": 1037, "Titan X (Pascal)": 972},
+                            "f64": {"Xeon Phi KNL 7230": 501, "Titan X (Pascal)": 90}}
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

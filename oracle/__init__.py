@@ -57,6 +57,7 @@ def load(path: str = _LIB):
     i64, i32p, vp = ctypes.c_int64, ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p
     lib.oracle_fw_f64.argtypes = [i64, vp, vp, ctypes.c_int]
     lib.oracle_fw_i64.argtypes = [i64, vp, vp, ctypes.c_int]
+    lib.oracle_fw_f64_steps.argtypes = [i64, vp, vp, i64, i64, ctypes.c_int]
     lib.oracle_dijkstra_rows_f64.argtypes = [i64, vp, i64, vp, vp, vp, ctypes.c_int]
     lib.oracle_dijkstra_rows_i64.argtypes = [i64, vp, i64, vp, vp, vp, ctypes.c_int]
     lib.oracle_backward_pathwalk_f64.argtypes = [i64, vp, vp, vp, vp]
@@ -133,6 +134,18 @@ def fw(W: np.ndarray, exact: bool | None = None, threads: int = 0):
     D = np.ascontiguousarray(W, dtype=np.float64).copy()
     lib.oracle_fw_f64(n, _ptr(D), _ptr(P), threads)
     return D, P
+
+
+def fw_steps(D: np.ndarray, P: np.ndarray, k_begin: int, k_end: int, threads: int = 0):
+    """Run outer iterations [k_begin, k_end) of the float64 classic loop in place
+    (D float64, P int32, both C-contiguous; P set to -1 before the first call)."""
+    lib = load()
+    assert D.dtype == np.float64 and P.dtype == np.int32
+    lib.oracle_fw_f64_steps(D.shape[0], _ptr(D), _ptr(P), k_begin, k_end, threads)
+
+
+def max_threads() -> int:
+    return int(load().oracle_max_threads())
 
 
 def dijkstra_rows(W: np.ndarray, srcs, exact: bool | None = None, threads: int = 0):

@@ -44,10 +44,20 @@ static int pick_threads(int threads) { return threads > 0 ? threads : omp_get_ma
 /* Classic Floyd-Warshall, double.  D (n*n, row-major) holds W on entry and the
  * shortest distances on exit; P (n*n) receives the intermediate vertex, -1 for
  * "none".  Paper Sect. 2.2, Algorithm 1 (strict test, see header). */
+void oracle_fw_f64_steps(int64_t n, double *D, int32_t *P, int64_t k_begin, int64_t k_end, int threads);
+
 void oracle_fw_f64(int64_t n, double *D, int32_t *P, int threads)
 {
     for (int64_t x = 0; x < n * n; ++x) P[x] = -1;
-    for (int64_t k = 0; k < n; ++k) {
+    oracle_fw_f64_steps(n, D, P, 0, n, threads);
+}
+
+/* Outer iterations k_begin <= k < k_end of the loop above (P already set up).
+ * oracle_fw_f64 runs all of them; a prefix of them times the loop on a bounded
+ * sample of a large input. */
+void oracle_fw_f64_steps(int64_t n, double *D, int32_t *P, int64_t k_begin, int64_t k_end, int threads)
+{
+    for (int64_t k = k_begin; k < k_end; ++k) {
         const double *rowk = D + k * n;
 #pragma omp parallel for schedule(static) num_threads(pick_threads(threads))
         for (int64_t i = 0; i < n; ++i) {

@@ -21,6 +21,12 @@ hipError_t launch_round(T *D, int32_t *P, int64_t ld, int r, TileCfg cfg, hipStr
 template <typename T>
 bool config_supported(TileCfg cfg);
 
+// Path mode, after the last round: resolve the labels the last phase left
+// pending.  DT (ld*ld elements) and P0 (ld*ld int32) are scratch: the transpose
+// of D and a snapshot of P.
+template <typename T>
+hipError_t launch_resolve(const T *D, T *DT, int32_t *P0, int32_t *P, int64_t ld, int block, hipStream_t s);
+
 // Fill n int32 with v.
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 

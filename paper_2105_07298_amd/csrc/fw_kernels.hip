@@ -13,11 +13,14 @@
 // (length, max(P[i][k], k, P[k][j])); an entry takes a candidate whose label is
 // lexicographically smaller.  This reproduces, whatever the block size, what the
 // classic loop with a strict test stores (the smallest possible largest interior
-// vertex over all shortest paths).  The last phase takes path mode in two
-// passes: the k-loop computes only the minimum length S (the same instructions
-// as distances-only mode), and the few entries whose S reaches or beats the
-// current length are queued and resolved afterwards by scanning the k that
-// attain S.
+// vertex over all shortest paths).  Phases 1-3 apply that rule directly.  The
+// last phase defers it: an entry that strictly improves in round r is only
+// marked "pending from round r" (P = -2 - r), and k_resolve computes all pending
+// labels in one pass after the last round (see there for why the final
+// distances suffice).  Pending values are negative, and every label they stand
+// for is below the first vertex of any later round, so phases 1-3 of later
+// rounds treat them exactly as they would treat the true label: it never wins a
+// max() against k and never makes a tie win.
 //
 // All arithmetic is on the vector ALU: the min-plus product is not a ring
 // contraction, so matrix cores do not apply.
@@ -235,6 +238,13 @@ __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__re
 // Tile order: workgroups are spread round-robin over the 8 XCDs; each XCD gets a
 // contiguous range of tiles, walked in groups of 8 tile rows so that the
 // workgroups resident on one XCD share A and B panels in its L2.
+//
+// Path mode: before this round every label of a phase-4 entry is below
+// k0 = r*TB (its paths use interior vertices of earlier blocks only), and every
+// candidate through block r has a label of at least k0.  So a candidate that
+// merely ties the old length never changes the label, and an entry that strictly
+// improves gets a label decided entirely by this round's candidates: it is
+// marked pending (P = -2 - r) and resolved by k_resolve.
 template <typename T, int TB, int BM, int BN, int RM, int RN, bool PATH>
 __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, int32_t *__restrict__ P, int64_t ld, int r,
                                               int gm, int gn, int skip, int per_xcd, int ntiles) {
@@ -245,13 +255,10 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, int32_t *__res
     static_assert(RN % V == 0, "micro-tile width");
     constexpr int HN = RN / V, CS = BN / HN;
     constexpr int AST = TB + V;
-    constexpr int CAP = 256;  // queued entries per wave and sweep (path mode)
-    constexpr int NW = NT / 64;
+    constexpr bool PREFETCH_C = true;
 
     __shared__ __attribute__((aligned(16))) T As[BM * AST];
     __shared__ __attribute__((aligned(16))) T Bs[TB * BN];
-    __shared__ uint32_t q_rc[PATH ? NW * CAP : 1];
-    __shared__ T q_s[PATH ? NW * CAP : 1];
 
     const int wg = blockIdx.x;
     const int lin = (wg % 8) * per_xcd + wg / 8;
@@ -272,14 +279,16 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, int32_t *__res
     const bool mask_cols = (J0 <= k0) && (k0 < J0 + BN);
 
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
+    auto c_ptr = [&](int ii, int h) { return D + (I0 + ty + TY * ii) * ld + J0 + h * CS + tx * V; };
 
-    // Old C values, requested first so their latency overlaps the panel loads.
     vec c[RM][HN];
+    if constexpr (PREFETCH_C) {
+        // Old C values, requested first so their latency overlaps the panel loads.
 #pragma unroll
-    for (int ii = 0; ii < RM; ++ii)
+        for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
-        for (int h = 0; h < HN; ++h)
-            c[ii][h] = *(const vec *)(D + (I0 + ty + TY * ii) * ld + J0 + h * CS + tx * V);
+            for (int h = 0; h < HN; ++h) c[ii][h] = *(const vec *)c_ptr(ii, h);
+    }
 
     const vec vinf = inf_v<T>();
     for (int q = tid; q < BM * (TB / V); q += NT) {
@@ -327,132 +336,119 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, int32_t *__res
         }
     }
 
-    // New distances: store the 16-byte vectors in which some entry decreased.
+    if constexpr (!PREFETCH_C) {
+#pragma unroll
+        for (int ii = 0; ii < RM; ++ii)
+#pragma unroll
+            for (int h = 0; h < HN; ++h) c[ii][h] = *(const vec *)c_ptr(ii, h);
+    }
+
+    // New distances: store the 16-byte vectors in which some entry decreased;
+    // in path mode mark each decreased entry pending from this round.
+    const int32_t pend = -2 - r;
 #pragma unroll
     for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
         for (int h = 0; h < HN; ++h) {
             vec nv = c[ii][h];
+            bool lt[V];
             bool ch = false;
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 const T s = acc[ii][h * V + e];
-                ch |= s < nv[e];
-                nv[e] = s < nv[e] ? s : nv[e];
+                lt[e] = s < nv[e];
+                ch |= lt[e];
+                nv[e] = lt[e] ? s : nv[e];
             }
-            if (ch) *(vec *)(D + (I0 + ty + TY * ii) * ld + J0 + h * CS + tx * V) = nv;
+            if (ch) {
+                *(vec *)c_ptr(ii, h) = nv;
+                if constexpr (PATH) {
+                    int32_t *pp = P + (c_ptr(ii, h) - D);
+#pragma unroll
+                    for (int e = 0; e < V; ++e)
+                        if (lt[e]) pp[e] = pend;
+                }
+            }
         }
+}
 
-    if constexpr (PATH) {
-        // Second pass.  An entry needs its path label when S = min_k(A+B) is
-        // finite and <= the old length: S < old ("improve") sets P to the
-        // smallest label among the k with A+B == S; S == old ("tie") keeps the
-        // smaller of that and the old P.  Each wave queues its own entries in
-        // LDS (ballot + prefix count, no atomics) and resolves CAP at a time,
-        // each lane taking four.  Labels need P of the panels, read from
-        // global memory (the panels are not written in this phase).
-        const int wave = tid >> 6, lane = tid & 63;
-        uint32_t *qrc = q_rc + wave * CAP;
-        T *qs = q_s + wave * CAP;
-        for (int skip_n = 0;; skip_n += CAP) {
-            int cum = 0;
+// ---------------------------------------------------------------------------
+// Label resolution (path mode, after the last round).  Entry (i, j) pending
+// from round r (P = -2 - r) last decreased in the last phase of round r, to
+// S = min over k in K_r of A[i][k] + B[k][j].  For every k that attains S, the
+// entries (i, k) and (k, j) were already final then: a later decrease of either
+// would give (i, j) a strictly shorter path, contradicting that S is final.  So
+// the k that attain S are found from the final matrix -- those with
+// D[i][k] + D[k][j] == D[i][j], the same float addition -- and the label is
+// min over them of max(P[i][k], k, P[k][j]).  Any k that attains D[i][j] only
+// with final values (because D[i][k] or D[k][j] decreased later) has a label
+// from a later round, larger than every label of round r, so it never changes
+// the minimum -- and such a k is recognisable: one of its two entries
+// decreased after round r, so if that entry is still pending, it is pending
+// from a round later than r; such k are skipped.  Otherwise P[i][k] and
+// P[k][j] are either final labels or pending from rounds before r, whose
+// labels are below k0 and so do not change max(., k, .): their pending value
+// serves as well as the label.  Entries are therefore resolved independently,
+// in one launch, reading labels from a snapshot P0 of P taken before it.
+// Column segments come from a transposed copy DT (DT[j][k] = D[k][j]) so that
+// both segments are contiguous.  With non-integer weights, rounding can break
+// the exact equality (a sub-path decreased later by less than the sum's
+// rounding step); then the k with the smallest sum is taken and the label is k
+// itself, which still encodes a path of length D[i][j] up to rounding.
+template <typename T, int TB>
+__global__ void __launch_bounds__(NT) k_resolve(const T *__restrict__ D, const T *__restrict__ DT,
+                                               const int32_t *__restrict__ P0, int32_t *__restrict__ P,
+                                               int64_t ld) {
+    using vec = typename V16<T>::type;
+    constexpr int V = V16<T>::n;
+    const int64_t i = blockIdx.y;
+    const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (j >= ld) return;
+    const int64_t ij = i * ld + j;
+    const int32_t pv = P0[ij];
+    if (pv > -2) return;
+    const int64_t k0 = (int64_t)(-2 - pv) * TB;
+    const T d = D[ij];
+    const T *arow = D + i * ld + k0;
+    const T *brow = DT + j * ld + k0;
+    uint64_t hits = 0;
+    T best = inf_v<T>();
+    int kbest = 0;
+#pragma unroll 4
+    for (int kv = 0; kv < TB / V; ++kv) {
+        const vec a = *(const vec *)(arow + kv * V);
+        const vec b = *(const vec *)(brow + kv * V);
 #pragma unroll
-            for (int ii = 0; ii < RM; ++ii)
-#pragma unroll
-                for (int h = 0; h < HN; ++h)
-#pragma unroll
-                    for (int e = 0; e < V; ++e) {
-                        const T s = acc[ii][h * V + e], old = c[ii][h][e];
-                        const bool mk = (s <= old) && (s < inf_v<T>());
-                        const uint64_t bal = __ballot(mk);
-                        if (bal) {
-                            const int pos = cum + (int)__builtin_amdgcn_mbcnt_hi(
-                                                      (uint32_t)(bal >> 32),
-                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                            if (mk && pos >= skip_n && pos < skip_n + CAP) {
-                                const uint32_t row = ty + TY * ii, col = h * CS + tx * V + e;
-                                qrc[pos - skip_n] = row | (col << 8) | ((uint32_t)(s < old) << 16);
-                                qs[pos - skip_n] = s;
-                            }
-                            cum += __popcll(bal);
-                        }
-                    }
-            const int nq = min(cum - skip_n, CAP);
-            if (nq <= 0) break;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-            constexpr int U = CAP / 64;
-            uint64_t hits[U];
-            uint32_t rc[U];
-            int32_t M[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int t = lane + 64 * u;
-                hits[u] = 0;
-                rc[u] = 0;
-                M[u] = INT_MAX;
-                if (t < nq) {
-                    rc[u] = qrc[t];
-                    const T S = qs[t];
-                    const int row = rc[u] & 255, col = (rc[u] >> 8) & 255;
-                    const T *arow = As + row * AST;
-                    uint64_t hm = 0;
-#pragma unroll
-                    for (int kv = 0; kv < TB / V; ++kv) {
-                        const vec av = *(const vec *)(arow + kv * V);
-#pragma unroll
-                        for (int e = 0; e < V; ++e) {
-                            const T s = av[e] + Bs[(kv * V + e) * BN + col];
-                            hm |= (s == S) ? (1ull << (kv * V + e)) : 0ull;
-                        }
-                    }
-                    hits[u] = hm;
-                }
-            }
-            __builtin_amdgcn_wave_barrier();  // queue slots are free for the next sweep from here
-
-            // Old P of each queued entry and the labels of the k that attain S.
-            // Every lane issues its loads for all four entries before using any
-            // (indices are clamped into the tile when a slot is empty).
-            int32_t pold[U];
-            bool first = true;
-            for (;;) {
-                int32_t pa[U], pb[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int row = rc[u] & 255, col = (rc[u] >> 8) & 255;
-                    const int k = hits[u] ? __builtin_ctzll(hits[u]) : 0;
-                    pa[u] = P[(I0 + row) * ld + k0 + k];
-                    pb[u] = P[(k0 + k) * ld + J0 + col];
-                    if (first) pold[u] = P[(I0 + row) * ld + J0 + col];
-                }
-                bool more = false;
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (hits[u]) {
-                        const int k = __builtin_ctzll(hits[u]);
-                        M[u] = min(M[u], max(max(pa[u], pb[u]), (int32_t)(k0 + k)));
-                        hits[u] &= hits[u] - 1;
-                        more |= hits[u] != 0;
-                    }
-                }
-                first = false;
-                if (!__any(more)) break;
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (lane + 64 * u < nq) {
-                    const int row = rc[u] & 255, col = (rc[u] >> 8) & 255;
-                    const bool improve = (rc[u] >> 16) & 1;
-                    const int32_t np = improve ? M[u] : min(pold[u], M[u]);
-                    if (np != pold[u]) P[(I0 + row) * ld + J0 + col] = np;
-                }
-            }
-            if (cum <= skip_n + CAP) break;
+        for (int e = 0; e < V; ++e) {
+            const T s = a[e] + b[e];
+            const int k = kv * V + e;
+            hits |= (s == d) ? (1ull << k) : 0ull;
+            kbest = (s < best) ? k : kbest;
+            best = vmin(best, s);
         }
     }
+    const int32_t r = -2 - pv;
+    int32_t M = INT_MAX;
+    while (hits) {
+        const int k = __builtin_ctzll(hits);
+        hits &= hits - 1;
+        const int64_t kg = k0 + k;
+        const int32_t a = P0[i * ld + kg], b = P0[kg * ld + j];
+        if ((a <= -2 && -2 - a > r) || (b <= -2 && -2 - b > r)) continue;  // decreased after round r
+        M = min(M, max(max(a, b), (int32_t)kg));
+    }
+    P[ij] = (M == INT_MAX) ? (int32_t)(k0 + kbest) : M;
+}
+
+// Tiled transpose: DT[j][i] = D[i][j] (ld x ld, ld a multiple of 64).
+template <typename T>
+__global__ void __launch_bounds__(NT) k_transpose(const T *__restrict__ D, T *__restrict__ DT, int64_t ld) {
+    __shared__ T t[64][65];
+    const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
+    const int tx = threadIdx.x % 64, ty = threadIdx.x / 64;
+    for (int rr = ty; rr < 64; rr += NT / 64) t[rr][tx] = D[(i0 + rr) * ld + j0 + tx];
+    __syncthreads();
+    for (int rr = ty; rr < 64; rr += NT / 64) DT[(j0 + rr) * ld + i0 + tx] = t[tx][rr];
 }
 
 // ---------------------------------------------------------------------------
@@ -539,6 +535,21 @@ hipError_t launch_round(T *D, int32_t *P, int64_t ld, int r, TileCfg c, hipStrea
     return hipErrorInvalidValue;
 }
 
+template <typename T>
+hipError_t launch_resolve(const T *D, T *DT, int32_t *P0, int32_t *P, int64_t ld, int block, hipStream_t s) {
+    hipError_t e = hipMemcpyAsync(P0, P, (size_t)(ld * ld) * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_transpose<T>), dim3((unsigned)(ld / 64), (unsigned)(ld / 64)), dim3(NT), 0, s, D, DT, ld);
+    const dim3 grid((unsigned)((ld + NT - 1) / NT), (unsigned)ld);
+    if (block == 64)
+        hipLaunchKernelGGL((k_resolve<T, 64>), grid, dim3(NT), 0, s, D, DT, P0, P, ld);
+    else if (block == 32)
+        hipLaunchKernelGGL((k_resolve<T, 32>), grid, dim3(NT), 0, s, D, DT, P0, P, ld);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(NT), 0, s, p, n, v);
     return hipGetLastError();
@@ -560,6 +571,8 @@ template bool config_supported<float>(TileCfg);
 template bool config_supported<double>(TileCfg);
 template hipError_t launch_round<float>(float *, int32_t *, int64_t, int, TileCfg, hipStream_t);
 template hipError_t launch_round<double>(double *, int32_t *, int64_t, int, TileCfg, hipStream_t);
+template hipError_t launch_resolve<float>(const float *, float *, int32_t *, int32_t *, int64_t, int, hipStream_t);
+template hipError_t launch_resolve<double>(const double *, double *, int32_t *, int32_t *, int64_t, int, hipStream_t);
 template hipError_t launch_pad_in<float>(const float *, int64_t, float *, int64_t, hipStream_t);
 template hipError_t launch_pad_in<double>(const double *, int64_t, double *, int64_t, hipStream_t);
 template hipError_t launch_pad_out<float>(const float *, int64_t, float *, int64_t, hipStream_t);

@@ -80,6 +80,17 @@ fw_status_t run_apsp(int64_t n, T *dist, int32_t *path, fw::TileCfg cfg, hipStre
     const int R = (int)(npad / cfg.block);
     for (int r = 0; r < R; ++r)
         if ((e = fw::launch_round<T>(D, P, npad, r, cfg, s)) != hipSuccess) return hip_fail(e, "round launch");
+    if (P) {
+        // Labels the last phase left pending: transpose of D + snapshot of P as scratch.
+        void *rs = nullptr;
+        const size_t tb = (size_t)(npad * npad) * sizeof(T), pb = (size_t)(npad * npad) * sizeof(int32_t);
+        e = hipMallocAsync(&rs, tb + pb, s);
+        if (e != hipSuccess) return fail(FW_ENOMEM, "label scratch of %zu bytes: %s", tb + pb, hipGetErrorString(e));
+        e = fw::launch_resolve<T>(D, (T *)rs, (int32_t *)((char *)rs + tb), P, npad, cfg.block, s);
+        hipError_t e2 = hipFreeAsync(rs, s);
+        if (e != hipSuccess) return hip_fail(e, "label resolution");
+        if (e2 != hipSuccess) return hip_fail(e2, "label scratch free");
+    }
     if (scratch) {
         if ((e = fw::launch_pad_out<T>(D, npad, dist, n, s)) != hipSuccess) return hip_fail(e, "unpad");
         if (path && (e = fw::launch_pad_out<int32_t>(P, npad, path, n, s)) != hipSuccess) return hip_fail(e, "unpad P");

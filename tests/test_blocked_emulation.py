@@ -134,3 +134,78 @@ def test_model_real_weights_tolerance():
     Dm, Pm = blocked_model(W, 8)
     np.testing.assert_allclose(Dm, D, rtol=1e-14)
     oracle.check_invariants(W, Dm, Pm, exact=False, rtol=1e-12)
+
+
+def blocked_model_deferred(W, TB):
+    """The GPU's path-mode schedule: phases 1-3 apply the lexicographic rule to raw P
+    (pending marks included), the last phase only marks strict improvements as
+    pending (P = -2 - r), and one pass after the last round resolves every pending
+    label from the final D and a snapshot of P."""
+    n = W.shape[0]
+    npad = -(-n // TB) * TB
+    D = np.full((npad, npad), np.inf)
+    np.fill_diagonal(D, 0.0)
+    D[:n, :n] = W
+    P = np.full((npad, npad), -1, dtype=np.int64)
+    R = npad // TB
+    for r in range(R):
+        K = np.arange(r * TB, (r + 1) * TB)
+        ks = slice(r * TB, (r + 1) * TB)
+        for k in K:
+            s = D[ks, k:k + 1] + D[k:k + 1, ks]
+            m = np.maximum(np.maximum(P[ks, k:k + 1], k), P[k:k + 1, ks])
+            D[ks, ks], P[ks, ks] = lex_update(D[ks, ks], P[ks, ks], s, m)
+        Dkk, Pkk = D[ks, ks].copy(), P[ks, ks].copy()
+        others = [b for b in range(R) if b != r]
+        for b in others:
+            js = slice(b * TB, (b + 1) * TB)
+            D[ks, js], P[ks, js] = product_lex(Dkk, Pkk, D[ks, js].copy(), P[ks, js].copy(), K,
+                                               D[ks, js], P[ks, js])
+            D[js, ks], P[js, ks] = product_lex(D[js, ks].copy(), P[js, ks].copy(), Dkk, Pkk, K,
+                                               D[js, ks], P[js, ks])
+        for bi in others:
+            for bj in others:
+                is_, js = slice(bi * TB, (bi + 1) * TB), slice(bj * TB, (bj + 1) * TB)
+                S = np.full((TB, TB), np.inf)
+                for t in range(TB):
+                    S = np.minimum(S, D[is_, r * TB + t:r * TB + t + 1] + D[r * TB + t:r * TB + t + 1, js])
+                imp = S < D[is_, js]
+                D[is_, js] = np.where(imp, S, D[is_, js])
+                P[is_, js] = np.where(imp, -2 - r, P[is_, js])
+    P0 = P.copy()
+    for i, j in zip(*np.nonzero(P0 <= -2)):
+        r = -2 - P0[i, j]
+        ks = np.arange(r * TB, (r + 1) * TB)
+        sums = D[i, ks] + D[ks, j]
+        labels = []
+        for k in ks[sums == D[i, j]]:
+            a, b = P0[i, k], P0[k, j]
+            # a dependency pending from a later round decreased after round r: k
+            # attains D[i][j] only with final values and its label is larger than
+            # every label of round r
+            if (a <= -2 and -2 - a > r) or (b <= -2 and -2 - b > r):
+                continue
+            labels.append(max(a, k, b))
+        assert labels
+        P[i, j] = min(labels)
+    return D[:n, :n], P[:n, :n].astype(np.int32)
+
+
+@pytest.mark.parametrize("TB", [1, 2, 3, 4, 8, 16])
+@pytest.mark.parametrize("seed", range(4))
+def test_deferred_labels_equal_classic(TB, seed):
+    rng = np.random.default_rng(seed + 40)
+    n = int(rng.integers(5, 48))
+    W = workloads.int_graph(n=n, p=float(rng.uniform(0.05, 0.6)), wmax=int(rng.integers(1, 4)), seed=seed + 170)
+    D, P = oracle.fw(W)
+    Dm, Pm = blocked_model_deferred(W.astype(np.float64), TB)
+    np.testing.assert_array_equal(Dm, D)
+    np.testing.assert_array_equal(Pm, P)
+
+
+def test_deferred_labels_c1_like():
+    W = workloads.int_graph(n=128, p=0.5, wmax=1000, seed=1)
+    D, P = oracle.fw(W)
+    Dm, Pm = blocked_model_deferred(W.astype(np.float64), 16)
+    np.testing.assert_array_equal(Dm, D)
+    np.testing.assert_array_equal(Pm, P)

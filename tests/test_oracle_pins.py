@@ -243,3 +243,15 @@ def test_input_contract_rejected():
     W[0, 1] = np.nan
     with pytest.raises(ValueError):
         oracle.fw(W)
+
+
+def test_step_ranges_compose():
+    """Running the outer iterations in two ranges gives the full loop's result."""
+    W = workloads.unit_complete(200, dtype=np.float64, seed=13)
+    D, P = oracle.fw(W)
+    D2 = W.copy()
+    P2 = np.full((200, 200), -1, dtype=np.int32)
+    oracle.fw_steps(D2, P2, 0, 77)
+    oracle.fw_steps(D2, P2, 77, 200)
+    np.testing.assert_array_equal(D2, D)
+    np.testing.assert_array_equal(P2, P)
