@@ -54,3 +54,39 @@ def apsp(W, path: bool = True, block: int = 0, tile: int = 0):
     D = W.contiguous().clone()
     P = torch.empty(D.shape, dtype=torch.int32, device=D.device) if path else None
     return apsp_(D, P, block, tile)
+
+
+def apsp_batched_(Dcat, ns, offsets, Pcat=None):
+    """In-place APSP of many graphs in one persistent launch.
+
+    Dcat: 1-D contiguous device tensor (float32/float64) holding every graph's
+    n_b x n_b weight matrix row-major at element offset offsets[b]; overwritten
+    with distances.  ns (int32) and offsets (int64) are host sequences of length
+    batch.  Pcat (int32, same length as Dcat) receives the path matrices.
+    """
+    import numpy as np
+    import torch
+    ns = np.ascontiguousarray(ns, dtype=np.int32)
+    offs = np.ascontiguousarray(offsets, dtype=np.int64)
+    if ns.shape != offs.shape or ns.ndim != 1:
+        raise ValueError("ns and offsets must be 1-D of equal length")
+    if not (Dcat.is_cuda and Dcat.dim() == 1 and Dcat.is_contiguous()):
+        raise ValueError("Dcat must be a contiguous 1-D device tensor")
+    if (offs + ns.astype(np.int64) ** 2).max(initial=0) > Dcat.numel():
+        raise ValueError("a graph extends past the end of Dcat")
+    pp = None
+    if Pcat is not None:
+        if not (Pcat.is_cuda and Pcat.dtype == torch.int32 and Pcat.shape == Dcat.shape and Pcat.is_contiguous()):
+            raise ValueError("Pcat must be a contiguous int32 device tensor shaped like Dcat")
+        pp = Pcat.data_ptr()
+    fw_apsp_batched(_dtype_code(Dcat), int(ns.size), ns.ctypes.data, offs.ctypes.data, Dcat.data_ptr(), pp,
+                    _stream_ptr(Dcat.device))
+    return Dcat, Pcat
+
+
+def apsp_batched(Wcat, ns, offsets, path: bool = True):
+    """(Dcat, Pcat) for a ragged batch of weight matrices (Wcat is not modified)."""
+    import torch
+    D = Wcat.contiguous().clone()
+    P = torch.empty(D.shape, dtype=torch.int32, device=D.device) if path else None
+    return apsp_batched_(D, ns, offsets, P)

@@ -27,6 +27,16 @@ bool config_supported(TileCfg cfg);
 template <typename T>
 hipError_t launch_resolve(const T *D, T *DT, int32_t *P0, int32_t *P, int64_t ld, int block, hipStream_t s);
 
+// Persistent batched launch (one workgroup per graph at a time).  jobs is a
+// device table of 1 + 2*njobs int64: [0] the queue counter (must be 0), then
+// (element offset, n) per queue slot in processing order.  block = tile edge.
+template <typename T>
+hipError_t launch_batched(T *dist, int32_t *path, int64_t *jobs, int njobs, int block, int grid, hipStream_t s);
+
+// Workgroups of the batched kernel that fit on one CU at once.
+template <typename T>
+int batched_occupancy(int block, bool path);
+
 // Fill n int32 with v.
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 

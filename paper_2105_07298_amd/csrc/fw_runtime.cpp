@@ -8,6 +8,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -51,6 +52,13 @@ hipEvent_t take_event() {
 }
 
 constexpr int64_t kMaxN = int64_t(1) << 20;
+constexpr int32_t kMaxBatchedN = 4096;
+
+// Pinned staging for the batched job table.
+std::mutex g_stage_mu;
+void *g_stage = nullptr;
+size_t g_stage_cap = 0;
+hipEvent_t g_stage_ev = nullptr;
 
 fw::TileCfg default_cfg(fw_dtype_t dt, int64_t n) {
     if (dt == FW_F64) return {64, 64};
@@ -154,9 +162,63 @@ fw_status_t fw_apsp(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, void *s
 
 fw_status_t fw_apsp_batched(fw_dtype_t dt, int32_t batch, const int32_t *n_host, const int64_t *off_host, void *dist,
                             int32_t *path, void *stream) {
-    (void)dt; (void)batch; (void)n_host; (void)off_host; (void)dist; (void)path; (void)stream;
     g_err[0] = 0;
-    return fail(FW_EUNSUPPORTED, "fw_apsp_batched is not built yet");
+    if (dt != FW_F32 && dt != FW_F64) return fail(FW_EINVAL, "unknown dtype %d", (int)dt);
+    if (batch < 1) return fail(FW_EINVAL, "batch = %d < 1", batch);
+    if (!n_host || !off_host || !dist) return fail(FW_EINVAL, "NULL argument");
+    for (int32_t b = 0; b < batch; ++b) {
+        if (n_host[b] < 1 || n_host[b] > kMaxBatchedN)
+            return fail(FW_EINVAL, "n[%d] = %d outside [1, %d]", b, n_host[b], kMaxBatchedN);
+        if (off_host[b] < 0) return fail(FW_EINVAL, "offset[%d] < 0", b);
+    }
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    const int block = 64;
+    // Queue in order of decreasing n (longest job first); counter slot first.
+    std::vector<int32_t> order((size_t)batch);
+    for (int32_t b = 0; b < batch; ++b) order[(size_t)b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return n_host[x] > n_host[y]; });
+    const size_t words = 1 + 2 * (size_t)batch, bytes = words * sizeof(int64_t);
+    void *djobs = nullptr;
+    e = hipMallocAsync(&djobs, bytes, s);
+    if (e != hipSuccess) return fail(FW_ENOMEM, "job table of %zu bytes: %s", bytes, hipGetErrorString(e));
+    {
+        // Pinned staging buffer, reused across calls once its previous upload is done.
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        if (g_stage_ev && (e = hipEventSynchronize(g_stage_ev)) != hipSuccess) return hip_fail(e, "staging wait");
+        if (g_stage_cap < bytes) {
+            if (g_stage) (void)hipHostFree(g_stage);
+            g_stage = nullptr;
+            g_stage_cap = 0;
+            if ((e = hipHostMalloc(&g_stage, bytes, 0)) != hipSuccess) return fail(FW_ENOMEM, "pinned staging: %s", hipGetErrorString(e));
+            g_stage_cap = bytes;
+        }
+        int64_t *tab = (int64_t *)g_stage;
+        tab[0] = 0;
+        for (int32_t q = 0; q < batch; ++q) {
+            tab[1 + 2 * q] = off_host[order[(size_t)q]];
+            tab[2 + 2 * q] = n_host[order[(size_t)q]];
+        }
+        if ((e = hipMemcpyAsync(djobs, g_stage, bytes, hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e, "job upload");
+        if (!g_stage_ev && (e = hipEventCreateWithFlags(&g_stage_ev, hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(e, "event");
+        if ((e = hipEventRecord(g_stage_ev, s)) != hipSuccess) return hip_fail(e, "event record");
+    }
+    int cus = 0;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return hip_fail(e, "CU count");
+    const bool p = path != nullptr;
+    const int occ = dt == FW_F32 ? fw::batched_occupancy<float>(block, p) : fw::batched_occupancy<double>(block, p);
+    int grid = cus * occ;
+    if (grid > batch) grid = batch;
+    e = dt == FW_F32 ? fw::launch_batched<float>((float *)dist, path, (int64_t *)djobs, batch, block, grid, s)
+                     : fw::launch_batched<double>((double *)dist, path, (int64_t *)djobs, batch, block, grid, s);
+    hipError_t e2 = hipFreeAsync(djobs, s);
+    if (e != hipSuccess) return hip_fail(e, "batched launch");
+    if (e2 != hipSuccess) return hip_fail(e2, "job table free");
+    return FW_OK;
 }
 
 fw_status_t fw_apsp_backward(fw_dtype_t dt, int64_t n, int32_t batch, const void *dist, const int32_t *path,

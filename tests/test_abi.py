@@ -79,3 +79,16 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(ImportError):
         L.lib()
+
+
+def test_batched_argument_errors_before_device(fw):
+    import numpy as np
+    L = fw.lib()
+    ns = np.array([4, 0], dtype=np.int32)
+    offs = np.array([0, 16], dtype=np.int64)
+    assert L.fw_apsp_batched(0, 2, ns.ctypes.data, offs.ctypes.data, 4096, None, None) == fw.FW_EINVAL
+    assert L.fw_apsp_batched(0, 0, ns.ctypes.data, offs.ctypes.data, 4096, None, None) == fw.FW_EINVAL
+    assert L.fw_apsp_batched(0, 1, None, offs.ctypes.data, 4096, None, None) == fw.FW_EINVAL
+    offs2 = np.array([-1], dtype=np.int64)
+    ns2 = np.array([3], dtype=np.int32)
+    assert L.fw_apsp_batched(0, 1, ns2.ctypes.data, offs2.ctypes.data, 4096, None, None) == fw.FW_EINVAL

@@ -1,0 +1,135 @@
+"""GPU parity of fw_apsp_batched (one persistent launch over many graphs) against
+the CPU oracle, graph by graph, and against fw_apsp on each graph."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2105_07298_amd as fw
+    fw.lib()
+    return torch.device("cuda:0")
+
+
+def ragged(graphs, dtype):
+    ns = np.array([g.shape[0] for g in graphs], dtype=np.int32)
+    off = np.zeros(len(graphs) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(ns.astype(np.int64) ** 2)
+    W = np.concatenate([g.astype(dtype).ravel() for g in graphs])
+    return ns, off, W
+
+
+def run_batched(ns, off, W, dev, path=True, case=""):
+    import torch
+    import paper_2105_07298_amd as fw
+    print(f"[gpu] fw_apsp_batched {case} batch={ns.size} dtype={W.dtype} path={path}", flush=True)
+    D, P = fw.apsp_batched(torch.from_numpy(W).to(dev), ns, off[:-1], path=path)
+    torch.cuda.synchronize()
+    return D.cpu().numpy(), (P.cpu().numpy() if P is not None else None)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("path", [True, False])
+def test_batched_integer_exact(dev, dtype, path):
+    """Uneven sizes (1 .. 300, including non-multiples of the tile), tie-heavy integer
+    weights: every graph's D and P equal the oracle bit for bit."""
+    rng = np.random.default_rng(5)
+    sizes = [1, 2, 5, 17, 63, 64, 65, 100, 128, 129, 200, 300] + list(rng.integers(1, 260, 28))
+    graphs = [workloads.int_graph(n=int(n), p=float(rng.uniform(0.02, 0.5)), wmax=3, seed=300 + i)
+              for i, n in enumerate(sizes)]
+    ns, off, W = ragged(graphs, dtype)
+    D, P = run_batched(ns, off, W, dev, path=path, case="integer")
+    for b, g in enumerate(graphs):
+        n = g.shape[0]
+        Do, Po = oracle.fw(g)
+        np.testing.assert_array_equal(D[off[b]:off[b + 1]].reshape(n, n).astype(np.float64), Do)
+        if path:
+            np.testing.assert_array_equal(P[off[b]:off[b + 1]].reshape(n, n), Po)
+
+
+def test_batched_equals_single_graph(dev):
+    import torch
+    import paper_2105_07298_amd as fw
+    rng = np.random.default_rng(6)
+    graphs = [workloads.int_graph(n=int(n), p=0.2, wmax=20, seed=400 + i)
+              for i, n in enumerate(rng.integers(16, 400, 12))]
+    ns, off, W = ragged(graphs, np.float32)
+    D, P = run_batched(ns, off, W, dev, case="vs-single")
+    for b, g in enumerate(graphs):
+        n = g.shape[0]
+        Ds, Ps = fw.apsp(torch.from_numpy(g).to(dev))
+        np.testing.assert_array_equal(D[off[b]:off[b + 1]].reshape(n, n), Ds.cpu().numpy())
+        np.testing.assert_array_equal(P[off[b]:off[b + 1]].reshape(n, n), Ps.cpu().numpy())
+
+
+def test_batched_gaps_and_order(dev):
+    """Graphs at arbitrary (unaligned, non-contiguous) offsets; bytes between graphs untouched."""
+    rng = np.random.default_rng(7)
+    graphs = [workloads.int_graph(n=int(n), p=0.3, wmax=9, seed=500 + i)
+              for i, n in enumerate([70, 3, 129, 1, 40])]
+    ns = np.array([g.shape[0] for g in graphs], dtype=np.int32)
+    gaps = [5, 1, 3, 7, 2]
+    offs, pos = [], 0
+    for g, gap in zip(graphs, gaps):
+        pos += gap
+        offs.append(pos)
+        pos += g.size
+    W = np.full(pos + 3, -7.0, dtype=np.float32)
+    for g, o in zip(graphs, offs):
+        W[o:o + g.size] = g.ravel()
+    offs = np.array(offs + [pos], dtype=np.int64)
+    D, P = run_batched(ns, offs, W, dev, case="gaps")
+    mask = np.ones(W.size, dtype=bool)
+    for b, g in enumerate(graphs):
+        n = g.shape[0]
+        o = offs[b]
+        mask[o:o + g.size] = False
+        Do, Po = oracle.fw(g)
+        np.testing.assert_array_equal(D[o:o + g.size].reshape(n, n).astype(np.float64), Do)
+        np.testing.assert_array_equal(P[o:o + g.size].reshape(n, n), Po)
+    assert np.all(D[mask] == -7.0)
+
+
+def test_batched_c4_full(dev):
+    """The benchmark batch: 10,000 graphs, n uniform in [16, 512], density uniform in
+    [0.1, 1.0), weights uniform real in [1, 10] (float32), path matrices.  Every graph
+    within 1e-5 relative of the float64 oracle; path matrices encode paths summing
+    to D on sampled pairs."""
+    ns, off, W = workloads.batch_graphs(batch=10000, seed=4)
+    D, P = run_batched(ns, off, W, dev, case="C4")
+    print("[cpu] oracle on 10,000 graphs", flush=True)
+    worst = 0.0
+    rng = np.random.default_rng(8)
+    for b in range(ns.size):
+        n = int(ns[b])
+        Wg = W[off[b]:off[b + 1]].reshape(n, n)
+        Dg = D[off[b]:off[b + 1]].reshape(n, n)
+        Do, _ = oracle.fw(Wg, exact=False)
+        fin = np.isfinite(Do)
+        assert np.array_equal(np.isfinite(Dg), fin), b
+        nz = fin & (Do > 0)
+        worst = max(worst, float(np.max(np.abs(Dg[nz] - Do[nz]) / Do[nz])) if nz.any() else 0.0)
+        if b % 500 == 0:
+            Pg = P[off[b]:off[b + 1]].reshape(n, n)
+            oracle.check_invariants(Wg, Dg, Pg, exact=False, rtol=1e-6, nsample=200, seed=b)
+    print(f"max relative error over the batch {worst:.3e}", flush=True)
+    assert worst <= 1e-5
+
+
+def test_batched_rejects_bad_arguments(dev):
+    import paper_2105_07298_amd as fw
+    L = fw.lib()
+    ns = np.array([4, 0], dtype=np.int32)
+    offs = np.array([0, 16], dtype=np.int64)
+    st = L.fw_apsp_batched(0, 2, ns.ctypes.data, offs.ctypes.data, 4096, None, None)
+    assert st == fw.FW_EINVAL
+    ns = np.array([4097], dtype=np.int32)
+    st = L.fw_apsp_batched(0, 1, ns.ctypes.data, offs.ctypes.data, 4096, None, None)
+    assert st == fw.FW_EINVAL
