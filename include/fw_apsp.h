@@ -94,11 +94,14 @@ fw_status_t fw_apsp_batched(fw_dtype_t dt, int32_t batch, const int32_t *n_host,
  * on the path P encodes for (i, j), else 0 (the subgradient along that path at
  * ties).  Hence grad_w[u][v] = sum of grad_dist[i][j] over the pairs whose path
  * uses u->v, computed per source i as subtree sums over its shortest-path tree.
- *   n, batch   batch >= 1 graphs of n vertices each, contiguous with stride n*n.
+ *   n, batch   1 <= batch <= 65535 graphs of 1 <= n <= 4096 vertices each,
+ *              contiguous with stride n*n.
  *   dist, path forward outputs (device); path must not be NULL.
  *   grad_dist  device, dL/dD (same layout/type as dist).
  *   grad_w     device, output dL/dW (same layout/type), overwritten.
- * Diagonal and unused edges get 0.  Requires positive off-diagonal weights.
+ * Diagonal and unused edges get 0.  Requires positive off-diagonal weights and
+ * a path matrix produced by this library for the same dist.  Contributions
+ * are accumulated with atomics, so the last bits may vary between runs.
  */
 fw_status_t fw_apsp_backward(fw_dtype_t dt, int64_t n, int32_t batch, const void *dist,
                              const int32_t *path, const void *grad_dist, void *grad_w,

@@ -90,3 +90,71 @@ def apsp_batched(Wcat, ns, offsets, path: bool = True):
     D = Wcat.contiguous().clone()
     P = torch.empty(D.shape, dtype=torch.int32, device=D.device) if path else None
     return apsp_batched_(D, ns, offsets, P)
+
+
+def apsp_backward(D, P, G):
+    """dL/dW from forward outputs D, P ([n, n] or [B, n, n]) and G = dL/dD (same
+    shape and dtype as D), via the library's subtree-sum kernel."""
+    import torch
+    if D.shape != G.shape or D.shape != P.shape or D.dtype != G.dtype:
+        raise ValueError("D, P and G must have the same shape; D and G the same dtype")
+    if D.dim() not in (2, 3) or D.shape[-1] != D.shape[-2]:
+        raise ValueError("expected [n, n] or [B, n, n]")
+    Dc, Pc, Gc = D.contiguous(), P.contiguous(), G.contiguous()
+    gW = torch.empty_like(Dc)
+    n = D.shape[-1]
+    batch = 1 if D.dim() == 2 else D.shape[0]
+    fw_apsp_backward(_dtype_code(Dc), n, batch, Dc.data_ptr(), Pc.data_ptr(), Gc.data_ptr(), gW.data_ptr(),
+                     _stream_ptr(D.device))
+    return gW
+
+
+def _forward(W):
+    import numpy as np
+    import torch
+    if W.dim() == 2:
+        return apsp(W, path=True)
+    B, n = W.shape[0], W.shape[-1]
+    offs = np.arange(B, dtype=np.int64) * n * n
+    ns = np.full(B, n, dtype=np.int32)
+    Dc, Pc = apsp_batched(W.contiguous().reshape(-1), ns, offs, path=True)
+    return Dc.view(B, n, n), Pc.view(B, n, n)
+
+
+def _make_function():
+    import torch
+
+    class APSP(torch.autograd.Function):
+        """D = APSP(W) for W of shape [n, n] or [B, n, n] (float32/float64, device).
+
+        Forward: fw_apsp (or fw_apsp_batched for a batch), saving D and the path
+        matrix P (n^2 each; no per-k record).  Backward: fw_apsp_backward, the
+        subgradient along the shortest paths P encodes.
+        """
+
+        @staticmethod
+        def forward(ctx, W):
+            D, P = _forward(W.detach())
+            ctx.save_for_backward(D, P)
+            ctx.mark_non_differentiable(P)
+            return D, P
+
+        @staticmethod
+        def backward(ctx, gD, gP):
+            D, P = ctx.saved_tensors
+            if gD is None:
+                return None
+            return apsp_backward(D, P, gD)
+
+    return APSP
+
+
+_APSP = None
+
+
+def apsp_autograd(W):
+    """(D, P) = APSP(W) with autograd support for D (P carries no gradient)."""
+    global _APSP
+    if _APSP is None:
+        _APSP = _make_function()
+    return _APSP.apply(W)

@@ -9,13 +9,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfwapsp.so")
 
-SOURCES = ["fw_kernels.hip", "fw_batched.hip", "fw_runtime.cpp"]
+SOURCES = ["fw_kernels.hip", "fw_batched.hip", "fw_backward.hip", "fw_runtime.cpp"]
 
 # Packed FP32 instructions are kept out of the generated code (the feature is
 # disabled, not merely avoided): two scalar adds plus one 3-way min per pair of
 # updates is the schedule the kernels are written for.
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall", "-munsafe-fp-atomics",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 

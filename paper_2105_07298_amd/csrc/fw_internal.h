@@ -37,6 +37,11 @@ hipError_t launch_batched(T *dist, int32_t *path, int64_t *jobs, int njobs, int 
 template <typename T>
 int batched_occupancy(int block, bool path);
 
+// Gradient dL/dW (zeroed here) from (D, P) and G = dL/dD for batch graphs of n
+// vertices each (contiguous, stride n*n), n <= 4096.
+template <typename T>
+hipError_t launch_backward(const T *D, const int32_t *P, const T *G, T *gW, int n, int batch, hipStream_t s);
+
 // Fill n int32 with v.
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 

@@ -53,6 +53,7 @@ hipEvent_t take_event() {
 
 constexpr int64_t kMaxN = int64_t(1) << 20;
 constexpr int32_t kMaxBatchedN = 4096;
+constexpr int32_t kMaxBackwardN = 4096;
 
 // Pinned staging for the batched job table.
 std::mutex g_stage_mu;
@@ -223,9 +224,21 @@ fw_status_t fw_apsp_batched(fw_dtype_t dt, int32_t batch, const int32_t *n_host,
 
 fw_status_t fw_apsp_backward(fw_dtype_t dt, int64_t n, int32_t batch, const void *dist, const int32_t *path,
                              const void *grad_dist, void *grad_w, void *stream) {
-    (void)dt; (void)n; (void)batch; (void)dist; (void)path; (void)grad_dist; (void)grad_w; (void)stream;
     g_err[0] = 0;
-    return fail(FW_EUNSUPPORTED, "fw_apsp_backward is not built yet");
+    if (dt != FW_F32 && dt != FW_F64) return fail(FW_EINVAL, "unknown dtype %d", (int)dt);
+    if (n < 1 || n > kMaxBackwardN) return fail(FW_EINVAL, "n = %lld outside [1, %d]", (long long)n, kMaxBackwardN);
+    if (batch < 1 || batch > 65535) return fail(FW_EINVAL, "batch = %d outside [1, 65535]", batch);
+    if (!dist || !path || !grad_dist || !grad_w) return fail(FW_EINVAL, "NULL argument (path is required)");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    e = dt == FW_F32 ? fw::launch_backward<float>((const float *)dist, path, (const float *)grad_dist,
+                                                  (float *)grad_w, (int)n, batch, s)
+                     : fw::launch_backward<double>((const double *)dist, path, (const double *)grad_dist,
+                                                   (double *)grad_w, (int)n, batch, s);
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
+    return FW_OK;
 }
 
 const char *fw_status_string(int st) {

@@ -92,3 +92,11 @@ def test_batched_argument_errors_before_device(fw):
     offs2 = np.array([-1], dtype=np.int64)
     ns2 = np.array([3], dtype=np.int32)
     assert L.fw_apsp_batched(0, 1, ns2.ctypes.data, offs2.ctypes.data, 4096, None, None) == fw.FW_EINVAL
+
+
+def test_backward_argument_errors_before_device(fw):
+    L = fw.lib()
+    assert L.fw_apsp_backward(0, 5000, 1, 4096, 4096, 4096, 4096, None) == fw.FW_EINVAL
+    assert L.fw_apsp_backward(0, 16, 1, 4096, None, 4096, 4096, None) == fw.FW_EINVAL
+    assert L.fw_apsp_backward(0, 16, 0, 4096, 4096, 4096, 4096, None) == fw.FW_EINVAL
+    assert L.fw_apsp_backward(3, 16, 1, 4096, 4096, 4096, 4096, None) == fw.FW_EINVAL
