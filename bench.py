@@ -41,7 +41,6 @@ METRIC = "APSP GFLOPS=2n³/t at n=16384 FP32/FP64; batched graphs/s; fwd+bwd vs 
 # (v_add_f64 + v_min_f64).
 LANE_INSTR_PER_S = 256 * 64 * 2.4e9
 PEAK_TFLOPS = {"f32": LANE_INSTR_PER_S / 1.5 * 2 / 1e12, "f64": LANE_INSTR_PER_S / 2.0 * 2 / 1e12}
-CONFIG = {"f32": (64, 128), "f64": (64, 64)}  # (block, tile) used by the library by default
 KERNEL_SRC = os.path.join(ROOT, "paper_2105_07298_amd", "csrc", "fw_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
@@ -60,7 +59,7 @@ def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False):
     import numpy as np
     import workloads
     npdt = np.float32 if dtype == "f32" else np.float64
-    block, tile = CONFIG[dtype]
+    block, tile = fw.fw_query_config(fw.FW_F32 if dtype == "f32" else fw.FW_F64, n, path)  # tuned choice
     Wd = torch.from_numpy(workloads.unit_complete(n, dtype=npdt, seed=2)).cuda()
     D = torch.empty_like(Wd)
     P = torch.empty((n, n), dtype=torch.int32, device=Wd.device) if path else None
@@ -91,6 +90,76 @@ def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False):
     del Wd, D, P
     torch.cuda.empty_cache()
     return sec, stats
+
+
+def time_batched(fw, torch, steps=3, warmup=1):
+    """The batched workload: 10,000 graphs, n uniform in [16, 512], density uniform in
+    [0.1, 1.0), float32 weights in [1, 10], path matrices, one persistent launch."""
+    import numpy as np
+    import workloads
+    ns, off, W = workloads.batch_graphs(batch=10000, seed=4)
+    Wd = torch.from_numpy(W).cuda()
+    D = torch.empty_like(Wd)
+    P = torch.empty(Wd.shape, dtype=torch.int32, device=Wd.device)
+    offs = off[:-1].copy()
+
+    def step():
+        D.copy_(Wd)
+        fw.apsp_batched_(D, ns, offs, P)
+
+    for _ in range(warmup):
+        step()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    sec = t0.elapsed_time(t1) / 1e3 / steps
+    flops = 2.0 * float(np.sum(ns.astype(np.float64) ** 3))
+    return {"graphs_per_s": round(ns.size / sec, 1), "ms_per_batch": round(sec * 1e3, 3),
+            "gflops": round(flops / sec / 1e9, 2), "batch": int(ns.size), "n_range": [16, 512]}
+
+
+def time_fwd_bwd(fw, torch, steps=5, warmup=2):
+    """Forward (D and P) and forward + backward (dL/dW for G ~ N(0,1)): n = 2048 complete
+    graph with float32 weights in [1, 2), and a batch of 256 such graphs at n = 128."""
+    import numpy as np
+    import workloads
+
+    def measure(W, G):
+        Wd = torch.from_numpy(W).cuda()
+        Gd = torch.from_numpy(G).cuda()
+
+        def fwd():
+            return fw._forward(Wd)
+
+        def fwd_bwd():
+            D, P = fw._forward(Wd)
+            return fw.apsp_backward(D, P, Gd)
+
+        res = {}
+        for name, fn in (("fwd", fwd), ("fwd_bwd", fwd_bwd)):
+            for _ in range(warmup):
+                fn()
+            t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t0.record()
+            for _ in range(steps):
+                fn()
+            t1.record()
+            torch.cuda.synchronize()
+            res[name + "_ms"] = round(t0.elapsed_time(t1) / steps, 3)
+        res["ratio"] = round(res["fwd_bwd_ms"] / res["fwd_ms"], 3)
+        return res
+
+    W, G = workloads.grad_graph(n=2048, seed=5)
+    single = measure(W, G)
+    Ws = np.stack([workloads.grad_graph(n=128, seed=5, g=b)[0] for b in range(256)])
+    Gs = np.stack([workloads.grad_graph(n=128, seed=5, g=b)[1] for b in range(256)])
+    batch = measure(Ws, Gs)
+    return {"n2048": single, "batch256_n128": batch}
 
 
 def roofline(n, dtype, stats):
@@ -200,6 +269,10 @@ def main():
             key = f"{dt_}_{'path' if pth else 'dist'}"
             sec_out[key] = {"gflops": round(gflops(args.n, s), 2), "ms_per_step": round(s * 1e3, 2),
                             "roofline_frac": roofline(args.n, dt_, st)["frac"]}
+        print("[bench] secondary batched 10,000 graphs", file=sys.stderr, flush=True)
+        sec_out["batched"] = time_batched(fw, torch)
+        print("[bench] secondary forward + backward", file=sys.stderr, flush=True)
+        sec_out["fwd_bwd"] = time_fwd_bwd(fw, torch)
         out["secondary"] = sec_out
     out["paper_context"] = {"note": "best measured GFLOPS over N in {4096..65536}, other hardware",
                             "f32": {"Xeon Phi KNL 7230": 1037, "Titan X (Pascal)": 972},

@@ -65,8 +65,9 @@ fw_status_t fw_apsp(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, void *s
  * Tile configuration of fw_apsp, for tuning and for the tests that show results
  * do not depend on it.  block = round depth (the paper's TB) in {32, 64};
  * tile = edge of the square output tile one workgroup updates in the last phase,
- * in {64, 128} and a multiple of block.  Fields set to 0 keep the library's
- * choice; reserved fields must be 0.
+ * in {64, 128} and a multiple of block.  Fields set to 0 keep the tuned choice
+ * (a table of timings on gfx950 per element type, path mode and size range);
+ * reserved fields must be 0.
  */
 typedef struct { int32_t block; int32_t tile; int32_t reserved0; int32_t reserved1; } fw_config_t;
 
@@ -74,6 +75,10 @@ typedef struct { int32_t block; int32_t tile; int32_t reserved0; int32_t reserve
  * FW_EUNSUPPORTED if the combination is not compiled in. */
 fw_status_t fw_apsp_config(fw_dtype_t dt, int64_t n, void *dist, int32_t *path,
                            const fw_config_t *cfg, void *stream);
+
+/* The configuration fw_apsp uses for (dt, n, path != 0) -- the tuned table's
+ * entry -- written to *out (reserved fields 0).  Host only; launches nothing. */
+fw_status_t fw_query_config(fw_dtype_t dt, int64_t n, int32_t path, fw_config_t *out);
 
 /*
  * Many independent graphs of uneven size in one persistent launch.
@@ -87,6 +92,20 @@ fw_status_t fw_apsp_config(fw_dtype_t dt, int64_t n, void *dist, int32_t *path,
  */
 fw_status_t fw_apsp_batched(fw_dtype_t dt, int32_t batch, const int32_t *n_host,
                             const int64_t *off_host, void *dist, int32_t *path, void *stream);
+
+/*
+ * Tile choice of fw_apsp_batched, for tuning and for the tests that show results
+ * do not depend on it: a graph is processed in 64 x 64 tiles when
+ * n > small_max_n and 64-tiles pad it to no more vertices than 32-tiles would
+ * (n mod 64 = 0 or > 32), otherwise in 32 x 32 tiles.  small_max_n = -1 keeps
+ * the tuned choice; reserved fields must be 0.
+ */
+typedef struct { int32_t small_max_n; int32_t reserved0; int32_t reserved1; int32_t reserved2; } fw_batched_config_t;
+
+/* fw_apsp_batched with an explicit tile choice (cfg may be NULL = tuned choice). */
+fw_status_t fw_apsp_batched_config(fw_dtype_t dt, int32_t batch, const int32_t *n_host,
+                                   const int64_t *off_host, void *dist, int32_t *path,
+                                   const fw_batched_config_t *cfg, void *stream);
 
 /*
  * Gradient of a loss L(D) with respect to the weights W, given the forward

@@ -9,8 +9,8 @@ PyTorch provides device memory and streams only; no step of the method runs in i
 from __future__ import annotations
 
 from ._lib import (FW_EHIP, FW_EINVAL, FW_ENOMEM, FW_EUNSUPPORTED, FW_F32, FW_F64, FW_OK,  # noqa: F401
-                   FwError, fw_apsp, fw_apsp_backward, fw_apsp_batched, fw_apsp_config, fw_last_error,
-                   fw_prof_enable, fw_prof_read, fw_status_string, fw_version, lib)
+                   FwError, fw_apsp, fw_apsp_backward, fw_apsp_batched, fw_apsp_batched_config, fw_apsp_config,
+                   fw_last_error, fw_prof_enable, fw_prof_read, fw_query_config, fw_status_string, fw_version, lib)
 
 
 def _dtype_code(t):
@@ -56,13 +56,14 @@ def apsp(W, path: bool = True, block: int = 0, tile: int = 0):
     return apsp_(D, P, block, tile)
 
 
-def apsp_batched_(Dcat, ns, offsets, Pcat=None):
+def apsp_batched_(Dcat, ns, offsets, Pcat=None, small_max_n: int = -1):
     """In-place APSP of many graphs in one persistent launch.
 
     Dcat: 1-D contiguous device tensor (float32/float64) holding every graph's
     n_b x n_b weight matrix row-major at element offset offsets[b]; overwritten
     with distances.  ns (int32) and offsets (int64) are host sequences of length
     batch.  Pcat (int32, same length as Dcat) receives the path matrices.
+    small_max_n: graphs with n <= small_max_n use 32 x 32 tiles (-1 = tuned).
     """
     import numpy as np
     import torch
@@ -79,17 +80,17 @@ def apsp_batched_(Dcat, ns, offsets, Pcat=None):
         if not (Pcat.is_cuda and Pcat.dtype == torch.int32 and Pcat.shape == Dcat.shape and Pcat.is_contiguous()):
             raise ValueError("Pcat must be a contiguous int32 device tensor shaped like Dcat")
         pp = Pcat.data_ptr()
-    fw_apsp_batched(_dtype_code(Dcat), int(ns.size), ns.ctypes.data, offs.ctypes.data, Dcat.data_ptr(), pp,
-                    _stream_ptr(Dcat.device))
+    fw_apsp_batched_config(_dtype_code(Dcat), int(ns.size), ns.ctypes.data, offs.ctypes.data, Dcat.data_ptr(), pp,
+                           small_max_n, _stream_ptr(Dcat.device))
     return Dcat, Pcat
 
 
-def apsp_batched(Wcat, ns, offsets, path: bool = True):
+def apsp_batched(Wcat, ns, offsets, path: bool = True, small_max_n: int = -1):
     """(Dcat, Pcat) for a ragged batch of weight matrices (Wcat is not modified)."""
     import torch
     D = Wcat.contiguous().clone()
     P = torch.empty(D.shape, dtype=torch.int32, device=D.device) if path else None
-    return apsp_batched_(D, ns, offsets, P)
+    return apsp_batched_(D, ns, offsets, P, small_max_n)
 
 
 def apsp_backward(D, P, G):

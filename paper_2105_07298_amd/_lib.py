@@ -14,13 +14,19 @@ LIB_PATH = os.path.join(HERE, "libfwapsp.so")
 FW_F32, FW_F64 = 0, 1
 FW_OK, FW_EINVAL, FW_ENOMEM, FW_EHIP, FW_EUNSUPPORTED = 0, -1, -2, -3, -4
 
-EXPORTS = ("fw_apsp", "fw_apsp_config", "fw_apsp_batched", "fw_apsp_backward",
+EXPORTS = ("fw_apsp", "fw_apsp_config", "fw_query_config", "fw_apsp_batched", "fw_apsp_batched_config",
+           "fw_apsp_backward",
            "fw_status_string", "fw_last_error", "fw_version", "fw_prof_enable", "fw_prof_read")
 
 
 class FwConfig(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+
+
+class FwBatchedConfig(ctypes.Structure):
+    _fields_ = [("small_max_n", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("reserved1", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
 class FwError(RuntimeError):
@@ -44,9 +50,12 @@ def lib():
     i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
     L.fw_apsp.argtypes = [ctypes.c_int, i64, vp, vp, vp]
     L.fw_apsp_config.argtypes = [ctypes.c_int, i64, vp, vp, ctypes.POINTER(FwConfig), vp]
+    L.fw_query_config.argtypes = [ctypes.c_int, i64, i32, ctypes.POINTER(FwConfig)]
+    L.fw_query_config.restype = ctypes.c_int
     L.fw_apsp_batched.argtypes = [ctypes.c_int, i32, vp, vp, vp, vp, vp]
+    L.fw_apsp_batched_config.argtypes = [ctypes.c_int, i32, vp, vp, vp, vp, ctypes.POINTER(FwBatchedConfig), vp]
     L.fw_apsp_backward.argtypes = [ctypes.c_int, i64, i32, vp, vp, vp, vp, vp]
-    for f in ("fw_apsp", "fw_apsp_config", "fw_apsp_batched", "fw_apsp_backward"):
+    for f in ("fw_apsp", "fw_apsp_config", "fw_apsp_batched", "fw_apsp_batched_config", "fw_apsp_backward"):
         getattr(L, f).restype = ctypes.c_int
     L.fw_status_string.argtypes = [ctypes.c_int]
     L.fw_status_string.restype = ctypes.c_char_p
@@ -74,9 +83,22 @@ def fw_apsp_config(dt, n, dist, path, block=0, tile=0, stream=None):
     _check(lib().fw_apsp_config(dt, n, dist, path, ctypes.byref(cfg), stream), "fw_apsp_config")
 
 
+def fw_query_config(dt: int, n: int, path: bool):
+    """(block, tile) that fw_apsp uses for this case (from the tuned table)."""
+    cfg = FwConfig(0, 0, 0, 0)
+    _check(lib().fw_query_config(dt, n, 1 if path else 0, ctypes.byref(cfg)), "fw_query_config")
+    return int(cfg.block), int(cfg.tile)
+
+
 def fw_apsp_batched(dt, batch, n_host, off_host, dist, path, stream=None):
     """n_host / off_host: host pointers (e.g. numpy .ctypes.data)."""
     _check(lib().fw_apsp_batched(dt, batch, n_host, off_host, dist, path, stream), "fw_apsp_batched")
+
+
+def fw_apsp_batched_config(dt, batch, n_host, off_host, dist, path, small_max_n=-1, stream=None):
+    cfg = FwBatchedConfig(small_max_n, 0, 0, 0)
+    _check(lib().fw_apsp_batched_config(dt, batch, n_host, off_host, dist, path, ctypes.byref(cfg), stream),
+           "fw_apsp_batched_config")
 
 
 def fw_apsp_backward(dt, n, batch, dist, path, grad_dist, grad_w, stream=None):

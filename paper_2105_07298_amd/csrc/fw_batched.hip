@@ -8,7 +8,8 @@
 // host orders the queue by decreasing n (longest job first), so the largest
 // graphs start first and the small ones fill the gaps at the end.
 //
-// Inside a workgroup a graph is processed TB x TB tile by tile through LDS: the
+// Inside a workgroup a graph is processed TB x TB tile by tile through LDS (TB =
+// 32 or 64 per graph, by size, from the tuning table): the
 // diagonal block is closed by TB sequential k-steps; panel and remaining tiles
 // are min-plus products of two LDS-resident operand tiles with the old tile
 // held in registers.  Every step applies the lexicographic label rule
@@ -211,15 +212,19 @@ __device__ void solve_graph(GraphTiles<T, TB, PATH> g, T *sa, T *sb, int32_t *sp
 }
 
 // Persistent batched kernel.  jobs[0] holds the queue counter (set to 0 by the
-// host copy that uploads the table); jobs[1 + q] = (offset, n) of queue slot q.
-template <typename T, int TB, bool PATH>
+// host copy that uploads the table); jobs[1 + 2q], jobs[2 + 2q] = offset and n
+// of queue slot q.  A graph uses 64 x 64 tiles when n > small_max_n (from the
+// tuning table) and 64-tiles pad it to no more vertices than 32-tiles would
+// (n mod 64 = 0 or > 32); otherwise 32 x 32 tiles.  Both share the LDS arrays,
+// sized for 64.
+template <typename T, bool PATH>
 __global__ void __launch_bounds__(NT) k_batched(T *__restrict__ dist, int32_t *__restrict__ path,
-                                               int64_t *__restrict__ jobs, int njobs) {
-    constexpr int ST = TB + 1;
-    __shared__ T sa[TB * ST];
-    __shared__ T sb[TB * ST];
-    __shared__ int32_t spa[PATH ? TB * ST : 1];
-    __shared__ int32_t spb[PATH ? TB * ST : 1];
+                                               int64_t *__restrict__ jobs, int njobs, int small_max_n) {
+    constexpr int ST = 64 + 1;
+    __shared__ T sa[64 * ST];
+    __shared__ T sb[64 * ST];
+    __shared__ int32_t spa[PATH ? 64 * ST : 1];
+    __shared__ int32_t spb[PATH ? 64 * ST : 1];
     __shared__ int s_job;
     unsigned long long *counter = (unsigned long long *)jobs;
     for (;;) {
@@ -230,43 +235,39 @@ __global__ void __launch_bounds__(NT) k_batched(T *__restrict__ dist, int32_t *_
         if (q >= njobs) return;
         const int64_t off = jobs[1 + 2 * q];
         const int n = (int)jobs[2 + 2 * q];
-        GraphTiles<T, TB, PATH> g{dist + off, PATH ? path + off : nullptr, n};
-        solve_graph<T, TB, PATH>(g, sa, sb, spa, spb);
+        const bool small = (n <= small_max_n) || (((n + 63) & ~63) != ((n + 31) & ~31));
+        if (small) {
+            GraphTiles<T, 32, PATH> g{dist + off, PATH ? path + off : nullptr, n};
+            solve_graph<T, 32, PATH>(g, sa, sb, spa, spb);
+        } else {
+            GraphTiles<T, 64, PATH> g{dist + off, PATH ? path + off : nullptr, n};
+            solve_graph<T, 64, PATH>(g, sa, sb, spa, spb);
+        }
     }
 }
 
 }  // namespace
 
 template <typename T>
-hipError_t launch_batched(T *dist, int32_t *path, int64_t *jobs, int njobs, int block, int grid, hipStream_t s) {
-    const bool p = path != nullptr;
-    if (block == 64) {
-        if (p) hipLaunchKernelGGL((k_batched<T, 64, true>), dim3(grid), dim3(NT), 0, s, dist, path, jobs, njobs);
-        else hipLaunchKernelGGL((k_batched<T, 64, false>), dim3(grid), dim3(NT), 0, s, dist, path, jobs, njobs);
-    } else if (block == 32) {
-        if (p) hipLaunchKernelGGL((k_batched<T, 32, true>), dim3(grid), dim3(NT), 0, s, dist, path, jobs, njobs);
-        else hipLaunchKernelGGL((k_batched<T, 32, false>), dim3(grid), dim3(NT), 0, s, dist, path, jobs, njobs);
-    } else {
-        return hipErrorInvalidValue;
-    }
+hipError_t launch_batched(T *dist, int32_t *path, int64_t *jobs, int njobs, int small_max_n, int grid,
+                          hipStream_t s) {
+    if (path)
+        hipLaunchKernelGGL((k_batched<T, true>), dim3(grid), dim3(NT), 0, s, dist, path, jobs, njobs, small_max_n);
+    else
+        hipLaunchKernelGGL((k_batched<T, false>), dim3(grid), dim3(NT), 0, s, dist, path, jobs, njobs, small_max_n);
     return hipGetLastError();
 }
 
 template <typename T>
-int batched_occupancy(int block, bool path) {
+int batched_occupancy(bool path) {
     int nb = 0;
-    hipError_t e;
-    if (block == 64)
-        e = path ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batched<T, 64, true>, NT, 0)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batched<T, 64, false>, NT, 0);
-    else
-        e = path ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batched<T, 32, true>, NT, 0)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batched<T, 32, false>, NT, 0);
+    hipError_t e = path ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batched<T, true>, NT, 0)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batched<T, false>, NT, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
-template int batched_occupancy<float>(int, bool);
-template int batched_occupancy<double>(int, bool);
+template int batched_occupancy<float>(bool);
+template int batched_occupancy<double>(bool);
 template hipError_t launch_batched<float>(float *, int32_t *, int64_t *, int, int, int, hipStream_t);
 template hipError_t launch_batched<double>(double *, int32_t *, int64_t *, int, int, int, hipStream_t);
 

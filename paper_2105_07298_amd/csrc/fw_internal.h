@@ -29,13 +29,21 @@ hipError_t launch_resolve(const T *D, T *DT, int32_t *P0, int32_t *P, int64_t ld
 
 // Persistent batched launch (one workgroup per graph at a time).  jobs is a
 // device table of 1 + 2*njobs int64: [0] the queue counter (must be 0), then
-// (element offset, n) per queue slot in processing order.  block = tile edge.
+// (element offset, n) per queue slot in processing order.  Graphs with
+// n <= small_max_n, or that 64-tiles would pad further than 32-tiles, use
+// 32 x 32 tiles; the others 64 x 64.
 template <typename T>
-hipError_t launch_batched(T *dist, int32_t *path, int64_t *jobs, int njobs, int block, int grid, hipStream_t s);
+hipError_t launch_batched(T *dist, int32_t *path, int64_t *jobs, int njobs, int small_max_n, int grid,
+                          hipStream_t s);
 
 // Workgroups of the batched kernel that fit on one CU at once.
 template <typename T>
-int batched_occupancy(int block, bool path);
+int batched_occupancy(bool path);
+
+// Tuning table lookup (tune_table.inc): tile configuration for fw_apsp and the
+// small-graph split of fw_apsp_batched.
+TileCfg tuned_config(bool f64, bool path, int64_t n);
+int tuned_batched_small_max_n(bool f64, bool path);
 
 // Gradient dL/dW (zeroed here) from (D, P) and G = dL/dD for batch graphs of n
 // vertices each (contiguous, stride n*n), n <= 4096.

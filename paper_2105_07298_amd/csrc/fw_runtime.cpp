@@ -61,10 +61,11 @@ void *g_stage = nullptr;
 size_t g_stage_cap = 0;
 hipEvent_t g_stage_ev = nullptr;
 
-fw::TileCfg default_cfg(fw_dtype_t dt, int64_t n) {
-    if (dt == FW_F64) return {64, 64};
-    return n >= 512 ? fw::TileCfg{64, 128} : fw::TileCfg{64, 64};
-}
+struct TuneEntry { int f64, path; long long n_lo, n_hi; int block, tile; };
+struct TuneBatchedEntry { int f64, path, small_max_n; };
+#include "tune_table.inc"
+
+fw::TileCfg default_cfg(fw_dtype_t dt, int64_t n, bool path) { return fw::tuned_config(dt == FW_F64, path, n); }
 
 template <typename T>
 fw_status_t run_apsp(int64_t n, T *dist, int32_t *path, fw::TileCfg cfg, hipStream_t s) {
@@ -118,6 +119,17 @@ fw_status_t check_common(fw_dtype_t dt, int64_t n, const void *dist) {
 }  // namespace
 
 namespace fw {
+TileCfg tuned_config(bool f64, bool path, int64_t n) {
+    for (const TuneEntry &t : kTuneApsp)
+        if (t.f64 == (int)f64 && t.path == (int)path && n >= t.n_lo && n < t.n_hi) return {t.block, t.tile};
+    return {64, 64};
+}
+int tuned_batched_small_max_n(bool f64, bool path) {
+    for (const TuneBatchedEntry &t : kTuneBatched)
+        if (t.f64 == (int)f64 && t.path == (int)path) return t.small_max_n;
+    return 0;
+}
+
 void prof_begin_p4(hipStream_t s) {
     if (!g_prof_on) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -142,7 +154,7 @@ fw_status_t fw_apsp_config(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, 
     g_err[0] = 0;
     fw_status_t st = check_common(dt, n, dist);
     if (st != FW_OK) return st;
-    fw::TileCfg tc = default_cfg(dt, n);
+    fw::TileCfg tc = default_cfg(dt, n, path != nullptr);
     if (cfg) {
         if (cfg->reserved0 || cfg->reserved1) return fail(FW_EINVAL, "reserved config fields must be 0");
         if (cfg->block) tc.block = cfg->block;
@@ -157,13 +169,26 @@ fw_status_t fw_apsp_config(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, 
     return run_apsp<double>(n, (double *)dist, path, tc, s);
 }
 
+fw_status_t fw_query_config(fw_dtype_t dt, int64_t n, int32_t path, fw_config_t *out) {
+    g_err[0] = 0;
+    if (dt != FW_F32 && dt != FW_F64) return fail(FW_EINVAL, "unknown dtype %d", (int)dt);
+    if (n < 1 || n > kMaxN) return fail(FW_EINVAL, "n = %lld outside [1, %lld]", (long long)n, (long long)kMaxN);
+    if (!out) return fail(FW_EINVAL, "out is NULL");
+    const fw::TileCfg c = default_cfg(dt, n, path != 0);
+    out->block = c.block;
+    out->tile = c.tile;
+    out->reserved0 = out->reserved1 = 0;
+    return FW_OK;
+}
+
 fw_status_t fw_apsp(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, void *stream) {
     return fw_apsp_config(dt, n, dist, path, nullptr, stream);
 }
 
-fw_status_t fw_apsp_batched(fw_dtype_t dt, int32_t batch, const int32_t *n_host, const int64_t *off_host, void *dist,
-                            int32_t *path, void *stream) {
+fw_status_t fw_apsp_batched_config(fw_dtype_t dt, int32_t batch, const int32_t *n_host, const int64_t *off_host,
+                                   void *dist, int32_t *path, const fw_batched_config_t *cfg, void *stream) {
     g_err[0] = 0;
+    if (cfg && (cfg->reserved0 || cfg->reserved1 || cfg->reserved2)) return fail(FW_EINVAL, "reserved config fields must be 0");
     if (dt != FW_F32 && dt != FW_F64) return fail(FW_EINVAL, "unknown dtype %d", (int)dt);
     if (batch < 1) return fail(FW_EINVAL, "batch = %d < 1", batch);
     if (!n_host || !off_host || !dist) return fail(FW_EINVAL, "NULL argument");
@@ -176,7 +201,8 @@ fw_status_t fw_apsp_batched(fw_dtype_t dt, int32_t batch, const int32_t *n_host,
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     hipStream_t s = (hipStream_t)stream;
-    const int block = 64;
+    const int small_max_n = (cfg && cfg->small_max_n >= 0) ? cfg->small_max_n
+                                                          : fw::tuned_batched_small_max_n(dt == FW_F64, path != nullptr);
     // Queue in order of decreasing n (longest job first); counter slot first.
     std::vector<int32_t> order((size_t)batch);
     for (int32_t b = 0; b < batch; ++b) order[(size_t)b] = b;
@@ -211,15 +237,20 @@ fw_status_t fw_apsp_batched(fw_dtype_t dt, int32_t batch, const int32_t *n_host,
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
         return hip_fail(e, "CU count");
     const bool p = path != nullptr;
-    const int occ = dt == FW_F32 ? fw::batched_occupancy<float>(block, p) : fw::batched_occupancy<double>(block, p);
+    const int occ = dt == FW_F32 ? fw::batched_occupancy<float>(p) : fw::batched_occupancy<double>(p);
     int grid = cus * occ;
     if (grid > batch) grid = batch;
-    e = dt == FW_F32 ? fw::launch_batched<float>((float *)dist, path, (int64_t *)djobs, batch, block, grid, s)
-                     : fw::launch_batched<double>((double *)dist, path, (int64_t *)djobs, batch, block, grid, s);
+    e = dt == FW_F32 ? fw::launch_batched<float>((float *)dist, path, (int64_t *)djobs, batch, small_max_n, grid, s)
+                     : fw::launch_batched<double>((double *)dist, path, (int64_t *)djobs, batch, small_max_n, grid, s);
     hipError_t e2 = hipFreeAsync(djobs, s);
     if (e != hipSuccess) return hip_fail(e, "batched launch");
     if (e2 != hipSuccess) return hip_fail(e2, "job table free");
     return FW_OK;
+}
+
+fw_status_t fw_apsp_batched(fw_dtype_t dt, int32_t batch, const int32_t *n_host, const int64_t *off_host, void *dist,
+                            int32_t *path, void *stream) {
+    return fw_apsp_batched_config(dt, batch, n_host, off_host, dist, path, nullptr, stream);
 }
 
 fw_status_t fw_apsp_backward(fw_dtype_t dt, int64_t n, int32_t batch, const void *dist, const int32_t *path,

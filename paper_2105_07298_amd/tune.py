@@ -1,0 +1,157 @@
+"""Offline autotuner for the tile configurations (the paper tunes its block size by
+sweeping TB, Sect. 3.2 and 4.1; here the sweep is automated and its result is a
+table compiled into the library).
+
+Run on the GPU:  python -m paper_2105_07298_amd.tune --out DIR
+It times, with HIP events on the current stream,
+  * fw_apsp for every compiled (block, tile) at one representative n per size
+    range, for float32/float64 with and without the path matrix, on complete
+    graphs with weights uniform in (0, 1);
+  * fw_apsp_batched on batches of equal-size graphs (weights in [1, 10],
+    density 0.5) in 32 x 32 tiles and in 64 x 64 tiles, for the sizes from 16
+    to 512 that both tilings pad alike; the split point small_max_n is the
+    largest such n below the first size at which 64 x 64 tiles are faster.
+and writes DIR/tune_table.json (every timing) and DIR/tune_table.inc (the
+table the library compiles; copy it to csrc/ and rebuild).  Tuning never changes
+results: the tests check that every configuration gives the same D and P.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+CONFIGS = {"f32": [(32, 64), (64, 64), (64, 128)], "f64": [(32, 64), (64, 64)]}
+# size ranges [lo, hi) of the table and the n timed for each
+BUCKETS = [(0, 512, 256), (512, 2048, 1024), (2048, 8192, 4096), (8192, 1 << 40, 16384)]
+BATCHED_N = [16, 24, 32, 48, 64, 80, 96, 128, 160, 192, 256, 320, 384, 512]
+
+
+def _timeit(fn, torch, reps, warmup=1):
+    for _ in range(warmup):
+        fn()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(reps):
+        fn()
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / reps
+
+
+def tune_apsp(fw, torch, log):
+    import numpy as np
+    import workloads
+    table = []
+    for dt in ("f32", "f64"):
+        npdt = np.float32 if dt == "f32" else np.float64
+        for lo, hi, n in BUCKETS:
+            W = torch.from_numpy(workloads.unit_complete(n, dtype=npdt, seed=2)).cuda()
+            D = torch.empty_like(W)
+            for path in (False, True):
+                P = torch.empty((n, n), dtype=torch.int32, device=W.device) if path else None
+                best = None
+                for block, tile in CONFIGS[dt]:
+                    def run():
+                        D.copy_(W)
+                        fw.apsp_(D, P, block=block, tile=tile)
+                    reps = 2 if n >= 8192 else 5
+                    ms = _timeit(run, torch, reps)
+                    log.append({"kind": "apsp", "dtype": dt, "path": path, "n": n, "block": block, "tile": tile,
+                                "ms": round(ms, 4)})
+                    print(f"apsp {dt} path={path} n={n} block={block} tile={tile}: {ms:.3f} ms", flush=True)
+                    if best is None or ms < best[0]:
+                        best = (ms, block, tile)
+                table.append({"f64": dt == "f64", "path": path, "n_lo": lo, "n_hi": hi,
+                              "block": best[1], "tile": best[2]})
+            del W, D
+            torch.cuda.empty_cache()
+    return table
+
+
+def tune_batched(fw, torch, log):
+    """small_max_n: the largest size, among those that 32- and 64-tiles pad alike
+    (the kernel takes 32-tiles for the others anyway), below the first one at
+    which 64-tiles are faster."""
+    import numpy as np
+    import workloads
+    table = []
+    sizes = [n for n in BATCHED_N if ((n + 63) // 64) * 64 == ((n + 31) // 32) * 32]
+    for dt in ("f32", "f64"):
+        npdt = np.float32 if dt == "f32" else np.float64
+        for path in (False, True):
+            small_max_n, done = 0, False
+            for n in sizes:
+                count = int(max(64, min(4096, 2.0e9 / n ** 3 * 64)))
+                g = workloads.graph(11, n, 0.5, workloads.W_ONE_TEN, 0, npdt)
+                W = torch.from_numpy(np.tile(g.ravel(), count)).cuda()
+                ns = np.full(count, n, dtype=np.int32)
+                offs = np.arange(count, dtype=np.int64) * n * n
+                D = torch.empty_like(W)
+                P = torch.empty(W.shape, dtype=torch.int32, device=W.device) if path else None
+                res = {}
+                for split, label in ((1 << 20, 32), (0, 64)):
+                    def run():
+                        D.copy_(W)
+                        fw.apsp_batched_(D, ns, offs, P, small_max_n=split)
+                    res[label] = _timeit(run, torch, 3)
+                    log.append({"kind": "batched", "dtype": dt, "path": path, "n": n, "tile": label,
+                                "count": count, "ms": round(res[label], 4)})
+                print(f"batched {dt} path={path} n={n} x{count}: 32-tiles {res[32]:.3f} ms, "
+                      f"64-tiles {res[64]:.3f} ms", flush=True)
+                if not done and res[32] <= res[64]:
+                    small_max_n = n
+                else:
+                    done = True
+                del W, D, P
+            table.append({"f64": dt == "f64", "path": path, "small_max_n": small_max_n})
+    return table
+
+
+def write_inc(path, apsp_table, batched_table, arch):
+    lines = [
+        "// Tile configuration table.  Generated by paper_2105_07298_amd/tune.py from",
+        f"// timings on {arch} (do not edit by hand; rerun the tuner instead).",
+        "// fw_apsp:          {f64, path, n_lo, n_hi, block, tile}  for n_lo <= n < n_hi",
+        "// fw_apsp_batched:  {f64, path, small_max_n}",
+        f"// generated {time.strftime('%Y-%m-%d')}",
+        "static const TuneEntry kTuneApsp[] = {",
+    ]
+    for t in apsp_table:
+        hi = "1LL << 40" if t["n_hi"] >= (1 << 40) else str(t["n_hi"])
+        lines.append(f"    {{{int(t['f64'])}, {int(t['path'])}, {t['n_lo']}, {hi}, {t['block']}, {t['tile']}}},")
+    lines.append("};")
+    lines.append("static const TuneBatchedEntry kTuneBatched[] = {")
+    for t in batched_table:
+        lines.append(f"    {{{int(t['f64'])}, {int(t['path'])}, {t['small_max_n']}}},")
+    lines.append("};")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--skip-apsp", action="store_true")
+    args = ap.parse_args()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import torch
+    import paper_2105_07298_amd as fw
+    fw.lib()
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    os.makedirs(args.out, exist_ok=True)
+    log = []
+    apsp_table = [] if args.skip_apsp else tune_apsp(fw, torch, log)
+    batched_table = tune_batched(fw, torch, log)
+    with open(os.path.join(args.out, "tune_table.json"), "w") as f:
+        json.dump({"arch": arch, "apsp": apsp_table, "batched": batched_table, "timings": log}, f, indent=1)
+    write_inc(os.path.join(args.out, "tune_table.inc"), apsp_table, batched_table, arch)
+    print("wrote", args.out, flush=True)
+
+
+if __name__ == "__main__":
+    main()

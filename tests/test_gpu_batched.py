@@ -133,3 +133,23 @@ def test_batched_rejects_bad_arguments(dev):
     ns = np.array([4097], dtype=np.int32)
     st = L.fw_apsp_batched(0, 1, ns.ctypes.data, offs.ctypes.data, 4096, None, None)
     assert st == fw.FW_EINVAL
+
+
+@pytest.mark.parametrize("small_max_n", [0, 96, 1 << 20])
+def test_batched_tile_choice_invariance(dev, small_max_n):
+    """Whatever graphs are processed in 32 x 32 or 64 x 64 tiles, D and P are the oracle's."""
+    import torch
+    import paper_2105_07298_amd as fw
+    rng = np.random.default_rng(9)
+    graphs = [workloads.int_graph(n=int(n), p=0.1, wmax=3, seed=600 + i)
+              for i, n in enumerate(rng.integers(1, 200, 24))]
+    ns, off, W = ragged(graphs, np.float32)
+    print(f"[gpu] fw_apsp_batched_config small_max_n={small_max_n}", flush=True)
+    D, P = fw.apsp_batched(torch.from_numpy(W).to(dev), ns, off[:-1], path=True, small_max_n=small_max_n)
+    torch.cuda.synchronize()
+    D, P = D.cpu().numpy(), P.cpu().numpy()
+    for b, g in enumerate(graphs):
+        n = g.shape[0]
+        Do, Po = oracle.fw(g)
+        np.testing.assert_array_equal(D[off[b]:off[b + 1]].reshape(n, n).astype(np.float64), Do)
+        np.testing.assert_array_equal(P[off[b]:off[b + 1]].reshape(n, n), Po)

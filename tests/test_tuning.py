@@ -1,0 +1,41 @@
+"""The tuning table compiled into the library: well-formed and covering every case."""
+import os
+import re
+
+from conftest import ROOT
+
+INC = os.path.join(ROOT, "paper_2105_07298_amd", "csrc", "tune_table.inc")
+
+
+def entries():
+    text = open(INC).read()
+    apsp = re.search(r"kTuneApsp\[\] = \{(.*?)\};", text, re.S).group(1)
+    batched = re.search(r"kTuneBatched\[\] = \{(.*?)\};", text, re.S).group(1)
+    rows = []
+    for m in re.finditer(r"\{([^{}]*)\}", apsp):
+        f = [x.strip() for x in m.group(1).split(",")]
+        hi = (1 << 40) if "<<" in f[3] else int(f[3])
+        rows.append((int(f[0]), int(f[1]), int(f[2]), hi, int(f[4]), int(f[5])))
+    brows = [tuple(int(x) for x in m.group(1).split(",")) for m in re.finditer(r"\{([^{}]*)\}", batched)]
+    return rows, brows
+
+
+def test_apsp_table_covers_every_size_once():
+    rows, _ = entries()
+    supported = {0: {(32, 64), (64, 64), (64, 128)}, 1: {(32, 64), (64, 64)}}
+    for f64 in (0, 1):
+        for path in (0, 1):
+            rs = sorted((r for r in rows if r[0] == f64 and r[1] == path), key=lambda r: r[2])
+            assert rs, (f64, path)
+            assert rs[0][2] == 0 and rs[-1][3] >= (1 << 40)
+            for a, b in zip(rs[:-1], rs[1:]):
+                assert a[3] == b[2], "size ranges must tile [0, inf)"
+            for r in rs:
+                assert (r[4], r[5]) in supported[f64], r
+
+
+def test_batched_table_complete():
+    _, brows = entries()
+    keys = {(b[0], b[1]) for b in brows}
+    assert keys == {(0, 0), (0, 1), (1, 0), (1, 1)}
+    assert all(0 <= b[2] <= 4096 for b in brows)
