@@ -35,12 +35,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "APSP GFLOPS=2n³/t at n=16384 FP32/FP64; batched graphs/s; fwd+bwd vs fwd"
 
-# Vector-ALU bound of the last-phase kernel, in 2-flop updates: 256 CUs x 4 SIMD x
-# 16 lanes x 2.4 GHz = 3.93e13 lane-instructions/s; float32 spends 1.5
-# instructions per update (2 v_add_f32 + 1 v_min3_f32 per two updates), float64 2
-# (v_add_f64 + v_min_f64).
-LANE_INSTR_PER_S = 256 * 64 * 2.4e9
-PEAK_TFLOPS = {"f32": LANE_INSTR_PER_S / 1.5 * 2 / 1e12, "f64": LANE_INSTR_PER_S / 2.0 * 2 / 1e12}
+# Vector-ALU bound of the last-phase kernel, in 2-flop updates.  256 CUs x 4 SIMDs
+# at 2.4 GHz; a SIMD retires 32 lanes/clk of v_add_f32 and 16 lanes/clk of
+# v_min3_f32, v_add_f64 and v_min_f64.  float32 spends one v_add_f32 and half a
+# v_min3_f32 per update (1/32 + 0.5/16 = 1/16 SIMD-clk per lane-update), float64
+# one v_add_f64 and one v_min_f64 (1/8).  Hence 64 (float32) and 32 (float64)
+# updates per CU per clock.
+CU_CLK = 256 * 2.4e9
+PEAK_TFLOPS = {"f32": CU_CLK * 64 * 2 / 1e12, "f64": CU_CLK * 32 * 2 / 1e12}
 KERNEL_SRC = os.path.join(ROOT, "paper_2105_07298_amd", "csrc", "fw_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
@@ -59,14 +61,14 @@ def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False):
     import numpy as np
     import workloads
     npdt = np.float32 if dtype == "f32" else np.float64
-    block, tile = fw.fw_query_config(fw.FW_F32 if dtype == "f32" else fw.FW_F64, n, path)  # tuned choice
+    block, tm, tn = fw.fw_query_config(fw.FW_F32 if dtype == "f32" else fw.FW_F64, n, path)  # tuned choice
     Wd = torch.from_numpy(workloads.unit_complete(n, dtype=npdt, seed=2)).cuda()
     D = torch.empty_like(Wd)
     P = torch.empty((n, n), dtype=torch.int32, device=Wd.device) if path else None
 
     def step():
         D.copy_(Wd)
-        fw.apsp_(D, P, block=block, tile=tile)
+        fw.apsp_(D, P, block=block, tile_m=tm, tile_n=tn)
 
     for _ in range(warmup):
         step()
@@ -86,7 +88,7 @@ def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False):
     if prof:
         fw.fw_prof_enable(False)
         cnt, tot_ms = fw.fw_prof_read(reset=True)
-        stats = {"launches": cnt, "mean_ms": tot_ms / max(cnt, 1), "block": block, "tile": tile}
+        stats = {"launches": cnt, "mean_ms": tot_ms / max(cnt, 1), "block": block, "tile": [tm, tn]}
     del Wd, D, P
     torch.cuda.empty_cache()
     return sec, stats

@@ -64,12 +64,12 @@ fw_status_t fw_apsp(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, void *s
 /*
  * Tile configuration of fw_apsp, for tuning and for the tests that show results
  * do not depend on it.  block = round depth (the paper's TB) in {32, 64};
- * tile = edge of the square output tile one workgroup updates in the last phase,
- * in {64, 128} and a multiple of block.  Fields set to 0 keep the tuned choice
- * (a table of timings on gfx950 per element type, path mode and size range);
- * reserved fields must be 0.
+ * tile_m x tile_n = the output tile one workgroup updates in the last phase,
+ * each edge in {64, 128} and a multiple of block.  Fields set to 0 keep the
+ * tuned choice (a table of timings on gfx950 per element type, path mode and
+ * size range); reserved must be 0.
  */
-typedef struct { int32_t block; int32_t tile; int32_t reserved0; int32_t reserved1; } fw_config_t;
+typedef struct { int32_t block; int32_t tile_m; int32_t tile_n; int32_t reserved; } fw_config_t;
 
 /* fw_apsp with an explicit configuration (cfg may be NULL = library choice).
  * FW_EUNSUPPORTED if the combination is not compiled in. */
@@ -77,7 +77,7 @@ fw_status_t fw_apsp_config(fw_dtype_t dt, int64_t n, void *dist, int32_t *path,
                            const fw_config_t *cfg, void *stream);
 
 /* The configuration fw_apsp uses for (dt, n, path != 0) -- the tuned table's
- * entry -- written to *out (reserved fields 0).  Host only; launches nothing. */
+ * entry -- written to *out (reserved 0).  Host only; launches nothing. */
 fw_status_t fw_query_config(fw_dtype_t dt, int64_t n, int32_t path, fw_config_t *out);
 
 /*

@@ -27,12 +27,13 @@ def _stream_ptr(device):
     return torch.cuda.current_stream(device).cuda_stream
 
 
-def apsp_(D, P=None, block: int = 0, tile: int = 0):
+def apsp_(D, P=None, block: int = 0, tile_m: int = 0, tile_n: int = 0):
     """In-place APSP of the square device tensor D (float32/float64, contiguous).
 
     D holds the weight matrix (0 diagonal, +inf = no edge) and is overwritten with
     shortest distances; P (int32, same shape) receives the path matrix if given.
-    Runs on the current stream of D's device.
+    Runs on the current stream of D's device.  block / tile_m / tile_n override
+    the tuned tile configuration (0 = tuned).
     """
     import torch
     if not (D.is_cuda and D.dim() == 2 and D.shape[0] == D.shape[1] and D.is_contiguous()):
@@ -43,17 +44,17 @@ def apsp_(D, P=None, block: int = 0, tile: int = 0):
         if not (P.is_cuda and P.dtype == torch.int32 and P.shape == D.shape and P.is_contiguous()):
             raise ValueError("P must be a contiguous int32 device tensor shaped like D")
         pp = P.data_ptr()
-    fw_apsp_config(_dtype_code(D), n, D.data_ptr(), pp, block, tile, _stream_ptr(D.device))
+    fw_apsp_config(_dtype_code(D), n, D.data_ptr(), pp, block, tile_m, tile_n, _stream_ptr(D.device))
     return D, P
 
 
-def apsp(W, path: bool = True, block: int = 0, tile: int = 0):
+def apsp(W, path: bool = True, block: int = 0, tile_m: int = 0, tile_n: int = 0):
     """Return (D, P) for the weight matrix W (device tensor; W is not modified).
     P is None when path=False."""
     import torch
     D = W.contiguous().clone()
     P = torch.empty(D.shape, dtype=torch.int32, device=D.device) if path else None
-    return apsp_(D, P, block, tile)
+    return apsp_(D, P, block, tile_m, tile_n)
 
 
 def apsp_batched_(Dcat, ns, offsets, Pcat=None, small_max_n: int = -1):

@@ -20,8 +20,8 @@ EXPORTS = ("fw_apsp", "fw_apsp_config", "fw_query_config", "fw_apsp_batched", "f
 
 
 class FwConfig(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+    _fields_ = [("block", ctypes.c_int32), ("tile_m", ctypes.c_int32),
+                ("tile_n", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class FwBatchedConfig(ctypes.Structure):
@@ -78,16 +78,16 @@ def fw_apsp(dt: int, n: int, dist: int, path: int | None, stream: int | None = N
     _check(lib().fw_apsp(dt, n, dist, path, stream), "fw_apsp")
 
 
-def fw_apsp_config(dt, n, dist, path, block=0, tile=0, stream=None):
-    cfg = FwConfig(block, tile, 0, 0)
+def fw_apsp_config(dt, n, dist, path, block=0, tile_m=0, tile_n=0, stream=None):
+    cfg = FwConfig(block, tile_m, tile_n, 0)
     _check(lib().fw_apsp_config(dt, n, dist, path, ctypes.byref(cfg), stream), "fw_apsp_config")
 
 
 def fw_query_config(dt: int, n: int, path: bool):
-    """(block, tile) that fw_apsp uses for this case (from the tuned table)."""
+    """(block, tile_m, tile_n) that fw_apsp uses for this case (from the tuned table)."""
     cfg = FwConfig(0, 0, 0, 0)
     _check(lib().fw_query_config(dt, n, 1 if path else 0, ctypes.byref(cfg)), "fw_query_config")
-    return int(cfg.block), int(cfg.tile)
+    return int(cfg.block), int(cfg.tile_m), int(cfg.tile_n)
 
 
 def fw_apsp_batched(dt, batch, n_host, off_host, dist, path, stream=None):

@@ -5,27 +5,30 @@
 
 namespace fw {
 
-// Compiled round depths (the paper's TB) and last-phase tile edges.
+// Round depth (the paper's TB) and last-phase output tile (rows x columns, each
+// a multiple of the block).
 struct TileCfg {
-    int block;  // round depth TB
-    int tile;   // last-phase output tile edge (multiple of block)
+    int block;
+    int tile_m;
+    int tile_n;
 };
 
 // One round of the blocked method, enqueued on `s`.  D, P are the padded
-// matrices (leading dimension ld, a multiple of cfg.tile); P may be null.
+// matrices (leading dimension ld, a multiple of both tile edges); P may be null
+// (distances only).  L (path mode) marks entries whose label is pending from a
+// round of the last phase (r + 1; 0 = current), zero-initialised.
 // Returns hipSuccess or the launch error.
 template <typename T>
-hipError_t launch_round(T *D, int32_t *P, int64_t ld, int r, TileCfg cfg, hipStream_t s);
+hipError_t launch_round(T *D, int32_t *P, uint16_t *L, int64_t ld, int r, TileCfg cfg, hipStream_t s);
 
-// Supported (block, tile) pairs for element type T.
+// Compiled (block, tile_m, tile_n) combinations for element type T.
 template <typename T>
 bool config_supported(TileCfg cfg);
 
 // Path mode, after the last round: resolve the labels the last phase left
-// pending.  DT (ld*ld elements) and P0 (ld*ld int32) are scratch: the transpose
-// of D and a snapshot of P.
+// pending (marked in L).  DT (ld*ld elements) is scratch for the transpose of D.
 template <typename T>
-hipError_t launch_resolve(const T *D, T *DT, int32_t *P0, int32_t *P, int64_t ld, int block, hipStream_t s);
+hipError_t launch_resolve(const T *D, T *DT, const uint16_t *L, int32_t *P, int64_t ld, int block, hipStream_t s);
 
 // Persistent batched launch (one workgroup per graph at a time).  jobs is a
 // device table of 1 + 2*njobs int64: [0] the queue counter (must be 0), then

@@ -15,12 +15,14 @@
 // classic loop with a strict test stores (the smallest possible largest interior
 // vertex over all shortest paths).  Phases 1-3 apply that rule directly.  The
 // last phase defers it: an entry that strictly improves in round r is only
-// marked "pending from round r" (P = -2 - r), and k_resolve computes all pending
-// labels in one pass after the last round (see there for why the final
-// distances suffice).  Pending values are negative, and every label they stand
-// for is below the first vertex of any later round, so phases 1-3 of later
-// rounds treat them exactly as they would treat the true label: it never wins a
-// max() against k and never makes a tie win.
+// marked "pending from round r" in a separate array L (L = r + 1; 0 means the
+// label in P is current), and k_resolve computes all pending labels in one pass
+// after the last round (see there for why the final distances suffice).  While
+// an entry is pending, P still holds an older label; every label set before
+// round r is below the round's first vertex k0, and so is the pending one, so
+// phases 1-3 of later rounds treat the stale value exactly as they would treat
+// the true label: it never wins a max() against k and never makes a tie win.
+// Phases 1-3 clear L for every entry whose (length, label) they change.
 //
 // All arithmetic is on the vector ALU: the min-plus product is not a ring
 // contraction, so matrix cores do not apply.
@@ -66,7 +68,8 @@ __device__ __forceinline__ void lex_take(T &d, int32_t &p, T s, int32_t m) {
 // smaller), hence updating in place while other threads read them is safe; one
 // barrier per k orders step k's writes before step k+1's reads.
 template <typename T, int TB, bool PATH>
-__global__ void __launch_bounds__(NT) k_phase1(T *__restrict__ D, int32_t *__restrict__ P, int64_t ld, int r) {
+__global__ void __launch_bounds__(NT) k_phase1(T *__restrict__ D, int32_t *__restrict__ P, uint16_t *__restrict__ L,
+                                              int64_t ld, int r) {
     constexpr int TS = 16, RM = TB / TS, ST = TB + 1;
     __shared__ T sd[TB * ST];
     __shared__ int32_t sp[PATH ? TB * ST : 1];
@@ -74,6 +77,7 @@ __global__ void __launch_bounds__(NT) k_phase1(T *__restrict__ D, int32_t *__res
     const int64_t k0 = (int64_t)r * TB;
     T d[RM][RM];
     int32_t p[RM][RM];
+    bool changed[RM][RM];
 #pragma unroll
     for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
@@ -82,6 +86,7 @@ __global__ void __launch_bounds__(NT) k_phase1(T *__restrict__ D, int32_t *__res
             const int64_t g = (k0 + row) * ld + k0 + col;
             d[ii][jj] = D[g];
             sd[row * ST + col] = d[ii][jj];
+            changed[ii][jj] = false;
             if (PATH) {
                 p[ii][jj] = P[g];
                 sp[row * ST + col] = p[ii][jj];
@@ -115,10 +120,12 @@ __global__ void __launch_bounds__(NT) k_phase1(T *__restrict__ D, int32_t *__res
                         p[ii][jj] = m;
                         sd[idx] = s;
                         sp[idx] = m;
+                        changed[ii][jj] = true;
                     }
                 } else if (s < d[ii][jj]) {
                     d[ii][jj] = s;
                     sd[idx] = s;
+                    changed[ii][jj] = true;
                 }
             }
         __syncthreads();
@@ -127,9 +134,13 @@ __global__ void __launch_bounds__(NT) k_phase1(T *__restrict__ D, int32_t *__res
     for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
         for (int jj = 0; jj < RM; ++jj) {
+            if (!changed[ii][jj]) continue;
             const int64_t g = (k0 + ty + TS * ii) * ld + k0 + tx + TS * jj;
             D[g] = d[ii][jj];
-            if (PATH) P[g] = p[ii][jj];
+            if (PATH) {
+                P[g] = p[ii][jj];
+                L[g] = 0;
+            }
         }
 }
 
@@ -145,7 +156,8 @@ __global__ void __launch_bounds__(NT) k_phase1(T *__restrict__ D, int32_t *__res
 // read completely (operands into LDS, old values into registers) before it is
 // written, and only its own workgroup touches it.
 template <typename T, int TB, bool PATH>
-__global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__restrict__ P, int64_t ld, int r, int nb) {
+__global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__restrict__ P, uint16_t *__restrict__ L,
+                                               int64_t ld, int r, int nb) {
     constexpr int TS = 16, RM = TB / TS, ST = TB + 1;
     __shared__ T sa[TB * ST];
     __shared__ T sb[TB * ST];
@@ -170,15 +182,15 @@ __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__re
         }
     }
     const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
-    T d[RM][RM];
-    int32_t p[RM][RM];
+    T d[RM][RM], d0[RM][RM];
+    int32_t p[RM][RM], p0[RM][RM];
 #pragma unroll
     for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
         for (int jj = 0; jj < RM; ++jj) {
             const int64_t g = (I0 + ty + TS * ii) * ld + J0 + tx + TS * jj;
-            d[ii][jj] = D[g];
-            if (PATH) p[ii][jj] = P[g];
+            d[ii][jj] = d0[ii][jj] = D[g];
+            if (PATH) p[ii][jj] = p0[ii][jj] = P[g];
         }
     __syncthreads();
     for (int k = 0; k < TB; ++k) {
@@ -210,9 +222,13 @@ __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__re
     for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
         for (int jj = 0; jj < RM; ++jj) {
+            if (d[ii][jj] == d0[ii][jj] && (!PATH || p[ii][jj] == p0[ii][jj])) continue;
             const int64_t g = (I0 + ty + TS * ii) * ld + J0 + tx + TS * jj;
             D[g] = d[ii][jj];
-            if (PATH) P[g] = p[ii][jj];
+            if (PATH) {
+                P[g] = p[ii][jj];
+                L[g] = 0;
+            }
         }
 }
 
@@ -244,10 +260,13 @@ __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__re
 // candidate through block r has a label of at least k0.  So a candidate that
 // merely ties the old length never changes the label, and an entry that strictly
 // improves gets a label decided entirely by this round's candidates: it is
-// marked pending (P = -2 - r) and resolved by k_resolve.
-template <typename T, int TB, int BM, int BN, int RM, int RN, bool PATH>
-__global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, int32_t *__restrict__ P, int64_t ld, int r,
-                                              int gm, int gn, int skip, int per_xcd, int ntiles) {
+// marked pending (L = r + 1) and resolved by k_resolve.  L is read with the old
+// tile and written back per 16-byte vector of D that changed, so its stores
+// cover whole 8-byte (float) or 4-byte (double) runs.
+template <typename T, int TB, int BM, int BN, bool PATH>
+__global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__restrict__ L, int64_t ld, int r,
+                                              int gm, int gn, int skip_i, int skip_j, int per_xcd, int ntiles) {
+    constexpr int RM = BM / 16, RN = BN / 16;  // 16 x 16 threads
     using vec = typename V16<T>::type;
     constexpr int V = V16<T>::n;
     constexpr int TX = BN / RN, TY = NT / TX;
@@ -255,7 +274,9 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, int32_t *__res
     static_assert(RN % V == 0, "micro-tile width");
     constexpr int HN = RN / V, CS = BN / HN;
     constexpr int AST = TB + V;
-    constexpr bool PREFETCH_C = true;
+    // Old C values are requested before the panel loads when they fit the
+    // register budget (up to 128 bytes per thread), else after the k-loop.
+    constexpr bool PREFETCH_C = RM * RN * (int)sizeof(T) <= 128;
 
     __shared__ __attribute__((aligned(16))) T As[BM * AST];
     __shared__ __attribute__((aligned(16))) T Bs[TB * BN];
@@ -263,17 +284,15 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, int32_t *__res
     const int wg = blockIdx.x;
     const int lin = (wg % 8) * per_xcd + wg / 8;
     if (lin >= ntiles) return;
-    const int gm_e = gm - (skip >= 0), gn_e = gn - (skip >= 0);
+    const int gm_e = gm - (skip_i >= 0), gn_e = gn - (skip_j >= 0);
     constexpr int G = 8;
     const int group = lin / (G * gn_e);
     const int first = group * G;
     const int rows_in = min(G, gm_e - first);
     const int idx = lin - group * G * gn_e;
     int bi = first + idx % rows_in, bj = idx / rows_in;
-    if (skip >= 0) {
-        bi += bi >= skip;
-        bj += bj >= skip;
-    }
+    if (skip_i >= 0) bi += bi >= skip_i;
+    if (skip_j >= 0) bj += bj >= skip_j;
     const int64_t I0 = (int64_t)bi * BM, J0 = (int64_t)bj * BN, k0 = (int64_t)r * TB;
     const bool mask_rows = (I0 <= k0) && (k0 < I0 + BM);
     const bool mask_cols = (J0 <= k0) && (k0 < J0 + BN);
@@ -281,13 +300,19 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, int32_t *__res
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
     auto c_ptr = [&](int ii, int h) { return D + (I0 + ty + TY * ii) * ld + J0 + h * CS + tx * V; };
 
+    typedef uint16_t lvec __attribute__((ext_vector_type(V)));
+    auto l_ptr = [&](int ii, int h) { return L + (c_ptr(ii, h) - D); };
     vec c[RM][HN];
+    lvec lm[PATH ? RM : 1][PATH ? HN : 1];
     if constexpr (PREFETCH_C) {
         // Old C values, requested first so their latency overlaps the panel loads.
 #pragma unroll
         for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
-            for (int h = 0; h < HN; ++h) c[ii][h] = *(const vec *)c_ptr(ii, h);
+            for (int h = 0; h < HN; ++h) {
+                c[ii][h] = *(const vec *)c_ptr(ii, h);
+                if constexpr (PATH) lm[ii][h] = *(const lvec *)l_ptr(ii, h);
+            }
     }
 
     const vec vinf = inf_v<T>();
@@ -340,12 +365,15 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, int32_t *__res
 #pragma unroll
         for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
-            for (int h = 0; h < HN; ++h) c[ii][h] = *(const vec *)c_ptr(ii, h);
+            for (int h = 0; h < HN; ++h) {
+                c[ii][h] = *(const vec *)c_ptr(ii, h);
+                if constexpr (PATH) lm[ii][h] = *(const lvec *)l_ptr(ii, h);
+            }
     }
 
     // New distances: store the 16-byte vectors in which some entry decreased;
     // in path mode mark each decreased entry pending from this round.
-    const int32_t pend = -2 - r;
+    const uint16_t pend = (uint16_t)(r + 1);
 #pragma unroll
     for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
@@ -363,10 +391,10 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, int32_t *__res
             if (ch) {
                 *(vec *)c_ptr(ii, h) = nv;
                 if constexpr (PATH) {
-                    int32_t *pp = P + (c_ptr(ii, h) - D);
+                    lvec nl = lm[ii][h];
 #pragma unroll
-                    for (int e = 0; e < V; ++e)
-                        if (lt[e]) pp[e] = pend;
+                    for (int e = 0; e < V; ++e) nl[e] = lt[e] ? pend : nl[e];
+                    *(lvec *)l_ptr(ii, h) = nl;
                 }
             }
         }
@@ -374,7 +402,7 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, int32_t *__res
 
 // ---------------------------------------------------------------------------
 // Label resolution (path mode, after the last round).  Entry (i, j) pending
-// from round r (P = -2 - r) last decreased in the last phase of round r, to
+// from round r (L = r + 1) last decreased in the last phase of round r, to
 // S = min over k in K_r of A[i][k] + B[k][j].  For every k that attains S, the
 // entries (i, k) and (k, j) were already final then: a later decrease of either
 // would give (i, j) a strictly shorter path, contradicting that S is final.  So
@@ -385,19 +413,19 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, int32_t *__res
 // from a later round, larger than every label of round r, so it never changes
 // the minimum -- and such a k is recognisable: one of its two entries
 // decreased after round r, so if that entry is still pending, it is pending
-// from a round later than r; such k are skipped.  Otherwise P[i][k] and
-// P[k][j] are either final labels or pending from rounds before r, whose
-// labels are below k0 and so do not change max(., k, .): their pending value
-// serves as well as the label.  Entries are therefore resolved independently,
-// in one launch, reading labels from a snapshot P0 of P taken before it.
-// Column segments come from a transposed copy DT (DT[j][k] = D[k][j]) so that
-// both segments are contiguous.  With non-integer weights, rounding can break
-// the exact equality (a sub-path decreased later by less than the sum's
-// rounding step); then the k with the smallest sum is taken and the label is k
-// itself, which still encodes a path of length D[i][j] up to rounding.
+// from a round later than r; such k are skipped.  Otherwise (i, k) and (k, j)
+// carry either their final label or, if pending from a round before r, a label
+// below k0 (P holds an older one, also below k0, until that entry is resolved),
+// which does not change max(., k, .).  Entries are therefore resolved
+// independently, in one launch, updating P in place.  Column segments come from
+// a transposed copy DT (DT[j][k] = D[k][j]) so that both segments are
+// contiguous.  With non-integer weights, rounding can break the exact equality
+// (a sub-path decreased later by less than the sum's rounding step); then the k
+// with the smallest sum is taken and the label is k itself, which still encodes
+// a path of length D[i][j] up to rounding.
 template <typename T, int TB>
 __global__ void __launch_bounds__(NT) k_resolve(const T *__restrict__ D, const T *__restrict__ DT,
-                                               const int32_t *__restrict__ P0, int32_t *__restrict__ P,
+                                               const uint16_t *__restrict__ L, int32_t *__restrict__ P,
                                                int64_t ld) {
     using vec = typename V16<T>::type;
     constexpr int V = V16<T>::n;
@@ -405,9 +433,9 @@ __global__ void __launch_bounds__(NT) k_resolve(const T *__restrict__ D, const T
     const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
     if (j >= ld) return;
     const int64_t ij = i * ld + j;
-    const int32_t pv = P0[ij];
-    if (pv > -2) return;
-    const int64_t k0 = (int64_t)(-2 - pv) * TB;
+    const int lv = L[ij];
+    if (lv == 0) return;
+    const int64_t k0 = (int64_t)(lv - 1) * TB;
     const T d = D[ij];
     const T *arow = D + i * ld + k0;
     const T *brow = DT + j * ld + k0;
@@ -427,15 +455,13 @@ __global__ void __launch_bounds__(NT) k_resolve(const T *__restrict__ D, const T
             best = vmin(best, s);
         }
     }
-    const int32_t r = -2 - pv;
     int32_t M = INT_MAX;
     while (hits) {
         const int k = __builtin_ctzll(hits);
         hits &= hits - 1;
         const int64_t kg = k0 + k;
-        const int32_t a = P0[i * ld + kg], b = P0[kg * ld + j];
-        if ((a <= -2 && -2 - a > r) || (b <= -2 && -2 - b > r)) continue;  // decreased after round r
-        M = min(M, max(max(a, b), (int32_t)kg));
+        if (L[i * ld + kg] > lv || L[kg * ld + j] > lv) continue;  // decreased after round r
+        M = min(M, max(max(P[i * ld + kg], P[kg * ld + j]), (int32_t)kg));
     }
     P[ij] = (M == INT_MAX) ? (int32_t)(k0 + kbest) : M;
 }
@@ -480,35 +506,34 @@ inline unsigned grid_for(int64_t n) {
     return (unsigned)(g < 8192 ? (g < 1 ? 1 : g) : 8192);
 }
 
-template <typename T, int TB, int TILE>
-hipError_t round_impl(T *D, int32_t *P, int64_t ld, int r, hipStream_t s) {
-    constexpr int RM4 = (TILE == 128) ? 8 : 4;
-    constexpr int RN4 = (sizeof(T) == 8) ? 4 : ((TILE == 128) ? 8 : 4);
-    constexpr int BM = TILE, BN = TILE;
+template <typename T, int TB, int BM, int BN>
+hipError_t round_impl(T *D, int32_t *P, uint16_t *L, int64_t ld, int r, hipStream_t s) {
     const int nb = (int)(ld / TB);
     const bool path = P != nullptr;
     if (path)
-        hipLaunchKernelGGL((k_phase1<T, TB, true>), dim3(1), dim3(NT), 0, s, D, P, ld, r);
+        hipLaunchKernelGGL((k_phase1<T, TB, true>), dim3(1), dim3(NT), 0, s, D, P, L, ld, r);
     else
-        hipLaunchKernelGGL((k_phase1<T, TB, false>), dim3(1), dim3(NT), 0, s, D, P, ld, r);
+        hipLaunchKernelGGL((k_phase1<T, TB, false>), dim3(1), dim3(NT), 0, s, D, P, L, ld, r);
     if (nb == 1) return hipGetLastError();
     if (path)
-        hipLaunchKernelGGL((k_phase23<T, TB, true>), dim3(2 * (nb - 1)), dim3(NT), 0, s, D, P, ld, r, nb);
+        hipLaunchKernelGGL((k_phase23<T, TB, true>), dim3(2 * (nb - 1)), dim3(NT), 0, s, D, P, L, ld, r, nb);
     else
-        hipLaunchKernelGGL((k_phase23<T, TB, false>), dim3(2 * (nb - 1)), dim3(NT), 0, s, D, P, ld, r, nb);
+        hipLaunchKernelGGL((k_phase23<T, TB, false>), dim3(2 * (nb - 1)), dim3(NT), 0, s, D, P, L, ld, r, nb);
+    // A tile dimension equal to the block skips block row / column r entirely;
+    // a wider one masks it inside the tile that contains it.
     const int gm = (int)(ld / BM), gn = (int)(ld / BN);
-    const int skip = (BM == TB) ? r : -1;
-    const int gm_e = gm - (skip >= 0), gn_e = gn - (skip >= 0);
+    const int skip_i = (BM == TB) ? r : -1, skip_j = (BN == TB) ? r : -1;
+    const int gm_e = gm - (skip_i >= 0), gn_e = gn - (skip_j >= 0);
     const int ntiles = gm_e * gn_e;
     if (ntiles > 0) {
         const int per = (ntiles + 7) / 8;
         prof_begin_p4(s);
         if (path)
-            hipLaunchKernelGGL((k_phase4<T, TB, BM, BN, RM4, RN4, true>), dim3(8 * per), dim3(NT), 0, s, D, P, ld, r,
-                               gm, gn, skip, per, ntiles);
+            hipLaunchKernelGGL((k_phase4<T, TB, BM, BN, true>), dim3(8 * per), dim3(NT), 0, s, D, L, ld, r, gm, gn,
+                               skip_i, skip_j, per, ntiles);
         else
-            hipLaunchKernelGGL((k_phase4<T, TB, BM, BN, RM4, RN4, false>), dim3(8 * per), dim3(NT), 0, s, D, P, ld,
-                               r, gm, gn, skip, per, ntiles);
+            hipLaunchKernelGGL((k_phase4<T, TB, BM, BN, false>), dim3(8 * per), dim3(NT), 0, s, D, L, ld, r, gm, gn,
+                               skip_i, skip_j, per, ntiles);
         prof_end_p4(s);
     }
     return hipGetLastError();
@@ -516,35 +541,43 @@ hipError_t round_impl(T *D, int32_t *P, int64_t ld, int r, hipStream_t s) {
 
 }  // namespace
 
+// Compiled (block, tile_m, tile_n) combinations.
+#define FW_P4_CONFIGS_F32(X) X(32, 64, 64) X(64, 64, 64) X(64, 128, 64) X(64, 64, 128) X(64, 128, 128)
+#define FW_P4_CONFIGS_F64(X) X(32, 64, 64) X(64, 64, 64) X(64, 128, 64) X(64, 64, 128)
+
 template <typename T>
 bool config_supported(TileCfg c) {
-    if (sizeof(T) == 8) return (c.block == 32 || c.block == 64) && c.tile == 64;
-    return (c.block == 32 && c.tile == 64) || (c.block == 64 && (c.tile == 64 || c.tile == 128));
+#define FW_MATCH(B, M, N) if (c.block == B && c.tile_m == M && c.tile_n == N) return true;
+    if (sizeof(T) == 4) {
+        FW_P4_CONFIGS_F32(FW_MATCH)
+    } else {
+        FW_P4_CONFIGS_F64(FW_MATCH)
+    }
+#undef FW_MATCH
+    return false;
 }
 
 template <typename T>
-hipError_t launch_round(T *D, int32_t *P, int64_t ld, int r, TileCfg c, hipStream_t s) {
+hipError_t launch_round(T *D, int32_t *P, uint16_t *L, int64_t ld, int r, TileCfg c, hipStream_t s) {
+#define FW_DISPATCH(B, M, N) \
+    if (c.block == B && c.tile_m == M && c.tile_n == N) return round_impl<T, B, M, N>(D, P, L, ld, r, s);
     if constexpr (sizeof(T) == 4) {
-        if (c.block == 64 && c.tile == 128) return round_impl<T, 64, 128>(D, P, ld, r, s);
-        if (c.block == 64 && c.tile == 64) return round_impl<T, 64, 64>(D, P, ld, r, s);
-        if (c.block == 32 && c.tile == 64) return round_impl<T, 32, 64>(D, P, ld, r, s);
+        FW_P4_CONFIGS_F32(FW_DISPATCH)
     } else {
-        if (c.block == 64 && c.tile == 64) return round_impl<T, 64, 64>(D, P, ld, r, s);
-        if (c.block == 32 && c.tile == 64) return round_impl<T, 32, 64>(D, P, ld, r, s);
+        FW_P4_CONFIGS_F64(FW_DISPATCH)
     }
+#undef FW_DISPATCH
     return hipErrorInvalidValue;
 }
 
 template <typename T>
-hipError_t launch_resolve(const T *D, T *DT, int32_t *P0, int32_t *P, int64_t ld, int block, hipStream_t s) {
-    hipError_t e = hipMemcpyAsync(P0, P, (size_t)(ld * ld) * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return e;
+hipError_t launch_resolve(const T *D, T *DT, const uint16_t *L, int32_t *P, int64_t ld, int block, hipStream_t s) {
     hipLaunchKernelGGL((k_transpose<T>), dim3((unsigned)(ld / 64), (unsigned)(ld / 64)), dim3(NT), 0, s, D, DT, ld);
     const dim3 grid((unsigned)((ld + NT - 1) / NT), (unsigned)ld);
     if (block == 64)
-        hipLaunchKernelGGL((k_resolve<T, 64>), grid, dim3(NT), 0, s, D, DT, P0, P, ld);
+        hipLaunchKernelGGL((k_resolve<T, 64>), grid, dim3(NT), 0, s, D, DT, L, P, ld);
     else if (block == 32)
-        hipLaunchKernelGGL((k_resolve<T, 32>), grid, dim3(NT), 0, s, D, DT, P0, P, ld);
+        hipLaunchKernelGGL((k_resolve<T, 32>), grid, dim3(NT), 0, s, D, DT, L, P, ld);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -569,10 +602,10 @@ hipError_t launch_pad_out(const T *src, int64_t npad, T *dst, int64_t n, hipStre
 
 template bool config_supported<float>(TileCfg);
 template bool config_supported<double>(TileCfg);
-template hipError_t launch_round<float>(float *, int32_t *, int64_t, int, TileCfg, hipStream_t);
-template hipError_t launch_round<double>(double *, int32_t *, int64_t, int, TileCfg, hipStream_t);
-template hipError_t launch_resolve<float>(const float *, float *, int32_t *, int32_t *, int64_t, int, hipStream_t);
-template hipError_t launch_resolve<double>(const double *, double *, int32_t *, int32_t *, int64_t, int, hipStream_t);
+template hipError_t launch_round<float>(float *, int32_t *, uint16_t *, int64_t, int, TileCfg, hipStream_t);
+template hipError_t launch_round<double>(double *, int32_t *, uint16_t *, int64_t, int, TileCfg, hipStream_t);
+template hipError_t launch_resolve<float>(const float *, float *, const uint16_t *, int32_t *, int64_t, int, hipStream_t);
+template hipError_t launch_resolve<double>(const double *, double *, const uint16_t *, int32_t *, int64_t, int, hipStream_t);
 template hipError_t launch_pad_in<float>(const float *, int64_t, float *, int64_t, hipStream_t);
 template hipError_t launch_pad_in<double>(const double *, int64_t, double *, int64_t, hipStream_t);
 template hipError_t launch_pad_out<float>(const float *, int64_t, float *, int64_t, hipStream_t);

@@ -61,7 +61,7 @@ void *g_stage = nullptr;
 size_t g_stage_cap = 0;
 hipEvent_t g_stage_ev = nullptr;
 
-struct TuneEntry { int f64, path; long long n_lo, n_hi; int block, tile; };
+struct TuneEntry { int f64, path; long long n_lo, n_hi; int block, tile_m, tile_n; };
 struct TuneBatchedEntry { int f64, path, small_max_n; };
 #include "tune_table.inc"
 
@@ -69,8 +69,9 @@ fw::TileCfg default_cfg(fw_dtype_t dt, int64_t n, bool path) { return fw::tuned_
 
 template <typename T>
 fw_status_t run_apsp(int64_t n, T *dist, int32_t *path, fw::TileCfg cfg, hipStream_t s) {
-    if (!fw::config_supported<T>(cfg)) return fail(FW_EUNSUPPORTED, "block %d / tile %d not compiled in", cfg.block, cfg.tile);
-    const int64_t unit = cfg.tile;
+    if (!fw::config_supported<T>(cfg))
+        return fail(FW_EUNSUPPORTED, "block %d / tile %d x %d not compiled in", cfg.block, cfg.tile_m, cfg.tile_n);
+    const int64_t unit = cfg.tile_m > cfg.tile_n ? cfg.tile_m : cfg.tile_n;
     const int64_t npad = (n + unit - 1) / unit * unit;
     const bool aligned = ((uintptr_t)dist % 16 == 0) && (path == nullptr || (uintptr_t)path % 16 == 0);
     hipError_t e;
@@ -87,17 +88,23 @@ fw_status_t run_apsp(int64_t n, T *dist, int32_t *path, fw::TileCfg cfg, hipStre
         if ((e = fw::launch_pad_in<T>(dist, n, D, npad, s)) != hipSuccess) return hip_fail(e, "pad");
     }
     if (P && (e = fw::launch_fill_i32(P, npad * npad, -1, s)) != hipSuccess) return hip_fail(e, "path init");
+    // Path mode scratch: pending marks L (uint16, zeroed), then the transpose of
+    // D for the label resolution.
+    void *ps = nullptr;
+    uint16_t *L = nullptr;
+    const size_t lbytes = (size_t)(npad * npad) * sizeof(uint16_t), tbytes = (size_t)(npad * npad) * sizeof(T);
+    if (P) {
+        e = hipMallocAsync(&ps, lbytes + tbytes, s);
+        if (e != hipSuccess) return fail(FW_ENOMEM, "label scratch of %zu bytes: %s", lbytes + tbytes, hipGetErrorString(e));
+        L = (uint16_t *)ps;
+        if ((e = fw::launch_fill_i32((int32_t *)L, npad * npad / 2, 0, s)) != hipSuccess) return hip_fail(e, "mark init");
+    }
     const int R = (int)(npad / cfg.block);
     for (int r = 0; r < R; ++r)
-        if ((e = fw::launch_round<T>(D, P, npad, r, cfg, s)) != hipSuccess) return hip_fail(e, "round launch");
+        if ((e = fw::launch_round<T>(D, P, L, npad, r, cfg, s)) != hipSuccess) return hip_fail(e, "round launch");
     if (P) {
-        // Labels the last phase left pending: transpose of D + snapshot of P as scratch.
-        void *rs = nullptr;
-        const size_t tb = (size_t)(npad * npad) * sizeof(T), pb = (size_t)(npad * npad) * sizeof(int32_t);
-        e = hipMallocAsync(&rs, tb + pb, s);
-        if (e != hipSuccess) return fail(FW_ENOMEM, "label scratch of %zu bytes: %s", tb + pb, hipGetErrorString(e));
-        e = fw::launch_resolve<T>(D, (T *)rs, (int32_t *)((char *)rs + tb), P, npad, cfg.block, s);
-        hipError_t e2 = hipFreeAsync(rs, s);
+        e = fw::launch_resolve<T>(D, (T *)((char *)ps + lbytes), L, P, npad, cfg.block, s);
+        hipError_t e2 = hipFreeAsync(ps, s);
         if (e != hipSuccess) return hip_fail(e, "label resolution");
         if (e2 != hipSuccess) return hip_fail(e2, "label scratch free");
     }
@@ -121,8 +128,8 @@ fw_status_t check_common(fw_dtype_t dt, int64_t n, const void *dist) {
 namespace fw {
 TileCfg tuned_config(bool f64, bool path, int64_t n) {
     for (const TuneEntry &t : kTuneApsp)
-        if (t.f64 == (int)f64 && t.path == (int)path && n >= t.n_lo && n < t.n_hi) return {t.block, t.tile};
-    return {64, 64};
+        if (t.f64 == (int)f64 && t.path == (int)path && n >= t.n_lo && n < t.n_hi) return {t.block, t.tile_m, t.tile_n};
+    return {64, 64, 64};
 }
 int tuned_batched_small_max_n(bool f64, bool path) {
     for (const TuneBatchedEntry &t : kTuneBatched)
@@ -156,10 +163,12 @@ fw_status_t fw_apsp_config(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, 
     if (st != FW_OK) return st;
     fw::TileCfg tc = default_cfg(dt, n, path != nullptr);
     if (cfg) {
-        if (cfg->reserved0 || cfg->reserved1) return fail(FW_EINVAL, "reserved config fields must be 0");
+        if (cfg->reserved) return fail(FW_EINVAL, "reserved config field must be 0");
         if (cfg->block) tc.block = cfg->block;
-        if (cfg->tile) tc.tile = cfg->tile;
-        if (tc.block <= 0 || tc.tile <= 0 || tc.tile % tc.block) return fail(FW_EINVAL, "tile must be a multiple of block");
+        if (cfg->tile_m) tc.tile_m = cfg->tile_m;
+        if (cfg->tile_n) tc.tile_n = cfg->tile_n;
+        if (tc.block <= 0 || tc.tile_m <= 0 || tc.tile_n <= 0 || tc.tile_m % tc.block || tc.tile_n % tc.block)
+            return fail(FW_EINVAL, "tile edges must be multiples of block");
     }
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);
@@ -176,8 +185,9 @@ fw_status_t fw_query_config(fw_dtype_t dt, int64_t n, int32_t path, fw_config_t 
     if (!out) return fail(FW_EINVAL, "out is NULL");
     const fw::TileCfg c = default_cfg(dt, n, path != 0);
     out->block = c.block;
-    out->tile = c.tile;
-    out->reserved0 = out->reserved1 = 0;
+    out->tile_m = c.tile_m;
+    out->tile_n = c.tile_n;
+    out->reserved = 0;
     return FW_OK;
 }
 

@@ -60,10 +60,19 @@ def test_invalid_arguments(fw, args):
 
 def test_invalid_config(fw):
     L = fw.lib()
-    cfg = fw._lib.FwConfig(64, 96, 0, 0)  # tile not a multiple of block
+    cfg = fw._lib.FwConfig(64, 96, 64, 0)  # tile not a multiple of block
     assert L.fw_apsp_config(0, 128, 4096, None, ctypes.byref(cfg), None) == fw.FW_EINVAL
-    cfg = fw._lib.FwConfig(64, 128, 1, 0)  # reserved field set
+    cfg = fw._lib.FwConfig(64, 128, 128, 1)  # reserved field set
     assert L.fw_apsp_config(0, 128, 4096, None, ctypes.byref(cfg), None) == fw.FW_EINVAL
+
+
+def test_query_config(fw):
+    for dt in (0, 1):
+        for n in (1, 100, 1000, 5000, 16384, 65536):
+            for path in (False, True):
+                b, tm, tn = fw.fw_query_config(dt, n, path)
+                assert b in (32, 64) and tm in (64, 128) and tn in (64, 128)
+                assert tm % b == 0 and tn % b == 0
 
 
 @pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="a GPU is present: would launch on a bogus pointer")

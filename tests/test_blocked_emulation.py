@@ -137,32 +137,41 @@ def test_model_real_weights_tolerance():
 
 
 def blocked_model_deferred(W, TB):
-    """The GPU's path-mode schedule: phases 1-3 apply the lexicographic rule to raw P
-    (pending marks included), the last phase only marks strict improvements as
-    pending (P = -2 - r), and one pass after the last round resolves every pending
-    label from the final D and a snapshot of P."""
+    """The GPU's path-mode schedule: phases 1-3 apply the lexicographic rule to P
+    (which holds an older label while an entry is pending) and clear the entry's
+    mark L when they change it; the last phase only marks strict improvements
+    (L = r + 1); one pass after the last round resolves every pending label from
+    the final D, in place, skipping the k whose entries are pending from a later
+    round."""
     n = W.shape[0]
     npad = -(-n // TB) * TB
     D = np.full((npad, npad), np.inf)
     np.fill_diagonal(D, 0.0)
     D[:n, :n] = W
     P = np.full((npad, npad), -1, dtype=np.int64)
+    L = np.zeros((npad, npad), dtype=np.int64)
     R = npad // TB
     for r in range(R):
         K = np.arange(r * TB, (r + 1) * TB)
         ks = slice(r * TB, (r + 1) * TB)
+        D0, P0 = D[ks, ks].copy(), P[ks, ks].copy()
         for k in K:
             s = D[ks, k:k + 1] + D[k:k + 1, ks]
             m = np.maximum(np.maximum(P[ks, k:k + 1], k), P[k:k + 1, ks])
             D[ks, ks], P[ks, ks] = lex_update(D[ks, ks], P[ks, ks], s, m)
+        L[ks, ks] = np.where((D[ks, ks] != D0) | (P[ks, ks] != P0), 0, L[ks, ks])
         Dkk, Pkk = D[ks, ks].copy(), P[ks, ks].copy()
         others = [b for b in range(R) if b != r]
         for b in others:
             js = slice(b * TB, (b + 1) * TB)
-            D[ks, js], P[ks, js] = product_lex(Dkk, Pkk, D[ks, js].copy(), P[ks, js].copy(), K,
-                                               D[ks, js], P[ks, js])
-            D[js, ks], P[js, ks] = product_lex(D[js, ks].copy(), P[js, ks].copy(), Dkk, Pkk, K,
-                                               D[js, ks], P[js, ks])
+            for (rs, cs, A, PA, B, PB) in ((ks, js, Dkk, Pkk, None, None), (js, ks, None, None, Dkk, Pkk)):
+                Dold, Pold = D[rs, cs].copy(), P[rs, cs].copy()
+                if A is not None:
+                    Dn, Pn = product_lex(A, PA, Dold, Pold, K, Dold, Pold)
+                else:
+                    Dn, Pn = product_lex(Dold, Pold, B, PB, K, Dold, Pold)
+                D[rs, cs], P[rs, cs] = Dn, Pn
+                L[rs, cs] = np.where((Dn != Dold) | (Pn != Pold), 0, L[rs, cs])
         for bi in others:
             for bj in others:
                 is_, js = slice(bi * TB, (bi + 1) * TB), slice(bj * TB, (bj + 1) * TB)
@@ -171,21 +180,16 @@ def blocked_model_deferred(W, TB):
                     S = np.minimum(S, D[is_, r * TB + t:r * TB + t + 1] + D[r * TB + t:r * TB + t + 1, js])
                 imp = S < D[is_, js]
                 D[is_, js] = np.where(imp, S, D[is_, js])
-                P[is_, js] = np.where(imp, -2 - r, P[is_, js])
-    P0 = P.copy()
-    for i, j in zip(*np.nonzero(P0 <= -2)):
-        r = -2 - P0[i, j]
-        ks = np.arange(r * TB, (r + 1) * TB)
+                L[is_, js] = np.where(imp, r + 1, L[is_, js])
+    # resolution, in place, entries in an arbitrary order
+    order = np.argwhere(L > 0)
+    np.random.default_rng(0).shuffle(order)
+    for i, j in order:
+        lv = L[i, j]
+        ks = np.arange((lv - 1) * TB, lv * TB)
         sums = D[i, ks] + D[ks, j]
-        labels = []
-        for k in ks[sums == D[i, j]]:
-            a, b = P0[i, k], P0[k, j]
-            # a dependency pending from a later round decreased after round r: k
-            # attains D[i][j] only with final values and its label is larger than
-            # every label of round r
-            if (a <= -2 and -2 - a > r) or (b <= -2 and -2 - b > r):
-                continue
-            labels.append(max(a, k, b))
+        labels = [max(P[i, k], k, P[k, j]) for k in ks[sums == D[i, j]]
+                  if L[i, k] <= lv and L[k, j] <= lv]
         assert labels
         P[i, j] = min(labels)
     return D[:n, :n], P[:n, :n].astype(np.int32)

@@ -15,7 +15,8 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-CONFIGS = {np.float32: [(32, 64), (64, 64), (64, 128)], np.float64: [(32, 64), (64, 64)]}
+CONFIGS = {np.float32: [(32, 64, 64), (64, 64, 64), (64, 128, 64), (64, 64, 128), (64, 128, 128)],
+           np.float64: [(32, 64, 64), (64, 64, 64), (64, 128, 64), (64, 64, 128)]}
 
 
 @pytest.fixture(scope="module")
@@ -27,12 +28,13 @@ def dev():
     return torch.device("cuda:0")
 
 
-def run_gpu(W, dev, path=True, block=0, tile=0, case=""):
+def run_gpu(W, dev, path=True, block=0, tile=(0, 0), case=""):
     import torch
     import paper_2105_07298_amd as fw
     print(f"[gpu] fw_apsp {case} n={W.shape[0]} dtype={W.dtype} path={path} block={block} tile={tile}",
           flush=True)
-    D, P = fw.apsp(torch.from_numpy(np.ascontiguousarray(W)).to(dev), path=path, block=block, tile=tile)
+    D, P = fw.apsp(torch.from_numpy(np.ascontiguousarray(W)).to(dev), path=path, block=block,
+                   tile_m=tile[0], tile_n=tile[1])
     torch.cuda.synchronize()
     return D.cpu().numpy(), (P.cpu().numpy() if P is not None else None)
 
@@ -73,8 +75,8 @@ def test_block_and_tile_invariance_tie_heavy(dev, dtype):
     W = workloads.int_graph(n=448, p=0.02, wmax=3, seed=21, dtype=dtype)
     Do, Po = oracle.fw(W)
     assert (Po >= 0).mean() > 0.5
-    for block, tile in CONFIGS[dtype]:
-        Dg, Pg = run_gpu(W, dev, block=block, tile=tile, case="tie-heavy")
+    for block, tm, tn in CONFIGS[dtype]:
+        Dg, Pg = run_gpu(W, dev, block=block, tile=(tm, tn), case="tie-heavy")
         assert_exact(W, Dg, Pg, Do, Po)
 
 
