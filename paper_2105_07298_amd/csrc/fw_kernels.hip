@@ -66,11 +66,14 @@ __device__ __forceinline__ void lex_take(T &d, int32_t &p, T s, int32_t m) {
 // column k of the block are unchanged by the update (D[k][k] = 0, so every
 // candidate for them equals the current value with a label that is not
 // smaller), hence updating in place while other threads read them is safe; one
-// barrier per k orders step k's writes before step k+1's reads.
+// barrier per k orders step k's writes before step k+1's reads.  The k-steps
+// are a dependent chain on one CU, so the block runs with P1_TS x P1_TS = 1024
+// threads (few entries each) to keep every SIMD busy within a step.
+constexpr int P1_TS = 32;
 template <typename T, int TB, bool PATH>
-__global__ void __launch_bounds__(NT) k_phase1(T *__restrict__ D, int32_t *__restrict__ P, uint16_t *__restrict__ L,
-                                              int64_t ld, int r) {
-    constexpr int TS = 16, RM = TB / TS, ST = TB + 1;
+__global__ void __launch_bounds__(P1_TS *P1_TS) k_phase1(T *__restrict__ D, int32_t *__restrict__ P,
+                                                        uint16_t *__restrict__ L, int64_t ld, int r) {
+    constexpr int TS = P1_TS, RM = TB / TS, ST = TB + 1;
     __shared__ T sd[TB * ST];
     __shared__ int32_t sp[PATH ? TB * ST : 1];
     const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
@@ -261,8 +264,8 @@ __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__re
 // merely ties the old length never changes the label, and an entry that strictly
 // improves gets a label decided entirely by this round's candidates: it is
 // marked pending (L = r + 1) and resolved by k_resolve.  L is read with the old
-// tile and written back per 16-byte vector of D that changed, so its stores
-// cover whole 8-byte (float) or 4-byte (double) runs.
+// tile and, for each 16-byte vector of D that changed, the matching run of L
+// (8 bytes for float, 4 for double) is written back whole.
 template <typename T, int TB, int BM, int BN, bool PATH>
 __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__restrict__ L, int64_t ld, int r,
                                               int gm, int gn, int skip_i, int skip_j, int per_xcd, int ntiles) {
@@ -305,7 +308,8 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
     vec c[RM][HN];
     lvec lm[PATH ? RM : 1][PATH ? HN : 1];
     if constexpr (PREFETCH_C) {
-        // Old C values, requested first so their latency overlaps the panel loads.
+        // Old C values (and marks), requested first so their latency overlaps
+        // the panel loads.
 #pragma unroll
         for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
@@ -511,9 +515,9 @@ hipError_t round_impl(T *D, int32_t *P, uint16_t *L, int64_t ld, int r, hipStrea
     const int nb = (int)(ld / TB);
     const bool path = P != nullptr;
     if (path)
-        hipLaunchKernelGGL((k_phase1<T, TB, true>), dim3(1), dim3(NT), 0, s, D, P, L, ld, r);
+        hipLaunchKernelGGL((k_phase1<T, TB, true>), dim3(1), dim3(P1_TS * P1_TS), 0, s, D, P, L, ld, r);
     else
-        hipLaunchKernelGGL((k_phase1<T, TB, false>), dim3(1), dim3(NT), 0, s, D, P, L, ld, r);
+        hipLaunchKernelGGL((k_phase1<T, TB, false>), dim3(1), dim3(P1_TS * P1_TS), 0, s, D, P, L, ld, r);
     if (nb == 1) return hipGetLastError();
     if (path)
         hipLaunchKernelGGL((k_phase23<T, TB, true>), dim3(2 * (nb - 1)), dim3(NT), 0, s, D, P, L, ld, r, nb);
@@ -542,8 +546,11 @@ hipError_t round_impl(T *D, int32_t *P, uint16_t *L, int64_t ld, int r, hipStrea
 }  // namespace
 
 // Compiled (block, tile_m, tile_n) combinations.
-#define FW_P4_CONFIGS_F32(X) X(32, 64, 64) X(64, 64, 64) X(64, 128, 64) X(64, 64, 128) X(64, 128, 128)
-#define FW_P4_CONFIGS_F64(X) X(32, 64, 64) X(64, 64, 64) X(64, 128, 64) X(64, 64, 128)
+#define FW_P4_CONFIGS_F32(X)                                                                           \
+    X(32, 64, 64) X(32, 128, 64) X(32, 64, 128) X(32, 128, 128) X(64, 64, 64) X(64, 128, 64) X(64, 64, 128) \
+    X(64, 128, 128)
+#define FW_P4_CONFIGS_F64(X) \
+    X(32, 64, 64) X(32, 128, 64) X(32, 64, 128) X(32, 128, 128) X(64, 64, 64) X(64, 128, 64) X(64, 64, 128)
 
 template <typename T>
 bool config_supported(TileCfg c) {

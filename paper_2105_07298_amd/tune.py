@@ -23,8 +23,10 @@ import os
 import sys
 import time
 
-CONFIGS = {"f32": [(32, 64, 64), (64, 64, 64), (64, 128, 64), (64, 64, 128), (64, 128, 128)],
-           "f64": [(32, 64, 64), (64, 64, 64), (64, 128, 64), (64, 64, 128)]}
+CONFIGS = {"f32": [(32, 64, 64), (32, 128, 64), (32, 64, 128), (32, 128, 128),
+                   (64, 64, 64), (64, 128, 64), (64, 64, 128), (64, 128, 128)],
+           "f64": [(32, 64, 64), (32, 128, 64), (32, 64, 128), (32, 128, 128),
+                   (64, 64, 64), (64, 128, 64), (64, 64, 128)]}
 # size ranges [lo, hi) of the table and the n timed for each
 BUCKETS = [(0, 512, 256), (512, 2048, 1024), (2048, 8192, 4096), (8192, 1 << 40, 16384)]
 BATCHED_N = [16, 24, 32, 48, 64, 80, 96, 128, 160, 192, 256, 320, 384, 512]

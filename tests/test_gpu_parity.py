@@ -15,8 +15,10 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-CONFIGS = {np.float32: [(32, 64, 64), (64, 64, 64), (64, 128, 64), (64, 64, 128), (64, 128, 128)],
-           np.float64: [(32, 64, 64), (64, 64, 64), (64, 128, 64), (64, 64, 128)]}
+CONFIGS = {np.float32: [(32, 64, 64), (32, 128, 64), (32, 64, 128), (32, 128, 128),
+                        (64, 64, 64), (64, 128, 64), (64, 64, 128), (64, 128, 128)],
+           np.float64: [(32, 64, 64), (32, 128, 64), (32, 64, 128), (32, 128, 128),
+                        (64, 64, 64), (64, 128, 64), (64, 64, 128)]}
 
 
 @pytest.fixture(scope="module")
