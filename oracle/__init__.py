@@ -11,6 +11,8 @@ Contents
   dijkstra_rows(W, src) per-source Dijkstra with lexicographic labels
                         (length, largest interior vertex): rows of D and of the
                         canonical P without the cubic loop.
+  dial_rows(W, src, C)  the same labels by Dial's bucket queue, for integer
+                        weights in [1, C] (large sparse-ish graphs).
   brute_force(W)        enumeration of every simple path, n <= 8: the definition
                         of (D, P) written out.
   backward_pathwalk     dL/dW from dL/dD by walking each pair's shortest path.
@@ -60,6 +62,8 @@ def load(path: str = _LIB):
     lib.oracle_fw_f64_steps.argtypes = [i64, vp, vp, i64, i64, ctypes.c_int]
     lib.oracle_dijkstra_rows_f64.argtypes = [i64, vp, i64, vp, vp, vp, ctypes.c_int]
     lib.oracle_dijkstra_rows_i64.argtypes = [i64, vp, i64, vp, vp, vp, ctypes.c_int]
+    lib.oracle_dijkstra_rows_floatint.argtypes = [i64, vp, ctypes.c_int, i64, vp, vp, vp, ctypes.c_int]
+    lib.oracle_dial_rows.argtypes = [i64, vp, ctypes.c_int, i64, i64, vp, vp, vp, ctypes.c_int]
     lib.oracle_backward_pathwalk_f64.argtypes = [i64, vp, vp, vp, vp]
     lib.oracle_backward_pathwalk_f64.restype = ctypes.c_int
     lib.oracle_reconstruct.argtypes = [i64, vp, i64, i64, vp, i64]
@@ -166,6 +170,39 @@ def dijkstra_rows(W: np.ndarray, srcs, exact: bool | None = None, threads: int =
     D = np.empty((srcs.size, n), dtype=np.float64)
     lib.oracle_dijkstra_rows_f64(n, _ptr(Wd), srcs.size, _ptr(srcs), _ptr(D), _ptr(P), threads)
     return D, P
+
+
+def dijkstra_rows_integer_float(W: np.ndarray, srcs, threads: int = 0):
+    """dijkstra_rows for integer-valued weights held as float32/float64 (+inf = no
+    edge), converting each weight exactly to int64 as it is read (no int64 copy of W;
+    the caller guarantees W is integer-valued, diagonal 0).  Returns (Drows float64,
+    Prows int32)."""
+    lib = load()
+    W = np.ascontiguousarray(W)
+    assert W.dtype in (np.float32, np.float64) and W.ndim == 2 and W.shape[0] == W.shape[1]
+    n = W.shape[0]
+    srcs = np.ascontiguousarray(np.asarray(srcs, dtype=np.int64))
+    D = np.empty((srcs.size, n), dtype=np.int64)
+    P = np.empty((srcs.size, n), dtype=np.int32)
+    lib.oracle_dijkstra_rows_floatint(n, _ptr(W), int(W.dtype == np.float64), srcs.size, _ptr(srcs),
+                                      _ptr(D), _ptr(P), threads)
+    return from_i64(D), P
+
+
+def dial_rows(W: np.ndarray, srcs, wmax: int, threads: int = 0):
+    """Rows srcs of (D, P) for positive integer weights in [1, wmax] held as
+    float32/float64 (+inf = no edge), by Dial's bucket-queue Dijkstra with the same
+    lexicographic labels.  Returns (Drows float64, Prows int32)."""
+    lib = load()
+    W = np.ascontiguousarray(W)
+    assert W.dtype in (np.float32, np.float64) and W.ndim == 2 and W.shape[0] == W.shape[1]
+    n = W.shape[0]
+    srcs = np.ascontiguousarray(np.asarray(srcs, dtype=np.int64))
+    D = np.empty((srcs.size, n), dtype=np.int64)
+    P = np.empty((srcs.size, n), dtype=np.int32)
+    lib.oracle_dial_rows(n, _ptr(W), int(W.dtype == np.float64), int(wmax), srcs.size, _ptr(srcs), _ptr(D),
+                         _ptr(P), threads)
+    return from_i64(D), P
 
 
 def backward_pathwalk(D: np.ndarray, P: np.ndarray, G: np.ndarray) -> np.ndarray:

@@ -168,6 +168,112 @@ void oracle_dijkstra_f64(int64_t n, const double *W, int64_t src, double *dist, 
     free(done);
 }
 
+/* oracle_dijkstra_i64 for integer-valued weights stored as float (is_f64 = 0) or
+ * double (is_f64 = 1): every finite weight is converted exactly to int64 when
+ * it is read, +inf is "no edge".  Avoids an int64 copy of a very large matrix. */
+static void dijkstra_floatint(int64_t n, const void *Wv, int is_f64, int64_t src, int64_t *dist, int32_t *pmax)
+{
+    unsigned char *done = (unsigned char *)calloc((size_t)n, 1);
+    for (int64_t v = 0; v < n; ++v) { dist[v] = ORACLE_I64_INF; pmax[v] = -1; }
+    dist[src] = 0;
+    for (;;) {
+        int64_t u = -1;
+        for (int64_t v = 0; v < n; ++v) {
+            if (done[v] || dist[v] == ORACLE_I64_INF) continue;
+            if (u < 0 || dist[v] < dist[u] || (dist[v] == dist[u] && pmax[v] < pmax[u])) u = v;
+        }
+        if (u < 0) break;
+        done[u] = 1;
+        int32_t mu = (u == src) ? -1 : (pmax[u] > (int32_t)u ? pmax[u] : (int32_t)u);
+        for (int64_t v = 0; v < n; ++v) {
+            double w = is_f64 ? ((const double *)Wv)[u * n + v] : (double)((const float *)Wv)[u * n + v];
+            if (done[v] || v == u || w == INFINITY) continue;
+            int64_t s = dist[u] + (int64_t)w;
+            if (s < dist[v] || (s == dist[v] && mu < pmax[v])) { dist[v] = s; pmax[v] = mu; }
+        }
+    }
+    free(done);
+}
+
+void oracle_dijkstra_rows_floatint(int64_t n, const void *W, int is_f64, int64_t nsrc, const int64_t *srcs,
+                                   int64_t *dist, int32_t *pmax, int threads)
+{
+#pragma omp parallel for schedule(dynamic, 1) num_threads(pick_threads(threads))
+    for (int64_t s = 0; s < nsrc; ++s)
+        dijkstra_floatint(n, W, is_f64, srcs[s], dist + s * n, pmax + s * n);
+}
+
+/*
+ * The same lexicographic single-source labels for positive integer weights
+ * (1 <= w <= wmax, held as float or double, +inf = no edge), by Dial's form of
+ * Dijkstra's algorithm: vertices wait in buckets indexed by tentative distance;
+ * since every edge is at least 1, all of bucket d is final when the scan reaches
+ * it, and relaxing it only fills buckets d+1 .. d+wmax, so a ring of wmax+1
+ * buckets suffices.  Within a bucket the order of relaxation does not matter
+ * (each target keeps the smallest label it is offered).  No minimum scan: one
+ * pass over the row of each reached vertex.  Doubly linked lists move a vertex
+ * to a lower bucket when its distance drops.
+ */
+static void dial_one(int64_t n, const void *Wv, int is_f64, int64_t wmax, int64_t src, int64_t *dist, int32_t *pmax)
+{
+    const int64_t nb = wmax + 1;
+    int64_t *head = (int64_t *)malloc(sizeof(int64_t) * (size_t)nb);
+    int64_t *nxt = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *prv = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    double *dd = (double *)malloc(sizeof(double) * (size_t)n); /* distances; integers, exact in double */
+    unsigned char *queued_v = (unsigned char *)calloc((size_t)n, 1);
+    for (int64_t b = 0; b < nb; ++b) head[b] = -1;
+    for (int64_t v = 0; v < n; ++v) { dd[v] = INFINITY; pmax[v] = -1; }
+#define DIAL_PUSH(v)  do { int64_t b_ = (int64_t)dd[v] % nb; prv[v] = -1; nxt[v] = head[b_]; \
+                           if (head[b_] >= 0) prv[head[b_]] = (v); \
+                           head[b_] = (v); queued_v[v] = 1; } while (0)
+#define DIAL_UNLINK(v) do { int64_t b_ = (int64_t)dd[v] % nb; \
+                            if (prv[v] >= 0) nxt[prv[v]] = nxt[v]; else head[b_] = nxt[v]; \
+                            if (nxt[v] >= 0) prv[nxt[v]] = prv[v]; \
+                            queued_v[v] = 0; } while (0)
+    dd[src] = 0.0;
+    DIAL_PUSH(src);
+    int64_t queued = 1;
+    for (int64_t d = 0; queued > 0; ++d) {
+        const int64_t b = d % nb;
+        const double df = (double)d;
+        while (head[b] >= 0) {
+            const int64_t u = head[b];
+            DIAL_UNLINK(u);
+            --queued;
+            const int32_t mu = (u == src) ? -1 : (pmax[u] > (int32_t)u ? pmax[u] : (int32_t)u);
+            const float *rf = (const float *)Wv + u * n;
+            const double *rd = (const double *)Wv + u * n;
+            /* A vertex already taken has a distance <= d < d + w, and a missing edge
+             * gives +inf, so neither passes the tests below. */
+            for (int64_t v = 0; v < n; ++v) {
+                const double w = is_f64 ? rd[v] : (double)rf[v];
+                const double sv = df + w;
+                if (sv < dd[v]) {
+                    if (queued_v[v]) DIAL_UNLINK(v); else ++queued;
+                    dd[v] = sv;
+                    pmax[v] = mu;
+                    DIAL_PUSH(v);
+                } else if (sv == dd[v] && mu < pmax[v] && v != u) {
+                    pmax[v] = mu;
+                }
+            }
+        }
+    }
+#undef DIAL_PUSH
+#undef DIAL_UNLINK
+    for (int64_t v = 0; v < n; ++v) dist[v] = (dd[v] == INFINITY) ? ORACLE_I64_INF : (int64_t)dd[v];
+    free(head); free(nxt); free(prv); free(dd); free(queued_v);
+}
+
+void oracle_dial_rows(int64_t n, const void *W, int is_f64, int64_t wmax, int64_t nsrc, const int64_t *srcs,
+                      int64_t *dist, int32_t *pmax, int threads)
+{
+#pragma omp parallel for schedule(dynamic, 1) num_threads(pick_threads(threads))
+    for (int64_t s = 0; s < nsrc; ++s)
+        dial_one(n, W, is_f64, wmax, srcs[s], dist + s * n, pmax + s * n);
+}
+
 /* Many sources at once, one source per thread (for sampled-row verification of
  * large graphs).  dist/pmax are nsrc x n. */
 void oracle_dijkstra_rows_i64(int64_t n, const int64_t *W, int64_t nsrc, const int64_t *srcs,

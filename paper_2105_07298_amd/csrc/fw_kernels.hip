@@ -428,14 +428,11 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
 // with the smallest sum is taken and the label is k itself, which still encodes
 // a path of length D[i][j] up to rounding.
 template <typename T, int TB>
-__global__ void __launch_bounds__(NT) k_resolve(const T *__restrict__ D, const T *__restrict__ DT,
-                                               const uint16_t *__restrict__ L, int32_t *__restrict__ P,
-                                               int64_t ld) {
+__device__ __forceinline__ void resolve_one(const T *__restrict__ D, const T *__restrict__ DT,
+                                            const uint16_t *__restrict__ L, int32_t *__restrict__ P, int64_t ld,
+                                            int64_t i, int64_t j) {
     using vec = typename V16<T>::type;
     constexpr int V = V16<T>::n;
-    const int64_t i = blockIdx.y;
-    const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (j >= ld) return;
     const int64_t ij = i * ld + j;
     const int lv = L[ij];
     if (lv == 0) return;
@@ -468,6 +465,17 @@ __global__ void __launch_bounds__(NT) k_resolve(const T *__restrict__ D, const T
         M = min(M, max(max(P[i * ld + kg], P[kg * ld + j]), (int32_t)kg));
     }
     P[ij] = (M == INT_MAX) ? (int32_t)(k0 + kbest) : M;
+}
+
+template <typename T, int TB>
+__global__ void __launch_bounds__(NT) k_resolve(const T *__restrict__ D, const T *__restrict__ DT,
+                                               const uint16_t *__restrict__ L, int32_t *__restrict__ P,
+                                               int64_t ld) {
+    const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (j >= ld) return;
+    for (int64_t i = blockIdx.y; i < ld; i += gridDim.y) {  // grid y is capped at 65535 rows
+        resolve_one<T, TB>(D, DT, L, P, ld, i, j);
+    }
 }
 
 // Tiled transpose: DT[j][i] = D[i][j] (ld x ld, ld a multiple of 64).
@@ -580,7 +588,7 @@ hipError_t launch_round(T *D, int32_t *P, uint16_t *L, int64_t ld, int r, TileCf
 template <typename T>
 hipError_t launch_resolve(const T *D, T *DT, const uint16_t *L, int32_t *P, int64_t ld, int block, hipStream_t s) {
     hipLaunchKernelGGL((k_transpose<T>), dim3((unsigned)(ld / 64), (unsigned)(ld / 64)), dim3(NT), 0, s, D, DT, ld);
-    const dim3 grid((unsigned)((ld + NT - 1) / NT), (unsigned)ld);
+    const dim3 grid((unsigned)((ld + NT - 1) / NT), (unsigned)(ld < 65535 ? ld : 65535));
     if (block == 64)
         hipLaunchKernelGGL((k_resolve<T, 64>), grid, dim3(NT), 0, s, D, DT, L, P, ld);
     else if (block == 32)

@@ -255,3 +255,32 @@ def test_step_ranges_compose():
     oracle.fw_steps(D2, P2, 77, 200)
     np.testing.assert_array_equal(D2, D)
     np.testing.assert_array_equal(P2, P)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_dijkstra_integer_float_input_matches_int64(dtype):
+    """The float-input Dijkstra (exact conversion on read) equals the int64 one and FW."""
+    W = workloads.int_graph(n=300, p=0.1, wmax=100, seed=31, dtype=dtype)
+    srcs = workloads.sample_sources(300, 40)
+    D1, P1 = oracle.dijkstra_rows_integer_float(W, srcs)
+    D2, P2 = oracle.dijkstra_rows(W, srcs, exact=True)
+    np.testing.assert_array_equal(D1, D2)
+    np.testing.assert_array_equal(P1, P2)
+    D, P = oracle.fw(W)
+    np.testing.assert_array_equal(D1, D[srcs])
+    np.testing.assert_array_equal(P1, P[srcs])
+
+
+@pytest.mark.parametrize("wmax,p", [(1, 0.05), (3, 0.03), (100, 0.1), (7, 0.6)])
+def test_dial_matches_fw_and_dijkstra(wmax, p):
+    """Dial's bucket queue gives the classic loop's rows of D and canonical P."""
+    n = 400
+    W = workloads.int_graph(n=n, p=p, wmax=wmax, seed=32 + wmax)
+    D, P = oracle.fw(W)
+    srcs = np.arange(0, n, 7)
+    Dd, Pd = oracle.dial_rows(W, srcs, wmax)
+    np.testing.assert_array_equal(Dd, D[srcs])
+    np.testing.assert_array_equal(Pd, P[srcs])
+    Dd64, Pd64 = oracle.dial_rows(W.astype(np.float64), srcs, wmax)
+    np.testing.assert_array_equal(Dd64, Dd)
+    np.testing.assert_array_equal(Pd64, Pd)
