@@ -56,19 +56,20 @@ def gflops(n, seconds):
     return 2.0 * n ** 3 / seconds / 1e9
 
 
-def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False):
-    """Mean seconds per fw_apsp step (D <- W, P <- -1, all rounds) and last-phase stats."""
+def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False, config=None):
+    """Mean seconds per fw_apsp step (D <- W, P <- -1, all rounds) and last-phase stats.
+    config: (block, tile_m, tile_n, variant), default the tuned choice."""
     import numpy as np
     import workloads
     npdt = np.float32 if dtype == "f32" else np.float64
-    block, tm, tn = fw.fw_query_config(fw.FW_F32 if dtype == "f32" else fw.FW_F64, n, path)  # tuned choice
+    block, tm, tn, var = config or fw.fw_query_config(fw.FW_F32 if dtype == "f32" else fw.FW_F64, n, path)
     Wd = torch.from_numpy(workloads.unit_complete(n, dtype=npdt, seed=2)).cuda()
     D = torch.empty_like(Wd)
     P = torch.empty((n, n), dtype=torch.int32, device=Wd.device) if path else None
 
     def step():
         D.copy_(Wd)
-        fw.apsp_(D, P, block=block, tile_m=tm, tile_n=tn)
+        fw.apsp_(D, P, block=block, tile_m=tm, tile_n=tn, variant=var)
 
     for _ in range(warmup):
         step()
@@ -87,8 +88,9 @@ def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False):
     stats = None
     if prof:
         fw.fw_prof_enable(False)
-        cnt, tot_ms = fw.fw_prof_read(reset=True)
-        stats = {"launches": cnt, "mean_ms": tot_ms / max(cnt, 1), "block": block, "tile": [tm, tn]}
+        cnt, tot_ms, upd = fw.fw_prof_read(reset=True)
+        stats = {"launches": cnt, "mean_ms": tot_ms / max(cnt, 1), "block": block, "tile": [tm, tn],
+                 "variant": var, "updates_per_launch": upd / max(cnt, 1)}
     del Wd, D, P
     torch.cuda.empty_cache()
     return sec, stats
@@ -166,7 +168,7 @@ def time_fwd_bwd(fw, torch, steps=5, warmup=2):
 
 def roofline(n, dtype, stats):
     block = stats["block"]
-    upd = (n - block) ** 2 * block  # algorithmic updates of one last-phase launch
+    upd = stats["updates_per_launch"]  # algorithmic min-plus updates per timed last-phase launch
     achieved = 2.0 * upd / (stats["mean_ms"] / 1e3) / 1e12
     peak = PEAK_TFLOPS[dtype]
     traffic = None
@@ -178,7 +180,9 @@ def roofline(n, dtype, stats):
             traffic = t[key]["bytes_per_launch"]
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": traffic,
-            "kernel": "k_phase4 (min-plus tile update)", "launches": stats["launches"],
+            "kernel": ("k_phase4w (wave-row min-plus tile update)" if stats["variant"] == 2
+                       else "k_phase4 (LDS-panel min-plus tile update)"),
+            "tile": stats["tile"], "block": block, "launches": stats["launches"],
             "mean_launch_ms": round(stats["mean_ms"], 4), "flops_per_launch": 2 * upd}
 
 
@@ -219,6 +223,7 @@ def main():
     ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
     ap.add_argument("--no-path", action="store_true", help="distances only (P = NULL)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--config", default="", help="block,tile_m,tile_n,variant instead of the tuned choice")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, one device copy of this many MiB (HBM counter calibration)")
@@ -238,7 +243,8 @@ def main():
     path = not args.no_path
     print(f"[bench] n={args.n} {args.dtype} path={path} warmup={args.warmup} steps={args.steps}",
           file=sys.stderr, flush=True)
-    sec, stats = time_apsp(fw, torch, args.n, args.dtype, path, args.steps, args.warmup, prof=True)
+    config = tuple(int(x) for x in args.config.split(",")) if args.config else None
+    sec, stats = time_apsp(fw, torch, args.n, args.dtype, path, args.steps, args.warmup, prof=True, config=config)
     value = gflops(args.n, sec)
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GFLOPS", "n_gpus": 1,

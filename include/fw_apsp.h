@@ -63,21 +63,36 @@ fw_status_t fw_apsp(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, void *s
 
 /*
  * Tile configuration of fw_apsp, for tuning and for the tests that show results
- * do not depend on it.  block = round depth (the paper's TB) in {32, 64};
- * tile_m x tile_n = the output tile one workgroup updates in the last phase,
- * each edge in {64, 128} and a multiple of block.  Fields set to 0 keep the
- * tuned choice (a table of timings on gfx950 per element type, path mode and
- * size range); reserved must be 0.
+ * do not depend on it.
+ *   block    round depth (the paper's TB), 32 or 64.
+ *   variant  the last-phase kernel:
+ *            FW_P4_PANELS    both operand panels staged in LDS; tile_m and
+ *                            tile_n each 64 or 128 and a multiple of block.
+ *            FW_P4_WAVEROWS  each wave of 4 takes tile_m / 4 rows of the tile
+ *                            and reads their column-panel values with scalar
+ *                            loads; only the row panel is staged in LDS.
+ *                            tile_m divides block; tile_n = 64 x columns per
+ *                            lane (64 to 256).
+ *   tile_m x tile_n  the output tile one workgroup updates in the last phase.
+ * Fields set to 0 keep the tuned choice (a table of timings on gfx950 per
+ * element type, path mode and size range).  The resulting combination must be
+ * one the library compiles (fw_apsp_config returns FW_EUNSUPPORTED otherwise).
  */
-typedef struct { int32_t block; int32_t tile_m; int32_t tile_n; int32_t reserved; } fw_config_t;
+enum { FW_P4_PANELS = 1, FW_P4_WAVEROWS = 2 };
+typedef struct { int32_t block; int32_t tile_m; int32_t tile_n; int32_t variant; } fw_config_t;
 
 /* fw_apsp with an explicit configuration (cfg may be NULL = library choice).
  * FW_EUNSUPPORTED if the combination is not compiled in. */
 fw_status_t fw_apsp_config(fw_dtype_t dt, int64_t n, void *dist, int32_t *path,
                            const fw_config_t *cfg, void *stream);
 
+/* Every configuration compiled in for dt: writes the first min(cap, count)
+ * to out (host memory; may be NULL when cap is 0) and returns count, or
+ * FW_EINVAL (negative) for a bad dtype or cap.  Host only; launches nothing. */
+int32_t fw_list_configs(fw_dtype_t dt, fw_config_t *out, int32_t cap);
+
 /* The configuration fw_apsp uses for (dt, n, path != 0) -- the tuned table's
- * entry -- written to *out (reserved 0).  Host only; launches nothing. */
+ * entry -- written to *out.  Host only; launches nothing. */
 fw_status_t fw_query_config(fw_dtype_t dt, int64_t n, int32_t path, fw_config_t *out);
 
 /*
@@ -136,14 +151,17 @@ const char *fw_last_error(void);
 const char *fw_version(void);
 
 /*
- * Timing hooks for benchmarks.  While enabled, every launch of the last-phase
- * kernel (the register-blocked min-plus tile update) is bracketed by two HIP
- * events recorded on the stream it runs on.  fw_prof_read waits for the recorded
- * events and returns the number of bracketed launches and their summed duration
- * in milliseconds since the last reset (reset != 0 starts a new window).
+ * Timing hooks for benchmarks.  While enabled, every bulk launch of the
+ * last-phase kernel (the register-blocked min-plus tile update: each round's
+ * whole last phase, or with lookahead its part outside the next round's block
+ * row and column) is bracketed by two HIP events recorded on the stream it runs
+ * on.  fw_prof_read waits for the recorded events and returns the number of
+ * bracketed launches, their summed duration in milliseconds and their summed
+ * algorithmic min-plus updates (entries updated x block) since the last reset
+ * (reset != 0 starts a new window).  Any output pointer may be NULL.
  */
 void fw_prof_enable(int on);
-int fw_prof_read(int64_t *count, double *total_ms, int reset);
+int fw_prof_read(int64_t *count, double *total_ms, int64_t *updates, int reset);
 
 #ifdef __cplusplus
 }

@@ -13,15 +13,17 @@ LIB_PATH = os.path.join(HERE, "libfwapsp.so")
 
 FW_F32, FW_F64 = 0, 1
 FW_OK, FW_EINVAL, FW_ENOMEM, FW_EHIP, FW_EUNSUPPORTED = 0, -1, -2, -3, -4
+FW_P4_PANELS, FW_P4_WAVEROWS = 1, 2
 
-EXPORTS = ("fw_apsp", "fw_apsp_config", "fw_query_config", "fw_apsp_batched", "fw_apsp_batched_config",
+EXPORTS = ("fw_apsp", "fw_apsp_config", "fw_query_config", "fw_list_configs", "fw_apsp_batched",
+           "fw_apsp_batched_config",
            "fw_apsp_backward",
            "fw_status_string", "fw_last_error", "fw_version", "fw_prof_enable", "fw_prof_read")
 
 
 class FwConfig(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("tile_m", ctypes.c_int32),
-                ("tile_n", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("tile_n", ctypes.c_int32), ("variant", ctypes.c_int32)]
 
 
 class FwBatchedConfig(ctypes.Structure):
@@ -52,6 +54,8 @@ def lib():
     L.fw_apsp_config.argtypes = [ctypes.c_int, i64, vp, vp, ctypes.POINTER(FwConfig), vp]
     L.fw_query_config.argtypes = [ctypes.c_int, i64, i32, ctypes.POINTER(FwConfig)]
     L.fw_query_config.restype = ctypes.c_int
+    L.fw_list_configs.argtypes = [ctypes.c_int, ctypes.POINTER(FwConfig), i32]
+    L.fw_list_configs.restype = ctypes.c_int32
     L.fw_apsp_batched.argtypes = [ctypes.c_int, i32, vp, vp, vp, vp, vp]
     L.fw_apsp_batched_config.argtypes = [ctypes.c_int, i32, vp, vp, vp, vp, ctypes.POINTER(FwBatchedConfig), vp]
     L.fw_apsp_backward.argtypes = [ctypes.c_int, i64, i32, vp, vp, vp, vp, vp]
@@ -62,7 +66,7 @@ def lib():
     L.fw_last_error.restype = ctypes.c_char_p
     L.fw_version.restype = ctypes.c_char_p
     L.fw_prof_enable.argtypes = [ctypes.c_int]
-    L.fw_prof_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+    L.fw_prof_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), ctypes.c_int]
     L.fw_prof_read.restype = ctypes.c_int
     _lib = L
     return L
@@ -78,16 +82,27 @@ def fw_apsp(dt: int, n: int, dist: int, path: int | None, stream: int | None = N
     _check(lib().fw_apsp(dt, n, dist, path, stream), "fw_apsp")
 
 
-def fw_apsp_config(dt, n, dist, path, block=0, tile_m=0, tile_n=0, stream=None):
-    cfg = FwConfig(block, tile_m, tile_n, 0)
+def fw_apsp_config(dt, n, dist, path, block=0, tile_m=0, tile_n=0, variant=0, stream=None):
+    cfg = FwConfig(block, tile_m, tile_n, variant)
     _check(lib().fw_apsp_config(dt, n, dist, path, ctypes.byref(cfg), stream), "fw_apsp_config")
 
 
 def fw_query_config(dt: int, n: int, path: bool):
-    """(block, tile_m, tile_n) that fw_apsp uses for this case (from the tuned table)."""
+    """(block, tile_m, tile_n, variant) that fw_apsp uses for this case (from the tuned table)."""
     cfg = FwConfig(0, 0, 0, 0)
     _check(lib().fw_query_config(dt, n, 1 if path else 0, ctypes.byref(cfg)), "fw_query_config")
-    return int(cfg.block), int(cfg.tile_m), int(cfg.tile_n)
+    return int(cfg.block), int(cfg.tile_m), int(cfg.tile_n), int(cfg.variant)
+
+
+def fw_list_configs(dt: int):
+    """Every compiled (block, tile_m, tile_n, variant) for dtype code dt."""
+    L = lib()
+    count = L.fw_list_configs(dt, None, 0)
+    if count < 0:
+        _check(count, "fw_list_configs")
+    arr = (FwConfig * count)()
+    L.fw_list_configs(dt, arr, count)
+    return [(int(c.block), int(c.tile_m), int(c.tile_n), int(c.variant)) for c in arr]
 
 
 def fw_apsp_batched(dt, batch, n_host, off_host, dist, path, stream=None):
@@ -122,8 +137,10 @@ def fw_prof_enable(on: bool):
 
 
 def fw_prof_read(reset: bool = True):
-    """(count, total_ms) of bracketed last-phase launches since the last reset."""
+    """(count, total_ms, updates) of bracketed last-phase launches since the last reset."""
     c = ctypes.c_int64(0)
     t = ctypes.c_double(0.0)
-    _check(lib().fw_prof_read(ctypes.byref(c), ctypes.byref(t), 1 if reset else 0), "fw_prof_read")
-    return int(c.value), float(t.value)
+    u = ctypes.c_int64(0)
+    _check(lib().fw_prof_read(ctypes.byref(c), ctypes.byref(t), ctypes.byref(u), 1 if reset else 0),
+           "fw_prof_read")
+    return int(c.value), float(t.value), int(u.value)

@@ -5,25 +5,51 @@
 
 namespace fw {
 
-// Round depth (the paper's TB) and last-phase output tile (rows x columns, each
-// a multiple of the block).
+// Last-phase kernels: both operand panels in LDS, or one column-panel row per
+// wave in scalar registers and the row panel in LDS.
+constexpr int FW_VARIANT_PANELS = 1;
+constexpr int FW_VARIANT_WAVEROWS = 2;
+
+// Round depth (the paper's TB), last-phase output tile (rows x columns) and
+// last-phase kernel.
 struct TileCfg {
     int block;
     int tile_m;
     int tile_n;
+    int variant;
 };
 
-// One round of the blocked method, enqueued on `s`.  D, P are the padded
-// matrices (leading dimension ld, a multiple of both tile edges); P may be null
-// (distances only).  L (path mode) marks entries whose label is pending from a
-// round of the last phase (r + 1; 0 = current), zero-initialised.
-// Returns hipSuccess or the launch error.
+// Launches of round r of the blocked method, enqueued on `s`.  D, P are the
+// padded matrices (leading dimension ld, a multiple of the block and of both
+// tile edges); P may be null (distances only).  L (path mode) marks entries
+// whose label is pending from a round of the last phase (r + 1; 0 = current),
+// zero-initialised.  Each returns hipSuccess or the launch error.
+//
+// Phases 1-3: the diagonal block of round r, then its row and column panels.
 template <typename T>
-hipError_t launch_round(T *D, int32_t *P, uint16_t *L, int64_t ld, int r, TileCfg cfg, hipStream_t s);
+hipError_t launch_phase123(T *D, int32_t *P, uint16_t *L, int64_t ld, int r, int block, hipStream_t s);
 
-// Compiled (block, tile_m, tile_n) combinations for element type T.
+// Phase 4 of round r over a selection of its tiles:
+//   all    every tile outside block row and column r;
+//   cross  the tiles of block row and column r + 1 (outside block row and
+//          column r): what phases 1-3 of round r + 1 read and write;
+//   rest   every tile outside block rows and columns r and r + 1.
+// cross and rest need lookahead_supported(cfg) and r + 1 < ld / block.
+enum class P4Mode { all, cross, rest };
+template <typename T>
+hipError_t launch_phase4(T *D, uint16_t *L, bool path, int64_t ld, int r, TileCfg cfg, P4Mode mode, hipStream_t s);
+
+// Tiles exactly one block wide and at most one block tall, so that block row
+// and column r + 1 are whole tiles.
+bool lookahead_supported(TileCfg cfg);
+
+// Compiled (block, tile_m, tile_n, variant) combinations for element type T.
 template <typename T>
 bool config_supported(TileCfg cfg);
+
+// Writes up to cap of them to out (may be null) and returns their number.
+template <typename T>
+int list_configs(TileCfg *out, int cap);
 
 // Path mode, after the last round: resolve the labels the last phase left
 // pending (marked in L).  DT (ld*ld elements) is scratch for the transpose of D.
@@ -65,8 +91,9 @@ hipError_t launch_pad_in(const T *src, int64_t n, T *dst, int64_t npad, hipStrea
 template <typename T>
 hipError_t launch_pad_out(const T *src, int64_t npad, T *dst, int64_t n, hipStream_t s);
 
-// Kernel-class timing hooks (events around the last-phase launches).
+// Kernel-class timing hooks: events around the last-phase launches of kind
+// all / rest, with the algorithmic min-plus updates each performs.
 void prof_begin_p4(hipStream_t s);
-void prof_end_p4(hipStream_t s);
+void prof_end_p4(hipStream_t s, int64_t updates);
 
 }  // namespace fw

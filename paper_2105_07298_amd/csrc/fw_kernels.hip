@@ -7,7 +7,9 @@
 //   k_phase23  the row panel D[K, J] and the column panel D[I, K], as min-plus
 //              products with the closed diagonal block (no sequential k-steps);
 //   k_phase4   every other tile, a register-blocked min-plus product of the final
-//              column panel D[I, K] and row panel D[K, J], both staged in LDS.
+//              column panel D[I, K] and row panel D[K, J], both staged in LDS;
+//   k_phase4w  the same product with one row of the column panel per wave and
+//              k, read into scalar registers, and only the row panel in LDS.
 //
 // Path matrix: every candidate through k carries the label
 // (length, max(P[i][k], k, P[k][j])); an entry takes a candidate whose label is
@@ -27,6 +29,8 @@
 // All arithmetic is on the vector ALU: the min-plus product is not a ring
 // contraction, so matrix cores do not apply.
 #include "fw_internal.h"
+#define FW_TILE_FN __host__ __device__ __forceinline__
+#include "fw_tiles.h"
 
 #include <limits.h>
 
@@ -254,10 +258,6 @@ __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__re
 // never change and are never written.  Entries are stored only where they
 // changed, so panel entries are never written during this phase.
 //
-// Tile order: workgroups are spread round-robin over the 8 XCDs; each XCD gets a
-// contiguous range of tiles, walked in groups of 8 tile rows so that the
-// workgroups resident on one XCD share A and B panels in its L2.
-//
 // Path mode: before this round every label of a phase-4 entry is below
 // k0 = r*TB (its paths use interior vertices of earlier blocks only), and every
 // candidate through block r has a label of at least k0.  So a candidate that
@@ -266,9 +266,9 @@ __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__re
 // marked pending (L = r + 1) and resolved by k_resolve.  L is read with the old
 // tile and, for each 16-byte vector of D that changed, the matching run of L
 // (8 bytes for float, 4 for double) is written back whole.
-template <typename T, int TB, int BM, int BN, bool PATH>
+template <typename T, int TB, int BM, int BN, bool PATH, bool CROSS>
 __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__restrict__ L, int64_t ld, int r,
-                                              int gm, int gn, int skip_i, int skip_j, int per_xcd, int ntiles) {
+                                              TileSel sel) {
     constexpr int RM = BM / 16, RN = BN / 16;  // 16 x 16 threads
     using vec = typename V16<T>::type;
     constexpr int V = V16<T>::n;
@@ -284,21 +284,11 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
     __shared__ __attribute__((aligned(16))) T As[BM * AST];
     __shared__ __attribute__((aligned(16))) T Bs[TB * BN];
 
-    const int wg = blockIdx.x;
-    const int lin = (wg % 8) * per_xcd + wg / 8;
-    if (lin >= ntiles) return;
-    const int gm_e = gm - (skip_i >= 0), gn_e = gn - (skip_j >= 0);
-    constexpr int G = 8;
-    const int group = lin / (G * gn_e);
-    const int first = group * G;
-    const int rows_in = min(G, gm_e - first);
-    const int idx = lin - group * G * gn_e;
-    int bi = first + idx % rows_in, bj = idx / rows_in;
-    if (skip_i >= 0) bi += bi >= skip_i;
-    if (skip_j >= 0) bj += bj >= skip_j;
+    int bi, bj;
+    if (!select_tile<CROSS>(sel, blockIdx.x, bi, bj)) return;
     const int64_t I0 = (int64_t)bi * BM, J0 = (int64_t)bj * BN, k0 = (int64_t)r * TB;
-    const bool mask_rows = (I0 <= k0) && (k0 < I0 + BM);
-    const bool mask_cols = (J0 <= k0) && (k0 < J0 + BN);
+    const bool mask_rows = sel.nsr == 0 && (I0 <= k0) && (k0 < I0 + BM);
+    const bool mask_cols = sel.nsc == 0 && (J0 <= k0) && (k0 < J0 + BN);
 
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
     auto c_ptr = [&](int ii, int h) { return D + (I0 + ty + TY * ii) * ld + J0 + h * CS + tx * V; };
@@ -402,6 +392,108 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
                 }
             }
         }
+}
+
+// ---------------------------------------------------------------------------
+// Phase 4, wave-row form.  Same tiles, same result and the same path-mode
+// marks as k_phase4; only the data movement differs.  Wave w of the workgroup
+// owns RM consecutive rows of a BM x BN tile (BM = 4 * RM, which divides TB, so
+// whole tile rows of block row K are skipped), lane l the RN consecutive
+// columns from l * RN (BN = 64 * RN; a tile containing block column K masks it
+// in the staged panel, as k_phase4 does).  For a given row i and k, the
+// column-panel value D[i][k] is the same for all 64 lanes of the wave, so it is
+// read with scalar loads (the column panel lies in block column K, which this
+// launch never writes) and enters each addition as a scalar operand.  Only the
+// row panel D[K, J] is staged in LDS; per k each lane reads its RN entries of
+// it, 4 / RM bytes of LDS traffic per update for float (k_phase4's 4 x 4
+// register tiles need 2 bytes, which is all the LDS delivers at the VALU's
+// update rate).
+template <typename T, int TB, int RM, int RN, bool PATH, bool CROSS>
+__global__ void __launch_bounds__(NT) k_phase4w(T *__restrict__ D, uint16_t *__restrict__ L, int64_t ld, int r,
+                                               TileSel sel) {
+    constexpr int BM = (NT / 64) * RM, BN = 64 * RN;
+    static_assert(TB % BM == 0, "wave-row tiles must divide the block");
+    using vec = typename V16<T>::type;
+    constexpr int V = V16<T>::n;
+    static_assert(BN % V == 0, "row panel width");
+    typedef T cvec __attribute__((ext_vector_type(RN)));
+    typedef uint16_t lvec __attribute__((ext_vector_type(RN)));
+    typedef const T __attribute__((address_space(4))) CT;  // scalar (constant) loads
+    __shared__ __attribute__((aligned(16))) T Bs[TB * BN];
+
+    int bi, bj;
+    if (!select_tile<CROSS>(sel, blockIdx.x, bi, bj)) return;
+    const int64_t I0 = (int64_t)bi * BM, J0 = (int64_t)bj * BN, k0 = (int64_t)r * TB;
+    const bool mask_cols = sel.nsc == 0 && (J0 <= k0) && (k0 < J0 + BN);
+
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t i0 = I0 + (int64_t)wave * RM;
+    T *crow = D + i0 * ld + J0 + lane * RN;
+    uint16_t *lrow = L + (crow - D);
+
+    // Old C values (and marks) first, so their latency overlaps the staging.
+    cvec c[RM];
+    lvec lm[PATH ? RM : 1];
+#pragma unroll
+    for (int ii = 0; ii < RM; ++ii) {
+        c[ii] = *(const cvec *)(crow + ii * ld);
+        if constexpr (PATH) lm[ii] = *(const lvec *)(lrow + ii * ld);
+    }
+    const vec vinf = inf_v<T>();
+    for (int q = threadIdx.x; q < TB * (BN / V); q += NT) {
+        const int krow = q / (BN / V), cv = q % (BN / V);
+        vec v = *(const vec *)(D + (k0 + krow) * ld + J0 + cv * V);
+        if (mask_cols && (uint64_t)(J0 + cv * V - k0) < (uint64_t)TB) v = vinf;
+        *(vec *)(Bs + krow * BN + cv * V) = v;
+    }
+    __syncthreads();
+
+    T acc[RM][RN];
+#pragma unroll
+    for (int ii = 0; ii < RM; ++ii)
+#pragma unroll
+        for (int e = 0; e < RN; ++e) acc[ii][e] = inf_v<T>();
+    CT *A = (CT *)(D + i0 * ld + k0);
+    constexpr int KC = 16 / (int)sizeof(T);  // k per 16-byte scalar load of a row
+#pragma unroll 2
+    for (int kc = 0; kc < TB; kc += KC) {
+        T a[RM][KC];
+#pragma unroll
+        for (int ii = 0; ii < RM; ++ii)
+#pragma unroll
+            for (int kk = 0; kk < KC; ++kk) a[ii][kk] = A[ii * ld + kc + kk];
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += 2) {
+            const cvec b0 = *(const cvec *)(Bs + (kc + kk) * BN + lane * RN);
+            const cvec b1 = *(const cvec *)(Bs + (kc + kk + 1) * BN + lane * RN);
+#pragma unroll
+            for (int ii = 0; ii < RM; ++ii)
+#pragma unroll
+                for (int e = 0; e < RN; ++e)
+                    acc[ii][e] = vmin(vmin(acc[ii][e], a[ii][kk] + b0[e]), a[ii][kk + 1] + b1[e]);
+        }
+    }
+
+    // Store the rows of a lane in which some entry decreased; in path mode mark
+    // each decreased entry pending from this round.
+    const uint16_t pend = (uint16_t)(r + 1);
+#pragma unroll
+    for (int ii = 0; ii < RM; ++ii) {
+        cvec nv = c[ii];
+        lvec nl = lm[PATH ? ii : 0];
+        bool ch = false;
+#pragma unroll
+        for (int e = 0; e < RN; ++e) {
+            const bool lt = acc[ii][e] < nv[e];
+            ch |= lt;
+            nv[e] = lt ? acc[ii][e] : nv[e];
+            if constexpr (PATH) nl[e] = lt ? pend : nl[e];
+        }
+        if (ch) {
+            *(cvec *)(crow + ii * ld) = nv;
+            if constexpr (PATH) *(lvec *)(lrow + ii * ld) = nl;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -518,72 +610,155 @@ inline unsigned grid_for(int64_t n) {
     return (unsigned)(g < 8192 ? (g < 1 ? 1 : g) : 8192);
 }
 
-template <typename T, int TB, int BM, int BN>
-hipError_t round_impl(T *D, int32_t *P, uint16_t *L, int64_t ld, int r, hipStream_t s) {
+template <typename T, int TB>
+void launch_p123(T *D, int32_t *P, uint16_t *L, int64_t ld, int r, hipStream_t s) {
     const int nb = (int)(ld / TB);
     const bool path = P != nullptr;
     if (path)
         hipLaunchKernelGGL((k_phase1<T, TB, true>), dim3(1), dim3(P1_TS * P1_TS), 0, s, D, P, L, ld, r);
     else
         hipLaunchKernelGGL((k_phase1<T, TB, false>), dim3(1), dim3(P1_TS * P1_TS), 0, s, D, P, L, ld, r);
-    if (nb == 1) return hipGetLastError();
+    if (nb == 1) return;
     if (path)
         hipLaunchKernelGGL((k_phase23<T, TB, true>), dim3(2 * (nb - 1)), dim3(NT), 0, s, D, P, L, ld, r, nb);
     else
         hipLaunchKernelGGL((k_phase23<T, TB, false>), dim3(2 * (nb - 1)), dim3(NT), 0, s, D, P, L, ld, r, nb);
-    // A tile dimension equal to the block skips block row / column r entirely;
-    // a wider one masks it inside the tile that contains it.
-    const int gm = (int)(ld / BM), gn = (int)(ld / BN);
-    const int skip_i = (BM == TB) ? r : -1, skip_j = (BN == TB) ? r : -1;
-    const int gm_e = gm - (skip_i >= 0), gn_e = gn - (skip_j >= 0);
-    const int ntiles = gm_e * gn_e;
-    if (ntiles > 0) {
-        const int per = (ntiles + 7) / 8;
+}
+
+// One last-phase launch (mode all / rest / cross, see TileSel) with the
+// LDS-panel kernel (WAVE = false) or the wave-row kernel (BM = 4 * RM).
+template <typename T, int TB, int BM, int BN, bool WAVE>
+hipError_t p4_impl(T *D, uint16_t *L, bool path, int64_t ld, int r, P4Mode mode, hipStream_t s) {
+    const int rb = BM <= TB ? TB / BM : 0;  // tile rows per block; 0: the block row is masked
+    const int cb = BN == TB ? 1 : 0;        // likewise for columns
+    TileSel sel;
+    int64_t upd;
+    if (!make_tile_sel((int)(ld / BM), (int)(ld / BN), rb, cb, r, (int)(ld / TB), (int)mode, sel))
+        return hipErrorInvalidValue;
+    if (sel.ntiles == 0) return hipSuccess;
+    {
+        const int64_t w = mode == P4Mode::rest ? 2 : 1;
+        upd = (ld - w * TB) * (ld - w * TB) * TB;  // algorithmic min-plus updates (all / rest)
+    }
+    const dim3 grid(8 * sel.per_xcd);
+    constexpr int RM = BM / (NT / 64), RN = BN / 64;
+#define FW_P4_LAUNCH(PATHV, CROSSV)                                                                          \
+    do {                                                                                                  \
+        if constexpr (WAVE)                                                                               \
+            hipLaunchKernelGGL((k_phase4w<T, TB, RM, RN, PATHV, CROSSV>), grid, dim3(NT), 0, s, D, L, ld, r, sel); \
+        else                                                                                              \
+            hipLaunchKernelGGL((k_phase4<T, TB, BM, BN, PATHV, CROSSV>), grid, dim3(NT), 0, s, D, L, ld, r, sel);  \
+    } while (0)
+    if (mode == P4Mode::cross) {
+        if (path)
+            FW_P4_LAUNCH(true, true);
+        else
+            FW_P4_LAUNCH(false, true);
+    } else {
         prof_begin_p4(s);
         if (path)
-            hipLaunchKernelGGL((k_phase4<T, TB, BM, BN, true>), dim3(8 * per), dim3(NT), 0, s, D, L, ld, r, gm, gn,
-                               skip_i, skip_j, per, ntiles);
+            FW_P4_LAUNCH(true, false);
         else
-            hipLaunchKernelGGL((k_phase4<T, TB, BM, BN, false>), dim3(8 * per), dim3(NT), 0, s, D, L, ld, r, gm, gn,
-                               skip_i, skip_j, per, ntiles);
-        prof_end_p4(s);
+            FW_P4_LAUNCH(false, false);
+        prof_end_p4(s, upd);
     }
+#undef FW_P4_LAUNCH
     return hipGetLastError();
 }
 
 }  // namespace
 
-// Compiled (block, tile_m, tile_n) combinations.
+// Compiled (block, tile_m, tile_n) combinations: LDS-panel last phase ...
 #define FW_P4_CONFIGS_F32(X)                                                                           \
     X(32, 64, 64) X(32, 128, 64) X(32, 64, 128) X(32, 128, 128) X(64, 64, 64) X(64, 128, 64) X(64, 64, 128) \
     X(64, 128, 128)
 #define FW_P4_CONFIGS_F64(X) \
     X(32, 64, 64) X(32, 128, 64) X(32, 64, 128) X(32, 128, 128) X(64, 64, 64) X(64, 128, 64) X(64, 64, 128)
+// ... and wave-row last phase (tile_m = 4 x rows per wave, tile_n = 64 x columns per lane).
+#define FW_P4W_CONFIGS_F32(X)                                                                               \
+    X(32, 16, 256) X(32, 32, 128) X(32, 32, 256) X(64, 16, 256) X(64, 32, 128) X(64, 32, 256) X(64, 64, 128) \
+    X(64, 64, 256)
+#define FW_P4W_CONFIGS_F64(X) X(32, 16, 128) X(32, 32, 64) X(32, 32, 128) X(64, 32, 64) X(64, 32, 128) X(64, 64, 128)
 
 template <typename T>
 bool config_supported(TileCfg c) {
 #define FW_MATCH(B, M, N) if (c.block == B && c.tile_m == M && c.tile_n == N) return true;
-    if (sizeof(T) == 4) {
-        FW_P4_CONFIGS_F32(FW_MATCH)
-    } else {
-        FW_P4_CONFIGS_F64(FW_MATCH)
+    if (c.variant == FW_VARIANT_PANELS) {
+        if (sizeof(T) == 4) {
+            FW_P4_CONFIGS_F32(FW_MATCH)
+        } else {
+            FW_P4_CONFIGS_F64(FW_MATCH)
+        }
+    } else if (c.variant == FW_VARIANT_WAVEROWS) {
+        if (sizeof(T) == 4) {
+            FW_P4W_CONFIGS_F32(FW_MATCH)
+        } else {
+            FW_P4W_CONFIGS_F64(FW_MATCH)
+        }
     }
 #undef FW_MATCH
     return false;
 }
 
 template <typename T>
-hipError_t launch_round(T *D, int32_t *P, uint16_t *L, int64_t ld, int r, TileCfg c, hipStream_t s) {
-#define FW_DISPATCH(B, M, N) \
-    if (c.block == B && c.tile_m == M && c.tile_n == N) return round_impl<T, B, M, N>(D, P, L, ld, r, s);
+int list_configs(TileCfg *out, int cap) {
+    int k = 0;
+#define FW_PUT(B, M, N, VAR)                              \
+    {                                                     \
+        if (out && k < cap) out[k] = TileCfg{B, M, N, VAR}; \
+        ++k;                                              \
+    }
+#define FW_PUT_P(B, M, N) FW_PUT(B, M, N, FW_VARIANT_PANELS)
+#define FW_PUT_W(B, M, N) FW_PUT(B, M, N, FW_VARIANT_WAVEROWS)
     if constexpr (sizeof(T) == 4) {
-        FW_P4_CONFIGS_F32(FW_DISPATCH)
+        FW_P4_CONFIGS_F32(FW_PUT_P)
+        FW_P4W_CONFIGS_F32(FW_PUT_W)
     } else {
-        FW_P4_CONFIGS_F64(FW_DISPATCH)
+        FW_P4_CONFIGS_F64(FW_PUT_P)
+        FW_P4W_CONFIGS_F64(FW_PUT_W)
+    }
+#undef FW_PUT
+#undef FW_PUT_P
+#undef FW_PUT_W
+    return k;
+}
+
+template <typename T>
+hipError_t launch_phase123(T *D, int32_t *P, uint16_t *L, int64_t ld, int r, int block, hipStream_t s) {
+    if (block == 64)
+        launch_p123<T, 64>(D, P, L, ld, r, s);
+    else if (block == 32)
+        launch_p123<T, 32>(D, P, L, ld, r, s);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_phase4(T *D, uint16_t *L, bool path, int64_t ld, int r, TileCfg c, P4Mode mode, hipStream_t s) {
+#define FW_DISPATCH(B, M, N) \
+    if (c.block == B && c.tile_m == M && c.tile_n == N) return p4_impl<T, B, M, N, false>(D, L, path, ld, r, mode, s);
+#define FW_DISPATCH_W(B, M, N) \
+    if (c.block == B && c.tile_m == M && c.tile_n == N) return p4_impl<T, B, M, N, true>(D, L, path, ld, r, mode, s);
+    if (c.variant == FW_VARIANT_PANELS) {
+        if constexpr (sizeof(T) == 4) {
+            FW_P4_CONFIGS_F32(FW_DISPATCH)
+        } else {
+            FW_P4_CONFIGS_F64(FW_DISPATCH)
+        }
+    } else if (c.variant == FW_VARIANT_WAVEROWS) {
+        if constexpr (sizeof(T) == 4) {
+            FW_P4W_CONFIGS_F32(FW_DISPATCH_W)
+        } else {
+            FW_P4W_CONFIGS_F64(FW_DISPATCH_W)
+        }
     }
 #undef FW_DISPATCH
+#undef FW_DISPATCH_W
     return hipErrorInvalidValue;
 }
+
+bool lookahead_supported(TileCfg c) { return c.tile_n == c.block && c.tile_m <= c.block; }
 
 template <typename T>
 hipError_t launch_resolve(const T *D, T *DT, const uint16_t *L, int32_t *P, int64_t ld, int block, hipStream_t s) {
@@ -617,8 +792,12 @@ hipError_t launch_pad_out(const T *src, int64_t npad, T *dst, int64_t n, hipStre
 
 template bool config_supported<float>(TileCfg);
 template bool config_supported<double>(TileCfg);
-template hipError_t launch_round<float>(float *, int32_t *, uint16_t *, int64_t, int, TileCfg, hipStream_t);
-template hipError_t launch_round<double>(double *, int32_t *, uint16_t *, int64_t, int, TileCfg, hipStream_t);
+template int list_configs<float>(TileCfg *, int);
+template int list_configs<double>(TileCfg *, int);
+template hipError_t launch_phase123<float>(float *, int32_t *, uint16_t *, int64_t, int, int, hipStream_t);
+template hipError_t launch_phase123<double>(double *, int32_t *, uint16_t *, int64_t, int, int, hipStream_t);
+template hipError_t launch_phase4<float>(float *, uint16_t *, bool, int64_t, int, TileCfg, P4Mode, hipStream_t);
+template hipError_t launch_phase4<double>(double *, uint16_t *, bool, int64_t, int, TileCfg, P4Mode, hipStream_t);
 template hipError_t launch_resolve<float>(const float *, float *, const uint16_t *, int32_t *, int64_t, int, hipStream_t);
 template hipError_t launch_resolve<double>(const double *, double *, const uint16_t *, int32_t *, int64_t, int, hipStream_t);
 template hipError_t launch_pad_in<float>(const float *, int64_t, float *, int64_t, hipStream_t);

@@ -15,6 +15,9 @@
 #include "../../include/fw_apsp.h"
 #include "fw_internal.h"
 
+static_assert(fw::FW_VARIANT_PANELS == FW_P4_PANELS && fw::FW_VARIANT_WAVEROWS == FW_P4_WAVEROWS,
+              "variant codes of the C ABI");
+
 namespace {
 
 thread_local char g_err[512] = "";
@@ -37,7 +40,11 @@ fw_status_t hip_fail(hipError_t e, const char *what) {
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<hipEvent_t> g_ev_pool;
-std::vector<std::pair<hipEvent_t, hipEvent_t>> g_ev_used;
+struct ProfRec {
+    hipEvent_t begin, end;
+    int64_t updates;
+};
+std::vector<ProfRec> g_ev_used;
 hipEvent_t g_pending = nullptr;
 
 hipEvent_t take_event() {
@@ -61,17 +68,94 @@ void *g_stage = nullptr;
 size_t g_stage_cap = 0;
 hipEvent_t g_stage_ev = nullptr;
 
-struct TuneEntry { int f64, path; long long n_lo, n_hi; int block, tile_m, tile_n; };
+struct TuneEntry { int f64, path; long long n_lo, n_hi; int block, tile_m, tile_n, variant; };
 struct TuneBatchedEntry { int f64, path, small_max_n; };
 #include "tune_table.inc"
 
 fw::TileCfg default_cfg(fw_dtype_t dt, int64_t n, bool path) { return fw::tuned_config(dt == FW_F64, path, n); }
 
+// ---- lookahead ---------------------------------------------------------------
+// Phases 1-3 of round r + 1 only read and write block row and column r + 1,
+// which the last phase of round r finishes first (a small "cross" launch).  They
+// then run on an auxiliary stream while the rest of round r's last phase runs on
+// the caller's stream; the caller's stream waits for them before round r + 1's
+// last phase.  The auxiliary streams (default priority, non-blocking) and their
+// two events are kept per device and reused; one call holds one at a time.
+struct Aux {
+    int dev;
+    hipStream_t st;
+    hipEvent_t to_aux, to_main;
+    bool busy;
+};
+std::mutex g_aux_mu;
+std::vector<Aux *> g_aux;  // never freed: streams live until the process ends
+
+Aux *acquire_aux(int dev) {
+    std::lock_guard<std::mutex> lk(g_aux_mu);
+    for (Aux *a : g_aux)
+        if (a->dev == dev && !a->busy) {
+            a->busy = true;
+            return a;
+        }
+    Aux tmp{dev, nullptr, nullptr, nullptr, true};
+    if (hipStreamCreateWithFlags(&tmp.st, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&tmp.to_aux, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&tmp.to_main, hipEventDisableTiming) != hipSuccess) {
+        (void)hipStreamDestroy(tmp.st);
+        return nullptr;
+    }
+    g_aux.push_back(new Aux(tmp));
+    return g_aux.back();
+}
+
+void release_aux(Aux *a) {
+    std::lock_guard<std::mutex> lk(g_aux_mu);
+    a->busy = false;
+}
+
+// Rounds with lookahead need at least 3 blocks (else there is nothing to overlap).
+constexpr int kLookaheadMinRounds = 3;
+
+template <typename T>
+hipError_t run_rounds(T *D, int32_t *P, uint16_t *L, int64_t ld, fw::TileCfg cfg, hipStream_t s) {
+    using fw::P4Mode;
+    const int R = (int)(ld / cfg.block);
+    hipError_t e;
+    int dev = -1;
+    Aux *aux = nullptr;
+    if (R >= kLookaheadMinRounds && fw::lookahead_supported(cfg) && hipGetDevice(&dev) == hipSuccess)
+        aux = acquire_aux(dev);
+    if (!aux) {
+        for (int r = 0; r < R; ++r) {
+            if ((e = fw::launch_phase123<T>(D, P, L, ld, r, cfg.block, s)) != hipSuccess) return e;
+            if ((e = fw::launch_phase4<T>(D, L, P != nullptr, ld, r, cfg, P4Mode::all, s)) != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    e = fw::launch_phase123<T>(D, P, L, ld, 0, cfg.block, s);
+    for (int r = 0; r < R && e == hipSuccess; ++r) {
+        if (r + 1 == R) {
+            e = fw::launch_phase4<T>(D, L, P != nullptr, ld, r, cfg, P4Mode::all, s);
+            break;
+        }
+        if ((e = fw::launch_phase4<T>(D, L, P != nullptr, ld, r, cfg, P4Mode::cross, s)) != hipSuccess) break;
+        if ((e = hipEventRecord(aux->to_aux, s)) != hipSuccess) break;
+        if ((e = hipStreamWaitEvent(aux->st, aux->to_aux, 0)) != hipSuccess) break;
+        if ((e = fw::launch_phase123<T>(D, P, L, ld, r + 1, cfg.block, aux->st)) != hipSuccess) break;
+        if ((e = hipEventRecord(aux->to_main, aux->st)) != hipSuccess) break;
+        if ((e = fw::launch_phase4<T>(D, L, P != nullptr, ld, r, cfg, P4Mode::rest, s)) != hipSuccess) break;
+        e = hipStreamWaitEvent(s, aux->to_main, 0);
+    }
+    release_aux(aux);
+    return e;
+}
+
 template <typename T>
 fw_status_t run_apsp(int64_t n, T *dist, int32_t *path, fw::TileCfg cfg, hipStream_t s) {
     if (!fw::config_supported<T>(cfg))
-        return fail(FW_EUNSUPPORTED, "block %d / tile %d x %d not compiled in", cfg.block, cfg.tile_m, cfg.tile_n);
-    const int64_t unit = cfg.tile_m > cfg.tile_n ? cfg.tile_m : cfg.tile_n;
+        return fail(FW_EUNSUPPORTED, "block %d / tile %d x %d / variant %d not compiled in", cfg.block, cfg.tile_m,
+                    cfg.tile_n, cfg.variant);
+    const int64_t unit = std::max(cfg.block, std::max(cfg.tile_m, cfg.tile_n));  // powers of two
     const int64_t npad = (n + unit - 1) / unit * unit;
     const bool aligned = ((uintptr_t)dist % 16 == 0) && (path == nullptr || (uintptr_t)path % 16 == 0);
     hipError_t e;
@@ -99,9 +183,7 @@ fw_status_t run_apsp(int64_t n, T *dist, int32_t *path, fw::TileCfg cfg, hipStre
         L = (uint16_t *)ps;
         if ((e = fw::launch_fill_i32((int32_t *)L, npad * npad / 2, 0, s)) != hipSuccess) return hip_fail(e, "mark init");
     }
-    const int R = (int)(npad / cfg.block);
-    for (int r = 0; r < R; ++r)
-        if ((e = fw::launch_round<T>(D, P, L, npad, r, cfg, s)) != hipSuccess) return hip_fail(e, "round launch");
+    if ((e = run_rounds<T>(D, P, L, npad, cfg, s)) != hipSuccess) return hip_fail(e, "round launch");
     if (P) {
         e = fw::launch_resolve<T>(D, (T *)((char *)ps + lbytes), L, P, npad, cfg.block, s);
         hipError_t e2 = hipFreeAsync(ps, s);
@@ -128,8 +210,9 @@ fw_status_t check_common(fw_dtype_t dt, int64_t n, const void *dist) {
 namespace fw {
 TileCfg tuned_config(bool f64, bool path, int64_t n) {
     for (const TuneEntry &t : kTuneApsp)
-        if (t.f64 == (int)f64 && t.path == (int)path && n >= t.n_lo && n < t.n_hi) return {t.block, t.tile_m, t.tile_n};
-    return {64, 64, 64};
+        if (t.f64 == (int)f64 && t.path == (int)path && n >= t.n_lo && n < t.n_hi)
+            return {t.block, t.tile_m, t.tile_n, t.variant};
+    return {64, 64, 64, FW_VARIANT_PANELS};
 }
 int tuned_batched_small_max_n(bool f64, bool path) {
     for (const TuneBatchedEntry &t : kTuneBatched)
@@ -143,14 +226,14 @@ void prof_begin_p4(hipStream_t s) {
     g_pending = take_event();
     if (g_pending) (void)hipEventRecord(g_pending, s);
 }
-void prof_end_p4(hipStream_t s) {
+void prof_end_p4(hipStream_t s, int64_t updates) {
     if (!g_prof_on) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (!g_pending) return;
     hipEvent_t e = take_event();
     if (!e) return;
     (void)hipEventRecord(e, s);
-    g_ev_used.push_back({g_pending, e});
+    g_ev_used.push_back({g_pending, e, updates});
     g_pending = nullptr;
 }
 }  // namespace fw
@@ -163,13 +246,17 @@ fw_status_t fw_apsp_config(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, 
     if (st != FW_OK) return st;
     fw::TileCfg tc = default_cfg(dt, n, path != nullptr);
     if (cfg) {
-        if (cfg->reserved) return fail(FW_EINVAL, "reserved config field must be 0");
+        if (cfg->block < 0 || cfg->tile_m < 0 || cfg->tile_n < 0 || cfg->variant < 0 ||
+            cfg->variant > FW_P4_WAVEROWS)
+            return fail(FW_EINVAL, "config fields must be 0 (tuned) or positive, variant at most %d", FW_P4_WAVEROWS);
         if (cfg->block) tc.block = cfg->block;
         if (cfg->tile_m) tc.tile_m = cfg->tile_m;
         if (cfg->tile_n) tc.tile_n = cfg->tile_n;
-        if (tc.block <= 0 || tc.tile_m <= 0 || tc.tile_n <= 0 || tc.tile_m % tc.block || tc.tile_n % tc.block)
-            return fail(FW_EINVAL, "tile edges must be multiples of block");
+        if (cfg->variant) tc.variant = cfg->variant;
     }
+    if (!(dt == FW_F32 ? fw::config_supported<float>(tc) : fw::config_supported<double>(tc)))
+        return fail(FW_EUNSUPPORTED, "block %d / tile %d x %d / variant %d not compiled in", tc.block, tc.tile_m,
+                    tc.tile_n, tc.variant);
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -187,8 +274,20 @@ fw_status_t fw_query_config(fw_dtype_t dt, int64_t n, int32_t path, fw_config_t 
     out->block = c.block;
     out->tile_m = c.tile_m;
     out->tile_n = c.tile_n;
-    out->reserved = 0;
+    out->variant = c.variant;
     return FW_OK;
+}
+
+int32_t fw_list_configs(fw_dtype_t dt, fw_config_t *out, int32_t cap) {
+    g_err[0] = 0;
+    if (dt != FW_F32 && dt != FW_F64) return fail(FW_EINVAL, "unknown dtype %d", (int)dt);
+    if (cap < 0 || (cap > 0 && !out)) return fail(FW_EINVAL, "out must hold cap >= 0 entries");
+    std::vector<fw::TileCfg> all((size_t)(dt == FW_F32 ? fw::list_configs<float>(nullptr, 0)
+                                                       : fw::list_configs<double>(nullptr, 0)));
+    const int total = dt == FW_F32 ? fw::list_configs<float>(all.data(), (int)all.size())
+                                   : fw::list_configs<double>(all.data(), (int)all.size());
+    for (int k = 0; k < total && k < cap; ++k) out[k] = {all[k].block, all[k].tile_m, all[k].tile_n, all[k].variant};
+    return total;
 }
 
 fw_status_t fw_apsp(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, void *stream) {
@@ -298,30 +397,32 @@ const char *fw_last_error(void) { return g_err; }
 const char *fw_version(void) { return "fwapsp 0.1 gfx950"; }
 
 // Timing hooks for the benchmark: enable/disable bracketing of last-phase
-// launches with events, and read (count, summed milliseconds) since the last
-// reset.  fw_prof_read synchronizes on the recorded events.
+// launches with events, and read (count, summed milliseconds, summed updates)
+// since the last reset.  fw_prof_read synchronizes on the recorded events.
 void fw_prof_enable(int on) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_on = on != 0;
 }
 
-int fw_prof_read(int64_t *count, double *total_ms, int reset) {
+int fw_prof_read(int64_t *count, double *total_ms, int64_t *updates, int reset) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     double tot = 0.0;
-    int64_t cnt = 0;
+    int64_t cnt = 0, upd = 0;
     for (auto &pr : g_ev_used) {
-        if (hipEventSynchronize(pr.second) != hipSuccess) return FW_EHIP;
+        if (hipEventSynchronize(pr.end) != hipSuccess) return FW_EHIP;
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, pr.first, pr.second) != hipSuccess) return FW_EHIP;
+        if (hipEventElapsedTime(&ms, pr.begin, pr.end) != hipSuccess) return FW_EHIP;
         tot += ms;
+        upd += pr.updates;
         ++cnt;
     }
     if (count) *count = cnt;
     if (total_ms) *total_ms = tot;
+    if (updates) *updates = upd;
     if (reset) {
         for (auto &pr : g_ev_used) {
-            g_ev_pool.push_back(pr.first);
-            g_ev_pool.push_back(pr.second);
+            g_ev_pool.push_back(pr.begin);
+            g_ev_pool.push_back(pr.end);
         }
         g_ev_used.clear();
     }

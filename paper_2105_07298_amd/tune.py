@@ -4,7 +4,7 @@ table compiled into the library).
 
 Run on the GPU:  python -m paper_2105_07298_amd.tune --out DIR
 It times, with HIP events on the current stream,
-  * fw_apsp for every compiled (block, tile_m, tile_n) at one representative n per size
+  * fw_apsp for every compiled (block, tile_m, tile_n, variant) at one representative n per size
     range, for float32/float64 with and without the path matrix, on complete
     graphs with weights uniform in (0, 1);
   * fw_apsp_batched on batches of equal-size graphs (weights in [1, 10],
@@ -23,10 +23,6 @@ import os
 import sys
 import time
 
-CONFIGS = {"f32": [(32, 64, 64), (32, 128, 64), (32, 64, 128), (32, 128, 128),
-                   (64, 64, 64), (64, 128, 64), (64, 64, 128), (64, 128, 128)],
-           "f64": [(32, 64, 64), (32, 128, 64), (32, 64, 128), (32, 128, 128),
-                   (64, 64, 64), (64, 128, 64), (64, 64, 128)]}
 # size ranges [lo, hi) of the table and the n timed for each
 BUCKETS = [(0, 512, 256), (512, 2048, 1024), (2048, 8192, 4096), (8192, 1 << 40, 16384)]
 BATCHED_N = [16, 24, 32, 48, 64, 80, 96, 128, 160, 192, 256, 320, 384, 512]
@@ -57,19 +53,20 @@ def tune_apsp(fw, torch, log):
             for path in (False, True):
                 P = torch.empty((n, n), dtype=torch.int32, device=W.device) if path else None
                 best = None
-                for block, tm, tn in CONFIGS[dt]:
+                for block, tm, tn, var in fw.fw_list_configs(fw.FW_F32 if dt == "f32" else fw.FW_F64):
                     def run():
                         D.copy_(W)
-                        fw.apsp_(D, P, block=block, tile_m=tm, tile_n=tn)
+                        fw.apsp_(D, P, block=block, tile_m=tm, tile_n=tn, variant=var)
                     reps = 2 if n >= 8192 else 5
                     ms = _timeit(run, torch, reps)
                     log.append({"kind": "apsp", "dtype": dt, "path": path, "n": n, "block": block, "tile_m": tm,
-                                "tile_n": tn, "ms": round(ms, 4)})
-                    print(f"apsp {dt} path={path} n={n} block={block} tile={tm}x{tn}: {ms:.3f} ms", flush=True)
+                                "tile_n": tn, "variant": var, "ms": round(ms, 4)})
+                    print(f"apsp {dt} path={path} n={n} block={block} tile={tm}x{tn} variant={var}: {ms:.3f} ms",
+                          flush=True)
                     if best is None or ms < best[0]:
-                        best = (ms, block, tm, tn)
+                        best = (ms, block, tm, tn, var)
                 table.append({"f64": dt == "f64", "path": path, "n_lo": lo, "n_hi": hi,
-                              "block": best[1], "tile_m": best[2], "tile_n": best[3]})
+                              "block": best[1], "tile_m": best[2], "tile_n": best[3], "variant": best[4]})
             del W, D
             torch.cuda.empty_cache()
     return table
@@ -118,7 +115,7 @@ def write_inc(path, apsp_table, batched_table, arch):
     lines = [
         "// Tile configuration table.  Generated by paper_2105_07298_amd/tune.py from",
         f"// timings on {arch} (do not edit by hand; rerun the tuner instead).",
-        "// fw_apsp:          {f64, path, n_lo, n_hi, block, tile_m, tile_n}  for n_lo <= n < n_hi",
+        "// fw_apsp:          {f64, path, n_lo, n_hi, block, tile_m, tile_n, variant}  for n_lo <= n < n_hi",
         "// fw_apsp_batched:  {f64, path, small_max_n}",
         f"// generated {time.strftime('%Y-%m-%d')}",
         "static const TuneEntry kTuneApsp[] = {",
@@ -126,7 +123,7 @@ def write_inc(path, apsp_table, batched_table, arch):
     for t in apsp_table:
         hi = "1LL << 40" if t["n_hi"] >= (1 << 40) else str(t["n_hi"])
         lines.append(f"    {{{int(t['f64'])}, {int(t['path'])}, {t['n_lo']}, {hi}, {t['block']}, {t['tile_m']}, "
-                     f"{t['tile_n']}}},")
+                     f"{t['tile_n']}, {t['variant']}}},")
     lines.append("};")
     lines.append("static const TuneBatchedEntry kTuneBatched[] = {")
     for t in batched_table:

@@ -60,19 +60,41 @@ def test_invalid_arguments(fw, args):
 
 def test_invalid_config(fw):
     L = fw.lib()
-    cfg = fw._lib.FwConfig(64, 96, 64, 0)  # tile not a multiple of block
-    assert L.fw_apsp_config(0, 128, 4096, None, ctypes.byref(cfg), None) == fw.FW_EINVAL
-    cfg = fw._lib.FwConfig(64, 128, 128, 1)  # reserved field set
-    assert L.fw_apsp_config(0, 128, 4096, None, ctypes.byref(cfg), None) == fw.FW_EINVAL
+    for bad in ((64, 96, 64, 1),     # tile edge not compiled
+                (64, 32, 256, 1),    # a wave-row tile asked of the LDS-panel kernel
+                (64, 128, 128, 2),   # an LDS-panel tile asked of the wave-row kernel
+                (32, 64, 128, 2)):   # wave-row tile rows must divide the block
+        cfg = fw._lib.FwConfig(*bad)
+        assert L.fw_apsp_config(0, 128, 4096, None, ctypes.byref(cfg), None) == fw.FW_EUNSUPPORTED, bad
+        assert "not compiled in" in fw.fw_last_error()
+    for bad in ((64, 64, 64, 3), (-1, 64, 64, 1), (64, 64, -64, 0)):
+        cfg = fw._lib.FwConfig(*bad)
+        assert L.fw_apsp_config(0, 128, 4096, None, ctypes.byref(cfg), None) == fw.FW_EINVAL, bad
+
+
+def test_list_configs(fw):
+    for dt in (0, 1):
+        cfgs = fw.fw_list_configs(dt)
+        assert len(cfgs) == len(set(cfgs)) >= 10
+        assert {c[3] for c in cfgs} == {fw.FW_P4_PANELS, fw.FW_P4_WAVEROWS}
+        for b, tm, tn, var in cfgs:
+            assert b in (32, 64)
+            if var == fw.FW_P4_PANELS:
+                assert tm in (64, 128) and tn in (64, 128) and tm % b == 0 and tn % b == 0
+            else:
+                assert b % tm == 0 and tm % 4 == 0 and tn in (64, 128, 256)
+                if dt == 1:
+                    assert tn <= 128  # 16-byte lane vectors hold 2 doubles
+    assert fw.lib().fw_list_configs(7, None, 0) == fw.FW_EINVAL
+    assert fw.lib().fw_list_configs(0, None, 3) == fw.FW_EINVAL
 
 
 def test_query_config(fw):
     for dt in (0, 1):
+        compiled = set(fw.fw_list_configs(dt))
         for n in (1, 100, 1000, 5000, 16384, 65536):
             for path in (False, True):
-                b, tm, tn = fw.fw_query_config(dt, n, path)
-                assert b in (32, 64) and tm in (64, 128) and tn in (64, 128)
-                assert tm % b == 0 and tn % b == 0
+                assert fw.fw_query_config(dt, n, path) in compiled
 
 
 @pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="a GPU is present: would launch on a bogus pointer")

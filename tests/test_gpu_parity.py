@@ -15,10 +15,11 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-CONFIGS = {np.float32: [(32, 64, 64), (32, 128, 64), (32, 64, 128), (32, 128, 128),
-                        (64, 64, 64), (64, 128, 64), (64, 64, 128), (64, 128, 128)],
-           np.float64: [(32, 64, 64), (32, 128, 64), (32, 64, 128), (32, 128, 128),
-                        (64, 64, 64), (64, 128, 64), (64, 64, 128)]}
+
+
+def compiled_configs(dtype):
+    import paper_2105_07298_amd as fw
+    return fw.fw_list_configs(fw.FW_F32 if dtype == np.float32 else fw.FW_F64)
 
 
 @pytest.fixture(scope="module")
@@ -30,13 +31,13 @@ def dev():
     return torch.device("cuda:0")
 
 
-def run_gpu(W, dev, path=True, block=0, tile=(0, 0), case=""):
+def run_gpu(W, dev, path=True, block=0, tile=(0, 0), variant=0, case=""):
     import torch
     import paper_2105_07298_amd as fw
-    print(f"[gpu] fw_apsp {case} n={W.shape[0]} dtype={W.dtype} path={path} block={block} tile={tile}",
-          flush=True)
+    print(f"[gpu] fw_apsp {case} n={W.shape[0]} dtype={W.dtype} path={path} block={block} tile={tile} "
+          f"variant={variant}", flush=True)
     D, P = fw.apsp(torch.from_numpy(np.ascontiguousarray(W)).to(dev), path=path, block=block,
-                   tile_m=tile[0], tile_n=tile[1])
+                   tile_m=tile[0], tile_n=tile[1], variant=variant)
     torch.cuda.synchronize()
     return D.cpu().numpy(), (P.cpu().numpy() if P is not None else None)
 
@@ -77,8 +78,8 @@ def test_block_and_tile_invariance_tie_heavy(dev, dtype):
     W = workloads.int_graph(n=448, p=0.02, wmax=3, seed=21, dtype=dtype)
     Do, Po = oracle.fw(W)
     assert (Po >= 0).mean() > 0.5
-    for block, tm, tn in CONFIGS[dtype]:
-        Dg, Pg = run_gpu(W, dev, block=block, tile=(tm, tn), case="tie-heavy")
+    for block, tm, tn, var in compiled_configs(dtype):
+        Dg, Pg = run_gpu(W, dev, block=block, tile=(tm, tn), variant=var, case="tie-heavy")
         assert_exact(W, Dg, Pg, Do, Po)
 
 
@@ -174,6 +175,27 @@ def test_c2_4096_full_matrix(dev, dtype, tol):
     print(f"max relative error {err:.3e}", flush=True)
     assert err <= tol
     oracle.check_invariants(W, Dg, Pg, exact=False, rtol=max(tol, 1e-7), nsample=3000)
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float32, 1e-5), (np.float64, 1e-12)])
+def test_configs_real_weights(dev, dtype, tol):
+    """Complete graph, weights in (0, 1), n = 700 (pads to several tiles of every
+    shape, with a ragged last block): every compiled configuration is within the
+    tolerance of the float64 oracle, and those that share a block size agree bit
+    for bit (for each entry they form the minimum of the same float sums; only
+    the tile shape or the last-phase kernel differs)."""
+    W = workloads.unit_complete(700, dtype=dtype, seed=9)
+    Do, _ = oracle.fw(W, exact=False)
+    first = {}
+    for block, tm, tn, var in compiled_configs(dtype):
+        Dg, Pg = run_gpu(W, dev, block=block, tile=(tm, tn), variant=var, case="real-weights")
+        assert rel_err(Dg, Do) <= tol
+        if block not in first:
+            first[block] = (Dg, Pg)
+            oracle.check_invariants(W, Dg, Pg, exact=False, rtol=max(tol, 1e-7), nsample=1000)
+        else:
+            np.testing.assert_array_equal(Dg, first[block][0])
+            np.testing.assert_array_equal(Pg, first[block][1])
 
 
 @pytest.mark.parametrize("dtype,tol", [(np.float32, 1e-5), (np.float64, 1e-12)])

@@ -15,15 +15,15 @@ def entries():
     for m in re.finditer(r"\{([^{}]*)\}", apsp):
         f = [x.strip() for x in m.group(1).split(",")]
         hi = (1 << 40) if "<<" in f[3] else int(f[3])
-        rows.append((int(f[0]), int(f[1]), int(f[2]), hi, int(f[4]), int(f[5]), int(f[6])))
+        rows.append((int(f[0]), int(f[1]), int(f[2]), hi, int(f[4]), int(f[5]), int(f[6]), int(f[7])))
     brows = [tuple(int(x) for x in m.group(1).split(",")) for m in re.finditer(r"\{([^{}]*)\}", batched)]
     return rows, brows
 
 
 def test_apsp_table_covers_every_size_once():
+    import paper_2105_07298_amd as fw
     rows, _ = entries()
-    supported = {0: {(b, m, n) for b in (32, 64) for m in (64, 128) for n in (64, 128)},
-                 1: {(b, m, n) for b in (32, 64) for m in (64, 128) for n in (64, 128)} - {(64, 128, 128)}}
+    supported = {f64: set(fw.fw_list_configs(f64)) for f64 in (0, 1)}
     for f64 in (0, 1):
         for path in (0, 1):
             rs = sorted((r for r in rows if r[0] == f64 and r[1] == path), key=lambda r: r[2])
@@ -32,7 +32,7 @@ def test_apsp_table_covers_every_size_once():
             for a, b in zip(rs[:-1], rs[1:]):
                 assert a[3] == b[2], "size ranges must tile [0, inf)"
             for r in rs:
-                assert (r[4], r[5], r[6]) in supported[f64], r
+                assert (r[4], r[5], r[6], r[7]) in supported[f64], r
 
 
 def test_batched_table_complete():
