@@ -58,18 +58,18 @@ def gflops(n, seconds):
 
 def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False, config=None):
     """Mean seconds per fw_apsp step (D <- W, P <- -1, all rounds) and last-phase stats.
-    config: (block, tile_m, tile_n, variant), default the tuned choice."""
+    config: (block, tile_m, tile_n, variant, schedule), default the tuned choice."""
     import numpy as np
     import workloads
     npdt = np.float32 if dtype == "f32" else np.float64
-    block, tm, tn, var = config or fw.fw_query_config(fw.FW_F32 if dtype == "f32" else fw.FW_F64, n, path)
+    block, tm, tn, var, sch = config or fw.fw_query_config(fw.FW_F32 if dtype == "f32" else fw.FW_F64, n, path)
     Wd = torch.from_numpy(workloads.unit_complete(n, dtype=npdt, seed=2)).cuda()
     D = torch.empty_like(Wd)
     P = torch.empty((n, n), dtype=torch.int32, device=Wd.device) if path else None
 
     def step():
         D.copy_(Wd)
-        fw.apsp_(D, P, block=block, tile_m=tm, tile_n=tn, variant=var)
+        fw.apsp_(D, P, block=block, tile_m=tm, tile_n=tn, variant=var, schedule=sch)
 
     for _ in range(warmup):
         step()
@@ -90,7 +90,7 @@ def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False, config=None)
         fw.fw_prof_enable(False)
         cnt, tot_ms, upd = fw.fw_prof_read(reset=True)
         stats = {"launches": cnt, "mean_ms": tot_ms / max(cnt, 1), "block": block, "tile": [tm, tn],
-                 "variant": var, "updates_per_launch": upd / max(cnt, 1)}
+                 "variant": var, "schedule": sch, "updates_per_launch": upd / max(cnt, 1)}
     del Wd, D, P
     torch.cuda.empty_cache()
     return sec, stats
@@ -223,7 +223,7 @@ def main():
     ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
     ap.add_argument("--no-path", action="store_true", help="distances only (P = NULL)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--config", default="", help="block,tile_m,tile_n,variant instead of the tuned choice")
+    ap.add_argument("--config", default="", help="block,tile_m,tile_n,variant,schedule instead of the tuned choice")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, one device copy of this many MiB (HBM counter calibration)")

@@ -74,19 +74,35 @@ fw_status_t fw_apsp(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, void *s
  *                            tile_m divides block; tile_n = 64 x columns per
  *                            lane (64 to 256).
  *   tile_m x tile_n  the output tile one workgroup updates in the last phase.
+ *   schedule FW_SCHED_SERIAL: the three phases of each round one after the
+ *            other on the caller's stream.  FW_SCHED_LOOKAHEAD (tiles one
+ *            block wide, tile_m dividing block, at least 3 rounds; otherwise
+ *            serial): block row and column r + 1 of round r's last phase and
+ *            then phases 1-3 of round r + 1 run on an auxiliary stream of the
+ *            library, concurrently with the rest of round r's last phase on
+ *            the caller's stream, which waits for them before round r + 1.
+ *            The call stays stream-ordered on the caller's stream.
  * Fields set to 0 keep the tuned choice (a table of timings on gfx950 per
  * element type, path mode and size range).  The resulting combination must be
  * one the library compiles (fw_apsp_config returns FW_EUNSUPPORTED otherwise).
  */
 enum { FW_P4_PANELS = 1, FW_P4_WAVEROWS = 2 };
-typedef struct { int32_t block; int32_t tile_m; int32_t tile_n; int32_t variant; } fw_config_t;
+enum { FW_SCHED_SERIAL = 1, FW_SCHED_LOOKAHEAD = 2 };
+typedef struct {
+    int32_t block;
+    int32_t tile_m;
+    int32_t tile_n;
+    int32_t variant;
+    int32_t schedule;
+} fw_config_t;
 
 /* fw_apsp with an explicit configuration (cfg may be NULL = library choice).
  * FW_EUNSUPPORTED if the combination is not compiled in. */
 fw_status_t fw_apsp_config(fw_dtype_t dt, int64_t n, void *dist, int32_t *path,
                            const fw_config_t *cfg, void *stream);
 
-/* Every configuration compiled in for dt: writes the first min(cap, count)
+/* Every (block, tile_m, tile_n, variant) compiled in for dt, with schedule 0
+ * (either schedule runs with any of them): writes the first min(cap, count)
  * to out (host memory; may be NULL when cap is 0) and returns count, or
  * FW_EINVAL (negative) for a bad dtype or cap.  Host only; launches nothing. */
 int32_t fw_list_configs(fw_dtype_t dt, fw_config_t *out, int32_t cap);

@@ -9,9 +9,9 @@ PyTorch provides device memory and streams only; no step of the method runs in i
 from __future__ import annotations
 
 from ._lib import (FW_EHIP, FW_EINVAL, FW_ENOMEM, FW_EUNSUPPORTED, FW_F32, FW_F64, FW_OK,  # noqa: F401
-                   FW_P4_PANELS, FW_P4_WAVEROWS, FwError, fw_apsp, fw_apsp_backward, fw_apsp_batched,
+                   FW_P4_PANELS, FW_P4_WAVEROWS, FW_SCHED_LOOKAHEAD, FW_SCHED_SERIAL, FwError, fw_apsp, fw_apsp_backward, fw_apsp_batched,
                    fw_apsp_batched_config, fw_apsp_config, fw_last_error, fw_list_configs, fw_prof_enable,
-                   fw_prof_read, fw_query_config, fw_status_string, fw_version, lib)
+                   fw_prof_read, fw_query_config, fw_status_string, fw_version, lib, lookahead_applies)
 
 
 def _dtype_code(t):
@@ -28,14 +28,15 @@ def _stream_ptr(device):
     return torch.cuda.current_stream(device).cuda_stream
 
 
-def apsp_(D, P=None, block: int = 0, tile_m: int = 0, tile_n: int = 0, variant: int = 0):
+def apsp_(D, P=None, block: int = 0, tile_m: int = 0, tile_n: int = 0, variant: int = 0, schedule: int = 0):
     """In-place APSP of the square device tensor D (float32/float64, contiguous).
 
     D holds the weight matrix (0 diagonal, +inf = no edge) and is overwritten with
     shortest distances; P (int32, same shape) receives the path matrix if given.
-    Runs on the current stream of D's device.  block / tile_m / tile_n / variant
-    override the tuned configuration (0 = tuned; variant FW_P4_PANELS or
-    FW_P4_WAVEROWS picks the last-phase kernel).
+    Runs on the current stream of D's device.  block / tile_m / tile_n / variant /
+    schedule override the tuned configuration (0 = tuned; variant FW_P4_PANELS or
+    FW_P4_WAVEROWS picks the last-phase kernel, schedule FW_SCHED_SERIAL or
+    FW_SCHED_LOOKAHEAD the round schedule).
     """
     import torch
     if not (D.is_cuda and D.dim() == 2 and D.shape[0] == D.shape[1] and D.is_contiguous()):
@@ -46,17 +47,19 @@ def apsp_(D, P=None, block: int = 0, tile_m: int = 0, tile_n: int = 0, variant: 
         if not (P.is_cuda and P.dtype == torch.int32 and P.shape == D.shape and P.is_contiguous()):
             raise ValueError("P must be a contiguous int32 device tensor shaped like D")
         pp = P.data_ptr()
-    fw_apsp_config(_dtype_code(D), n, D.data_ptr(), pp, block, tile_m, tile_n, variant, _stream_ptr(D.device))
+    fw_apsp_config(_dtype_code(D), n, D.data_ptr(), pp, block, tile_m, tile_n, variant, schedule,
+                   _stream_ptr(D.device))
     return D, P
 
 
-def apsp(W, path: bool = True, block: int = 0, tile_m: int = 0, tile_n: int = 0, variant: int = 0):
+def apsp(W, path: bool = True, block: int = 0, tile_m: int = 0, tile_n: int = 0, variant: int = 0,
+         schedule: int = 0):
     """Return (D, P) for the weight matrix W (device tensor; W is not modified).
     P is None when path=False."""
     import torch
     D = W.contiguous().clone()
     P = torch.empty(D.shape, dtype=torch.int32, device=D.device) if path else None
-    return apsp_(D, P, block, tile_m, tile_n, variant)
+    return apsp_(D, P, block, tile_m, tile_n, variant, schedule)
 
 
 def apsp_batched_(Dcat, ns, offsets, Pcat=None, small_max_n: int = -1):

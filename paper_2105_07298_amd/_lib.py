@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libfwapsp.so")
 FW_F32, FW_F64 = 0, 1
 FW_OK, FW_EINVAL, FW_ENOMEM, FW_EHIP, FW_EUNSUPPORTED = 0, -1, -2, -3, -4
 FW_P4_PANELS, FW_P4_WAVEROWS = 1, 2
+FW_SCHED_SERIAL, FW_SCHED_LOOKAHEAD = 1, 2
 
 EXPORTS = ("fw_apsp", "fw_apsp_config", "fw_query_config", "fw_list_configs", "fw_apsp_batched",
            "fw_apsp_batched_config",
@@ -23,7 +24,7 @@ EXPORTS = ("fw_apsp", "fw_apsp_config", "fw_query_config", "fw_list_configs", "f
 
 class FwConfig(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("tile_m", ctypes.c_int32),
-                ("tile_n", ctypes.c_int32), ("variant", ctypes.c_int32)]
+                ("tile_n", ctypes.c_int32), ("variant", ctypes.c_int32), ("schedule", ctypes.c_int32)]
 
 
 class FwBatchedConfig(ctypes.Structure):
@@ -82,20 +83,20 @@ def fw_apsp(dt: int, n: int, dist: int, path: int | None, stream: int | None = N
     _check(lib().fw_apsp(dt, n, dist, path, stream), "fw_apsp")
 
 
-def fw_apsp_config(dt, n, dist, path, block=0, tile_m=0, tile_n=0, variant=0, stream=None):
-    cfg = FwConfig(block, tile_m, tile_n, variant)
+def fw_apsp_config(dt, n, dist, path, block=0, tile_m=0, tile_n=0, variant=0, schedule=0, stream=None):
+    cfg = FwConfig(block, tile_m, tile_n, variant, schedule)
     _check(lib().fw_apsp_config(dt, n, dist, path, ctypes.byref(cfg), stream), "fw_apsp_config")
 
 
 def fw_query_config(dt: int, n: int, path: bool):
-    """(block, tile_m, tile_n, variant) that fw_apsp uses for this case (from the tuned table)."""
-    cfg = FwConfig(0, 0, 0, 0)
+    """(block, tile_m, tile_n, variant, schedule) that fw_apsp uses for this case (the tuned table)."""
+    cfg = FwConfig(0, 0, 0, 0, 0)
     _check(lib().fw_query_config(dt, n, 1 if path else 0, ctypes.byref(cfg)), "fw_query_config")
-    return int(cfg.block), int(cfg.tile_m), int(cfg.tile_n), int(cfg.variant)
+    return int(cfg.block), int(cfg.tile_m), int(cfg.tile_n), int(cfg.variant), int(cfg.schedule)
 
 
 def fw_list_configs(dt: int):
-    """Every compiled (block, tile_m, tile_n, variant) for dtype code dt."""
+    """Every compiled (block, tile_m, tile_n, variant) for dtype code dt (any schedule applies)."""
     L = lib()
     count = L.fw_list_configs(dt, None, 0)
     if count < 0:
@@ -144,3 +145,11 @@ def fw_prof_read(reset: bool = True):
     _check(lib().fw_prof_read(ctypes.byref(c), ctypes.byref(t), ctypes.byref(u), 1 if reset else 0),
            "fw_prof_read")
     return int(c.value), float(t.value), int(u.value)
+
+
+def lookahead_applies(block: int, tile_m: int, tile_n: int, n: int) -> bool:
+    """Whether FW_SCHED_LOOKAHEAD changes anything for this configuration (else it runs serially):
+    tiles one block wide and at most one block tall, and at least 3 rounds after padding."""
+    unit = max(block, tile_m, tile_n)
+    npad = -(-n // unit) * unit
+    return tile_n == block and block % tile_m == 0 and npad // block >= 3

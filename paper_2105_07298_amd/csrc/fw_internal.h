@@ -9,14 +9,18 @@ namespace fw {
 // wave in scalar registers and the row panel in LDS.
 constexpr int FW_VARIANT_PANELS = 1;
 constexpr int FW_VARIANT_WAVEROWS = 2;
+// Round schedules: one stream, or lookahead on an auxiliary stream.
+constexpr int FW_SCHEDULE_SERIAL = 1;
+constexpr int FW_SCHEDULE_LOOKAHEAD = 2;
 
-// Round depth (the paper's TB), last-phase output tile (rows x columns) and
-// last-phase kernel.
+// Round depth (the paper's TB), last-phase output tile (rows x columns),
+// last-phase kernel and round schedule.
 struct TileCfg {
     int block;
     int tile_m;
     int tile_n;
     int variant;
+    int schedule;
 };
 
 // Launches of round r of the blocked method, enqueued on `s`.  D, P are the

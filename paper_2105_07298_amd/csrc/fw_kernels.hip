@@ -705,7 +705,7 @@ int list_configs(TileCfg *out, int cap) {
     int k = 0;
 #define FW_PUT(B, M, N, VAR)                              \
     {                                                     \
-        if (out && k < cap) out[k] = TileCfg{B, M, N, VAR}; \
+        if (out && k < cap) out[k] = TileCfg{B, M, N, VAR, 0}; \
         ++k;                                              \
     }
 #define FW_PUT_P(B, M, N) FW_PUT(B, M, N, FW_VARIANT_PANELS)

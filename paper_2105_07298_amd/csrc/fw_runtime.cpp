@@ -17,6 +17,8 @@
 
 static_assert(fw::FW_VARIANT_PANELS == FW_P4_PANELS && fw::FW_VARIANT_WAVEROWS == FW_P4_WAVEROWS,
               "variant codes of the C ABI");
+static_assert(fw::FW_SCHEDULE_SERIAL == FW_SCHED_SERIAL && fw::FW_SCHEDULE_LOOKAHEAD == FW_SCHED_LOOKAHEAD,
+              "schedule codes of the C ABI");
 
 namespace {
 
@@ -68,23 +70,29 @@ void *g_stage = nullptr;
 size_t g_stage_cap = 0;
 hipEvent_t g_stage_ev = nullptr;
 
-struct TuneEntry { int f64, path; long long n_lo, n_hi; int block, tile_m, tile_n, variant; };
+struct TuneEntry { int f64, path; long long n_lo, n_hi; int block, tile_m, tile_n, variant, schedule; };
 struct TuneBatchedEntry { int f64, path, small_max_n; };
 #include "tune_table.inc"
 
 fw::TileCfg default_cfg(fw_dtype_t dt, int64_t n, bool path) { return fw::tuned_config(dt == FW_F64, path, n); }
 
 // ---- lookahead ---------------------------------------------------------------
-// Phases 1-3 of round r + 1 only read and write block row and column r + 1,
-// which the last phase of round r finishes first (a small "cross" launch).  They
-// then run on an auxiliary stream while the rest of round r's last phase runs on
-// the caller's stream; the caller's stream waits for them before round r + 1's
-// last phase.  The auxiliary streams (default priority, non-blocking) and their
-// two events are kept per device and reused; one call holds one at a time.
+// Phases 1-3 of round r + 1 only read and write block row and column r + 1.  The
+// last phase of round r is therefore split: a small "cross" launch finishes
+// block row and column r + 1, and a "rest" launch does every other tile.  The
+// two are independent (disjoint tiles, read-only panels), and cross(r) only
+// needs rest(r - 1).  The caller's stream runs the rest launches back to back;
+// an auxiliary stream runs cross(r), then phases 1-3 of round r + 1, which the
+// caller's stream waits for before rest(r + 1):
+//   main: ... rest(r-1) -> [wait p23(r)]   rest(r)    -> [wait p23(r+1)] rest(r+1) ...
+//   aux:  ... [wait rest(r-1)] cross(r) -> p1(r+1) -> p23(r+1) -> [wait rest(r)] cross(r+1) ...
+// Events alternate between two per direction, so a wait never sees a record
+// from a later round.  The auxiliary streams (default priority, non-blocking)
+// and their events are kept per device and reused; one call holds one at a time.
 struct Aux {
     int dev;
     hipStream_t st;
-    hipEvent_t to_aux, to_main;
+    hipEvent_t rest_done[2], p23_done[2], start;
     bool busy;
 };
 std::mutex g_aux_mu;
@@ -97,15 +105,19 @@ Aux *acquire_aux(int dev) {
             a->busy = true;
             return a;
         }
-    Aux tmp{dev, nullptr, nullptr, nullptr, true};
-    if (hipStreamCreateWithFlags(&tmp.st, hipStreamNonBlocking) != hipSuccess) return nullptr;
-    if (hipEventCreateWithFlags(&tmp.to_aux, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&tmp.to_main, hipEventDisableTiming) != hipSuccess) {
-        (void)hipStreamDestroy(tmp.st);
+    Aux *a = new Aux{dev, nullptr, {nullptr, nullptr}, {nullptr, nullptr}, nullptr, true};
+    bool ok = hipStreamCreateWithFlags(&a->st, hipStreamNonBlocking) == hipSuccess;
+    hipEvent_t *evs[5] = {&a->rest_done[0], &a->rest_done[1], &a->p23_done[0], &a->p23_done[1], &a->start};
+    for (hipEvent_t *e : evs) ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        for (hipEvent_t *e : evs)
+            if (*e) (void)hipEventDestroy(*e);
+        if (a->st) (void)hipStreamDestroy(a->st);
+        delete a;
         return nullptr;
     }
-    g_aux.push_back(new Aux(tmp));
-    return g_aux.back();
+    g_aux.push_back(a);
+    return a;
 }
 
 void release_aux(Aux *a) {
@@ -120,32 +132,43 @@ template <typename T>
 hipError_t run_rounds(T *D, int32_t *P, uint16_t *L, int64_t ld, fw::TileCfg cfg, hipStream_t s) {
     using fw::P4Mode;
     const int R = (int)(ld / cfg.block);
+    const bool path = P != nullptr;
     hipError_t e;
     int dev = -1;
     Aux *aux = nullptr;
-    if (R >= kLookaheadMinRounds && fw::lookahead_supported(cfg) && hipGetDevice(&dev) == hipSuccess)
+    if (cfg.schedule == fw::FW_SCHEDULE_LOOKAHEAD && R >= kLookaheadMinRounds && fw::lookahead_supported(cfg) &&
+        hipGetDevice(&dev) == hipSuccess)
         aux = acquire_aux(dev);
     if (!aux) {
         for (int r = 0; r < R; ++r) {
             if ((e = fw::launch_phase123<T>(D, P, L, ld, r, cfg.block, s)) != hipSuccess) return e;
-            if ((e = fw::launch_phase4<T>(D, L, P != nullptr, ld, r, cfg, P4Mode::all, s)) != hipSuccess) return e;
+            if ((e = fw::launch_phase4<T>(D, L, path, ld, r, cfg, P4Mode::all, s)) != hipSuccess) return e;
         }
         return hipSuccess;
     }
-    e = fw::launch_phase123<T>(D, P, L, ld, 0, cfg.block, s);
-    for (int r = 0; r < R && e == hipSuccess; ++r) {
-        if (r + 1 == R) {
-            e = fw::launch_phase4<T>(D, L, P != nullptr, ld, r, cfg, P4Mode::all, s);
-            break;
+    hipStream_t a = aux->st;
+    auto body = [&]() -> hipError_t {
+        hipError_t e;
+        if ((e = hipEventRecord(aux->start, s)) != hipSuccess) return e;  // after the caller's earlier work
+        if ((e = hipStreamWaitEvent(a, aux->start, 0)) != hipSuccess) return e;
+        if ((e = fw::launch_phase123<T>(D, P, L, ld, 0, cfg.block, a)) != hipSuccess) return e;
+        if ((e = hipEventRecord(aux->p23_done[0], a)) != hipSuccess) return e;
+        for (int r = 0; r + 1 < R; ++r) {
+            // main stream: the bulk of round r
+            if ((e = hipStreamWaitEvent(s, aux->p23_done[r & 1], 0)) != hipSuccess) return e;
+            if ((e = fw::launch_phase4<T>(D, L, path, ld, r, cfg, P4Mode::rest, s)) != hipSuccess) return e;
+            if ((e = hipEventRecord(aux->rest_done[r & 1], s)) != hipSuccess) return e;
+            // auxiliary stream: block row / column r + 1, then phases 1-3 of round r + 1
+            if (r > 0 && (e = hipStreamWaitEvent(a, aux->rest_done[(r - 1) & 1], 0)) != hipSuccess) return e;
+            if ((e = fw::launch_phase4<T>(D, L, path, ld, r, cfg, P4Mode::cross, a)) != hipSuccess) return e;
+            if ((e = fw::launch_phase123<T>(D, P, L, ld, r + 1, cfg.block, a)) != hipSuccess) return e;
+            if ((e = hipEventRecord(aux->p23_done[(r + 1) & 1], a)) != hipSuccess) return e;
         }
-        if ((e = fw::launch_phase4<T>(D, L, P != nullptr, ld, r, cfg, P4Mode::cross, s)) != hipSuccess) break;
-        if ((e = hipEventRecord(aux->to_aux, s)) != hipSuccess) break;
-        if ((e = hipStreamWaitEvent(aux->st, aux->to_aux, 0)) != hipSuccess) break;
-        if ((e = fw::launch_phase123<T>(D, P, L, ld, r + 1, cfg.block, aux->st)) != hipSuccess) break;
-        if ((e = hipEventRecord(aux->to_main, aux->st)) != hipSuccess) break;
-        if ((e = fw::launch_phase4<T>(D, L, P != nullptr, ld, r, cfg, P4Mode::rest, s)) != hipSuccess) break;
-        e = hipStreamWaitEvent(s, aux->to_main, 0);
-    }
+        // last round: one launch on the main stream, after everything on the auxiliary one
+        if ((e = hipStreamWaitEvent(s, aux->p23_done[(R - 1) & 1], 0)) != hipSuccess) return e;
+        return fw::launch_phase4<T>(D, L, path, ld, R - 1, cfg, P4Mode::all, s);
+    };
+    e = body();
     release_aux(aux);
     return e;
 }
@@ -211,8 +234,8 @@ namespace fw {
 TileCfg tuned_config(bool f64, bool path, int64_t n) {
     for (const TuneEntry &t : kTuneApsp)
         if (t.f64 == (int)f64 && t.path == (int)path && n >= t.n_lo && n < t.n_hi)
-            return {t.block, t.tile_m, t.tile_n, t.variant};
-    return {64, 64, 64, FW_VARIANT_PANELS};
+            return {t.block, t.tile_m, t.tile_n, t.variant, t.schedule};
+    return {64, 64, 64, FW_VARIANT_PANELS, FW_SCHEDULE_SERIAL};
 }
 int tuned_batched_small_max_n(bool f64, bool path) {
     for (const TuneBatchedEntry &t : kTuneBatched)
@@ -247,12 +270,14 @@ fw_status_t fw_apsp_config(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, 
     fw::TileCfg tc = default_cfg(dt, n, path != nullptr);
     if (cfg) {
         if (cfg->block < 0 || cfg->tile_m < 0 || cfg->tile_n < 0 || cfg->variant < 0 ||
-            cfg->variant > FW_P4_WAVEROWS)
-            return fail(FW_EINVAL, "config fields must be 0 (tuned) or positive, variant at most %d", FW_P4_WAVEROWS);
+            cfg->variant > FW_P4_WAVEROWS || cfg->schedule < 0 || cfg->schedule > FW_SCHED_LOOKAHEAD)
+            return fail(FW_EINVAL, "config fields must be 0 (tuned) or positive, variant at most %d, schedule at most %d",
+                        FW_P4_WAVEROWS, FW_SCHED_LOOKAHEAD);
         if (cfg->block) tc.block = cfg->block;
         if (cfg->tile_m) tc.tile_m = cfg->tile_m;
         if (cfg->tile_n) tc.tile_n = cfg->tile_n;
         if (cfg->variant) tc.variant = cfg->variant;
+        if (cfg->schedule) tc.schedule = cfg->schedule;
     }
     if (!(dt == FW_F32 ? fw::config_supported<float>(tc) : fw::config_supported<double>(tc)))
         return fail(FW_EUNSUPPORTED, "block %d / tile %d x %d / variant %d not compiled in", tc.block, tc.tile_m,
@@ -275,6 +300,7 @@ fw_status_t fw_query_config(fw_dtype_t dt, int64_t n, int32_t path, fw_config_t 
     out->tile_m = c.tile_m;
     out->tile_n = c.tile_n;
     out->variant = c.variant;
+    out->schedule = c.schedule;
     return FW_OK;
 }
 
@@ -286,7 +312,7 @@ int32_t fw_list_configs(fw_dtype_t dt, fw_config_t *out, int32_t cap) {
                                                        : fw::list_configs<double>(nullptr, 0)));
     const int total = dt == FW_F32 ? fw::list_configs<float>(all.data(), (int)all.size())
                                    : fw::list_configs<double>(all.data(), (int)all.size());
-    for (int k = 0; k < total && k < cap; ++k) out[k] = {all[k].block, all[k].tile_m, all[k].tile_n, all[k].variant};
+    for (int k = 0; k < total && k < cap; ++k) out[k] = {all[k].block, all[k].tile_m, all[k].tile_n, all[k].variant, 0};
     return total;
 }
 

@@ -4,7 +4,8 @@ table compiled into the library).
 
 Run on the GPU:  python -m paper_2105_07298_amd.tune --out DIR
 It times, with HIP events on the current stream,
-  * fw_apsp for every compiled (block, tile_m, tile_n, variant) at one representative n per size
+  * fw_apsp for every compiled (block, tile_m, tile_n, variant), under each round schedule
+    that applies to it (serial; lookahead), at one representative n per size
     range, for float32/float64 with and without the path matrix, on complete
     graphs with weights uniform in (0, 1);
   * fw_apsp_batched on batches of equal-size graphs (weights in [1, 10],
@@ -53,20 +54,23 @@ def tune_apsp(fw, torch, log):
             for path in (False, True):
                 P = torch.empty((n, n), dtype=torch.int32, device=W.device) if path else None
                 best = None
-                for block, tm, tn, var in fw.fw_list_configs(fw.FW_F32 if dt == "f32" else fw.FW_F64):
+                cands = [(b, tm, tn, var, sch) for b, tm, tn, var in fw.fw_list_configs(
+                    fw.FW_F32 if dt == "f32" else fw.FW_F64) for sch in (fw.FW_SCHED_SERIAL, fw.FW_SCHED_LOOKAHEAD)
+                    if sch == fw.FW_SCHED_SERIAL or fw.lookahead_applies(b, tm, tn, n)]
+                for block, tm, tn, var, sch in cands:
                     def run():
                         D.copy_(W)
-                        fw.apsp_(D, P, block=block, tile_m=tm, tile_n=tn, variant=var)
+                        fw.apsp_(D, P, block=block, tile_m=tm, tile_n=tn, variant=var, schedule=sch)
                     reps = 2 if n >= 8192 else 5
                     ms = _timeit(run, torch, reps)
                     log.append({"kind": "apsp", "dtype": dt, "path": path, "n": n, "block": block, "tile_m": tm,
-                                "tile_n": tn, "variant": var, "ms": round(ms, 4)})
-                    print(f"apsp {dt} path={path} n={n} block={block} tile={tm}x{tn} variant={var}: {ms:.3f} ms",
-                          flush=True)
+                                "tile_n": tn, "variant": var, "schedule": sch, "ms": round(ms, 4)})
+                    print(f"apsp {dt} path={path} n={n} block={block} tile={tm}x{tn} variant={var} "
+                          f"schedule={sch}: {ms:.3f} ms", flush=True)
                     if best is None or ms < best[0]:
-                        best = (ms, block, tm, tn, var)
-                table.append({"f64": dt == "f64", "path": path, "n_lo": lo, "n_hi": hi,
-                              "block": best[1], "tile_m": best[2], "tile_n": best[3], "variant": best[4]})
+                        best = (ms, block, tm, tn, var, sch)
+                table.append({"f64": dt == "f64", "path": path, "n_lo": lo, "n_hi": hi, "block": best[1],
+                              "tile_m": best[2], "tile_n": best[3], "variant": best[4], "schedule": best[5]})
             del W, D
             torch.cuda.empty_cache()
     return table
@@ -115,7 +119,7 @@ def write_inc(path, apsp_table, batched_table, arch):
     lines = [
         "// Tile configuration table.  Generated by paper_2105_07298_amd/tune.py from",
         f"// timings on {arch} (do not edit by hand; rerun the tuner instead).",
-        "// fw_apsp:          {f64, path, n_lo, n_hi, block, tile_m, tile_n, variant}  for n_lo <= n < n_hi",
+        "// fw_apsp:          {f64, path, n_lo, n_hi, block, tile_m, tile_n, variant, schedule}  n_lo <= n < n_hi",
         "// fw_apsp_batched:  {f64, path, small_max_n}",
         f"// generated {time.strftime('%Y-%m-%d')}",
         "static const TuneEntry kTuneApsp[] = {",
@@ -123,7 +127,7 @@ def write_inc(path, apsp_table, batched_table, arch):
     for t in apsp_table:
         hi = "1LL << 40" if t["n_hi"] >= (1 << 40) else str(t["n_hi"])
         lines.append(f"    {{{int(t['f64'])}, {int(t['path'])}, {t['n_lo']}, {hi}, {t['block']}, {t['tile_m']}, "
-                     f"{t['tile_n']}, {t['variant']}}},")
+                     f"{t['tile_n']}, {t['variant']}, {t['schedule']}}},")
     lines.append("};")
     lines.append("static const TuneBatchedEntry kTuneBatched[] = {")
     for t in batched_table:

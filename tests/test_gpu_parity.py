@@ -17,9 +17,15 @@ pytestmark = pytest.mark.gpu
 
 
 
-def compiled_configs(dtype):
+def compiled_configs(dtype, n):
+    """Every compiled configuration, once per round schedule that applies to it at size n."""
     import paper_2105_07298_amd as fw
-    return fw.fw_list_configs(fw.FW_F32 if dtype == np.float32 else fw.FW_F64)
+    out = []
+    for b, tm, tn, var in fw.fw_list_configs(fw.FW_F32 if dtype == np.float32 else fw.FW_F64):
+        out.append((b, tm, tn, var, fw.FW_SCHED_SERIAL))
+        if fw.lookahead_applies(b, tm, tn, n):
+            out.append((b, tm, tn, var, fw.FW_SCHED_LOOKAHEAD))
+    return out
 
 
 @pytest.fixture(scope="module")
@@ -31,13 +37,13 @@ def dev():
     return torch.device("cuda:0")
 
 
-def run_gpu(W, dev, path=True, block=0, tile=(0, 0), variant=0, case=""):
+def run_gpu(W, dev, path=True, block=0, tile=(0, 0), variant=0, schedule=0, case=""):
     import torch
     import paper_2105_07298_amd as fw
     print(f"[gpu] fw_apsp {case} n={W.shape[0]} dtype={W.dtype} path={path} block={block} tile={tile} "
-          f"variant={variant}", flush=True)
+          f"variant={variant} schedule={schedule}", flush=True)
     D, P = fw.apsp(torch.from_numpy(np.ascontiguousarray(W)).to(dev), path=path, block=block,
-                   tile_m=tile[0], tile_n=tile[1], variant=variant)
+                   tile_m=tile[0], tile_n=tile[1], variant=variant, schedule=schedule)
     torch.cuda.synchronize()
     return D.cpu().numpy(), (P.cpu().numpy() if P is not None else None)
 
@@ -78,8 +84,8 @@ def test_block_and_tile_invariance_tie_heavy(dev, dtype):
     W = workloads.int_graph(n=448, p=0.02, wmax=3, seed=21, dtype=dtype)
     Do, Po = oracle.fw(W)
     assert (Po >= 0).mean() > 0.5
-    for block, tm, tn, var in compiled_configs(dtype):
-        Dg, Pg = run_gpu(W, dev, block=block, tile=(tm, tn), variant=var, case="tie-heavy")
+    for block, tm, tn, var, sch in compiled_configs(dtype, W.shape[0]):
+        Dg, Pg = run_gpu(W, dev, block=block, tile=(tm, tn), variant=var, schedule=sch, case="tie-heavy")
         assert_exact(W, Dg, Pg, Do, Po)
 
 
@@ -187,8 +193,8 @@ def test_configs_real_weights(dev, dtype, tol):
     W = workloads.unit_complete(700, dtype=dtype, seed=9)
     Do, _ = oracle.fw(W, exact=False)
     first = {}
-    for block, tm, tn, var in compiled_configs(dtype):
-        Dg, Pg = run_gpu(W, dev, block=block, tile=(tm, tn), variant=var, case="real-weights")
+    for block, tm, tn, var, sch in compiled_configs(dtype, W.shape[0]):
+        Dg, Pg = run_gpu(W, dev, block=block, tile=(tm, tn), variant=var, schedule=sch, case="real-weights")
         assert rel_err(Dg, Do) <= tol
         if block not in first:
             first[block] = (Dg, Pg)
@@ -217,3 +223,22 @@ def test_c2_16384_dijkstra_rows(dev, dtype, tol):
         assert pth is not None and pth[0] == i and pth[-1] == j
         s = sum(float(W[a, b]) for a, b in zip(pth[:-1], pth[1:]))
         assert abs(s - float(Dg[i, j])) <= 1e-5 * float(Dg[i, j]) * len(pth)
+
+
+def test_lookahead_16384_matches_serial(dev):
+    """n = 16384 float32 with the path matrix, 64 x 64 tiles: the lookahead schedule
+    (two streams) gives bit for bit the serial schedule's D and P, and its sampled
+    rows match the float64 Dijkstra oracle within the float32 tolerance."""
+    import paper_2105_07298_amd as fw
+    n = 16384
+    W = workloads.unit_complete(n, dtype=np.float32, seed=2)
+    res = {}
+    for sch in (fw.FW_SCHED_SERIAL, fw.FW_SCHED_LOOKAHEAD):
+        res[sch] = run_gpu(W, dev, block=64, tile=(64, 64), variant=fw.FW_P4_PANELS, schedule=sch,
+                           case="schedules")
+    np.testing.assert_array_equal(res[1][0], res[2][0])
+    np.testing.assert_array_equal(res[1][1], res[2][1])
+    srcs = workloads.sample_sources(n, 16)
+    print("[cpu] dijkstra 16 rows", flush=True)
+    Dr, _ = oracle.dijkstra_rows(W, srcs, exact=False)
+    assert rel_err(res[2][0][srcs], Dr) <= 1e-5

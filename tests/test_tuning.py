@@ -15,7 +15,7 @@ def entries():
     for m in re.finditer(r"\{([^{}]*)\}", apsp):
         f = [x.strip() for x in m.group(1).split(",")]
         hi = (1 << 40) if "<<" in f[3] else int(f[3])
-        rows.append((int(f[0]), int(f[1]), int(f[2]), hi, int(f[4]), int(f[5]), int(f[6]), int(f[7])))
+        rows.append((int(f[0]), int(f[1]), int(f[2]), hi, int(f[4]), int(f[5]), int(f[6]), int(f[7]), int(f[8])))
     brows = [tuple(int(x) for x in m.group(1).split(",")) for m in re.finditer(r"\{([^{}]*)\}", batched)]
     return rows, brows
 
@@ -33,6 +33,7 @@ def test_apsp_table_covers_every_size_once():
                 assert a[3] == b[2], "size ranges must tile [0, inf)"
             for r in rs:
                 assert (r[4], r[5], r[6], r[7]) in supported[f64], r
+                assert r[8] in (fw.FW_SCHED_SERIAL, fw.FW_SCHED_LOOKAHEAD), r
 
 
 def test_batched_table_complete():
