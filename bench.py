@@ -56,7 +56,87 @@ def gflops(n, seconds):
     return 2.0 * n ** 3 / seconds / 1e9
 
 
-def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False, config=None):
+class EnergyMeter:
+    """GPU energy over a timed region: the device's accumulated energy counter
+    (amdsmi), read before and after; socket power sampled every 20 ms alongside.
+    Every field is None, with a reason, where the counters cannot be read."""
+
+    def __init__(self, torch):
+        self.handle, self.reason = None, ""
+        try:
+            import amdsmi
+            self.smi = amdsmi
+            amdsmi.amdsmi_init(amdsmi.AmdSmiInitFlags.INIT_AMD_GPUS)
+            handles = amdsmi.amdsmi_get_processor_handles()
+            if len(handles) == 1:
+                self.handle = handles[0]
+            else:  # pick the device torch uses by PCI bus
+                props = torch.cuda.get_device_properties(torch.cuda.current_device())
+                bus = getattr(props, "pci_bus_id", None)
+                for h in handles:
+                    bdf = amdsmi.amdsmi_get_gpu_device_bdf(h)
+                    if bus is not None and int(bdf.split(":")[1], 16) == bus:
+                        self.handle = h
+                if self.handle is None:
+                    self.reason = f"{len(handles)} GPUs visible to amdsmi and none matched the PCI bus"
+        except Exception as e:  # no driver access, no library, ...
+            self.reason = f"amdsmi unavailable: {e}"
+
+    def _energy_uj(self):
+        e = self.smi.amdsmi_get_energy_count(self.handle)
+        return e["energy_accumulator"] * e["counter_resolution"]
+
+    def _sample(self):
+        while not self._stop.is_set():
+            try:
+                pw = self.smi.amdsmi_get_power_info(self.handle)
+                v = pw.get("current_socket_power")
+                if not isinstance(v, (int, float)) or v <= 0 or v > 10000:
+                    v = pw.get("average_socket_power")
+                if isinstance(v, (int, float)) and 0 < v < 10000:
+                    self._samples.append(float(v))
+            except Exception:
+                pass
+            self._stop.wait(0.02)
+
+    def start(self):
+        import threading
+        if self.handle is None:
+            return
+        self._samples, self._stop = [], threading.Event()
+        self._t0 = time.perf_counter()
+        try:
+            self._e0 = self._energy_uj()
+        except Exception as e:
+            self._e0, self.reason = None, f"energy counter unreadable: {e}"
+        self._thr = threading.Thread(target=self._sample, daemon=True)
+        self._thr.start()
+
+    def stop(self, steps, flops_per_step):
+        out = {"joules_per_step": None, "avg_power_w": None, "sampled_power_w": None, "gflops_per_w": None,
+               "source": None, "reason": self.reason or None}
+        if self.handle is None:
+            return out
+        sec = time.perf_counter() - self._t0
+        self._stop.set()
+        self._thr.join()
+        if self._samples:
+            out["sampled_power_w"] = round(sum(self._samples) / len(self._samples), 1)
+        if self._e0 is not None:
+            joules = (self._energy_uj() - self._e0) / 1e6
+            if joules > 0:
+                out.update({"joules_per_step": round(joules / steps, 3), "avg_power_w": round(joules / sec, 1),
+                            "gflops_per_w": round(flops_per_step * steps / joules / 1e9, 2),
+                            "source": "amdsmi energy accumulator over the timed steps", "reason": None})
+                return out
+        if out["sampled_power_w"]:
+            out.update({"avg_power_w": out["sampled_power_w"],
+                        "gflops_per_w": round(flops_per_step * steps / sec / 1e9 / out["sampled_power_w"], 2),
+                        "source": "amdsmi socket power, sampled every 20 ms"})
+        return out
+
+
+def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False, config=None, energy=None):
     """Mean seconds per fw_apsp step (D <- W, P <- -1, all rounds) and last-phase stats.
     config: (block, tile_m, tile_n, variant, schedule), default the tuned choice."""
     import numpy as np
@@ -79,11 +159,15 @@ def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False, config=None)
         fw.fw_prof_enable(True)
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    if energy is not None:
+        energy.start()
     t0.record()
     for _ in range(steps):
         step()
     t1.record()
     torch.cuda.synchronize()
+    if energy is not None:
+        energy.result = energy.stop(steps, 2.0 * n ** 3)
     sec = t0.elapsed_time(t1) / 1e3 / steps
     stats = None
     if prof:
@@ -124,6 +208,29 @@ def time_batched(fw, torch, steps=3, warmup=1):
     flops = 2.0 * float(np.sum(ns.astype(np.float64) ** 3))
     return {"graphs_per_s": round(ns.size / sec, 1), "ms_per_batch": round(sec * 1e3, 3),
             "gflops": round(flops / sec / 1e9, 2), "batch": int(ns.size), "n_range": [16, 512]}
+
+
+def time_ooc(fw, torch, n=32768, S=8192):
+    """Out of core: an n x n float32 complete graph (weights in (0,1)) in pinned host
+    memory, through a device budget that holds super-blocks of edge S (here 4 x 4
+    super-tiles, 4 super-rounds).  One timed call, transfers included."""
+    import numpy as np
+    import workloads
+    nb = -(-n // S)
+    budget = (4 * S * S + 2 * S * nb * S) * 4
+    assert fw.fw_ooc_superblock(fw.FW_F32, n, budget) == S
+    H = torch.empty((n, n), dtype=torch.float32, pin_memory=True)
+    Hn = H.numpy()
+    for i0 in range(0, n, 4096):  # the generator writes straight into the pinned rows
+        i1 = min(n, i0 + 4096)
+        workloads.rows(2, n, i0, i1, 1.0, workloads.W_UNIT_OPEN, 0, np.float32, 0, Hn[i0:i1])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    fw.apsp_ooc_(H, budget)
+    sec = time.perf_counter() - t
+    return {"n": n, "superblock": S, "device_bytes": budget, "seconds": round(sec, 3),
+            "gflops": round(gflops(n, sec), 2), "dtype": "f32", "path": False,
+            "note": "matrix in pinned host memory; host-to-device and device-to-host transfers included"}
 
 
 def time_fwd_bwd(fw, torch, steps=5, warmup=2):
@@ -223,6 +330,7 @@ def main():
     ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
     ap.add_argument("--no-path", action="store_true", help="distances only (P = NULL)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-energy", action="store_true", help="skip the amdsmi energy reading")
     ap.add_argument("--config", default="", help="block,tile_m,tile_n,variant,schedule instead of the tuned choice")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -244,7 +352,9 @@ def main():
     print(f"[bench] n={args.n} {args.dtype} path={path} warmup={args.warmup} steps={args.steps}",
           file=sys.stderr, flush=True)
     config = tuple(int(x) for x in args.config.split(",")) if args.config else None
-    sec, stats = time_apsp(fw, torch, args.n, args.dtype, path, args.steps, args.warmup, prof=True, config=config)
+    meter = None if args.no_energy else EnergyMeter(torch)
+    sec, stats = time_apsp(fw, torch, args.n, args.dtype, path, args.steps, args.warmup, prof=True, config=config,
+                           energy=meter)
     value = gflops(args.n, sec)
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GFLOPS", "n_gpus": 1,
@@ -257,6 +367,7 @@ def main():
                    "n": args.n, "path": path, "block": stats["block"], "tile": stats["tile"],
                    "parallelism": "single GPU"},
         "roofline": roofline(args.n, args.dtype, stats),
+        "energy": meter.result if meter is not None else None,
     }
     if args.calib_copy_mib:
         nb = args.calib_copy_mib * (1 << 20)
@@ -277,6 +388,8 @@ def main():
             key = f"{dt_}_{'path' if pth else 'dist'}"
             sec_out[key] = {"gflops": round(gflops(args.n, s), 2), "ms_per_step": round(s * 1e3, 2),
                             "roofline_frac": roofline(args.n, dt_, st)["frac"]}
+        print("[bench] secondary out of core n=32768", file=sys.stderr, flush=True)
+        sec_out["ooc_f32_dist"] = time_ooc(fw, torch)
         print("[bench] secondary batched 10,000 graphs", file=sys.stderr, flush=True)
         sec_out["batched"] = time_batched(fw, torch)
         print("[bench] secondary forward + backward", file=sys.stderr, flush=True)

@@ -10,7 +10,8 @@ from __future__ import annotations
 
 from ._lib import (FW_EHIP, FW_EINVAL, FW_ENOMEM, FW_EUNSUPPORTED, FW_F32, FW_F64, FW_OK,  # noqa: F401
                    FW_P4_PANELS, FW_P4_WAVEROWS, FW_SCHED_LOOKAHEAD, FW_SCHED_SERIAL, FwError, fw_apsp, fw_apsp_backward, fw_apsp_batched,
-                   fw_apsp_batched_config, fw_apsp_config, fw_last_error, fw_list_configs, fw_prof_enable,
+                   fw_apsp_batched_config, fw_apsp_config, fw_apsp_ooc, fw_last_error, fw_list_configs, fw_ooc_superblock,
+                   fw_prof_enable,
                    fw_prof_read, fw_query_config, fw_status_string, fw_version, lib, lookahead_applies)
 
 
@@ -60,6 +61,19 @@ def apsp(W, path: bool = True, block: int = 0, tile_m: int = 0, tile_n: int = 0,
     D = W.contiguous().clone()
     P = torch.empty(D.shape, dtype=torch.int32, device=D.device) if path else None
     return apsp_(D, P, block, tile_m, tile_n, variant, schedule)
+
+
+def apsp_ooc_(W, device_bytes: int = 0):
+    """Distances in place for a square CPU tensor W (float32/float64, contiguous;
+    pinned memory lets transfers overlap the work), through at most device_bytes
+    of device memory (0: 90% of the free memory).  Work is ordered after the
+    current stream; returns when W holds the distances."""
+    import torch
+    if W.is_cuda or W.dim() != 2 or W.shape[0] != W.shape[1] or not W.is_contiguous():
+        raise ValueError("W must be a contiguous square CPU tensor")
+    fw_apsp_ooc(_dtype_code(W), W.shape[0], W.data_ptr(), device_bytes,
+                torch.cuda.current_stream().cuda_stream)
+    return W
 
 
 def apsp_batched_(Dcat, ns, offsets, Pcat=None, small_max_n: int = -1):

@@ -16,8 +16,8 @@ FW_OK, FW_EINVAL, FW_ENOMEM, FW_EHIP, FW_EUNSUPPORTED = 0, -1, -2, -3, -4
 FW_P4_PANELS, FW_P4_WAVEROWS = 1, 2
 FW_SCHED_SERIAL, FW_SCHED_LOOKAHEAD = 1, 2
 
-EXPORTS = ("fw_apsp", "fw_apsp_config", "fw_query_config", "fw_list_configs", "fw_apsp_batched",
-           "fw_apsp_batched_config",
+EXPORTS = ("fw_apsp", "fw_apsp_config", "fw_query_config", "fw_list_configs", "fw_apsp_ooc", "fw_ooc_superblock",
+           "fw_apsp_batched", "fw_apsp_batched_config",
            "fw_apsp_backward",
            "fw_status_string", "fw_last_error", "fw_version", "fw_prof_enable", "fw_prof_read")
 
@@ -55,6 +55,10 @@ def lib():
     L.fw_apsp_config.argtypes = [ctypes.c_int, i64, vp, vp, ctypes.POINTER(FwConfig), vp]
     L.fw_query_config.argtypes = [ctypes.c_int, i64, i32, ctypes.POINTER(FwConfig)]
     L.fw_query_config.restype = ctypes.c_int
+    L.fw_apsp_ooc.argtypes = [ctypes.c_int, i64, vp, ctypes.c_size_t, vp]
+    L.fw_apsp_ooc.restype = ctypes.c_int
+    L.fw_ooc_superblock.argtypes = [ctypes.c_int, i64, ctypes.c_size_t]
+    L.fw_ooc_superblock.restype = i64
     L.fw_list_configs.argtypes = [ctypes.c_int, ctypes.POINTER(FwConfig), i32]
     L.fw_list_configs.restype = ctypes.c_int32
     L.fw_apsp_batched.argtypes = [ctypes.c_int, i32, vp, vp, vp, vp, vp]
@@ -104,6 +108,18 @@ def fw_list_configs(dt: int):
     arr = (FwConfig * count)()
     L.fw_list_configs(dt, arr, count)
     return [(int(c.block), int(c.tile_m), int(c.tile_n), int(c.variant)) for c in arr]
+
+
+def fw_apsp_ooc(dt, n, dist_host, device_bytes=0, stream=None):
+    """dist_host: host pointer (n*n elements); blocks until the distances are there."""
+    _check(lib().fw_apsp_ooc(dt, n, dist_host, device_bytes, stream), "fw_apsp_ooc")
+
+
+def fw_ooc_superblock(dt, n, device_bytes=0) -> int:
+    s = lib().fw_ooc_superblock(dt, n, device_bytes)
+    if s < 0:
+        _check(int(s), "fw_ooc_superblock")
+    return int(s)
 
 
 def fw_apsp_batched(dt, batch, n_host, off_host, dist, path, stream=None):

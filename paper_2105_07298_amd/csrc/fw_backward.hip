@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(NT) k_backward(const T *__restrict__ D, const 
     double *S = (double *)lds;
     int16_t *pred = (int16_t *)(S + n);
     int16_t *depth = pred + n;
-    __shared__ int s_changed, s_maxd;
+    __shared__ int s_changed;
     const int i = blockIdx.x;
     const int64_t base = (int64_t)blockIdx.y * n * n;
     const T *Drow = D + base + (int64_t)i * n;
@@ -78,9 +78,11 @@ __global__ void __launch_bounds__(NT) k_backward(const T *__restrict__ D, const 
         depth[j] = dp;
         S[j] = s;
     }
-    if (threadIdx.x == 0) s_maxd = 0;
     __syncthreads();
-    // 2. depths, one level per pass.
+    // 2. depths, one level per pass.  The flag is read into a register and a
+    //    barrier separates that read from the next pass's reset, so every wave
+    //    sees the same value and leaves the loop at the same level.
+    int maxd = 0;
     for (int lev = 1;; ++lev) {
         if (threadIdx.x == 0) s_changed = 0;
         __syncthreads();
@@ -91,13 +93,13 @@ __global__ void __launch_bounds__(NT) k_backward(const T *__restrict__ D, const 
             }
         }
         __syncthreads();
-        if (!s_changed) {
-            if (threadIdx.x == 0) s_maxd = lev - 1;
-            __syncthreads();
+        const int changed = s_changed;
+        __syncthreads();
+        if (!changed) {
+            maxd = lev - 1;
             break;
         }
     }
-    const int maxd = s_maxd;
     // 3. subtree sums from the deepest level up (level-1 vertices hang off i).
     for (int lev = maxd; lev >= 2; --lev) {
         for (int j = threadIdx.x; j < n; j += NT)

@@ -83,6 +83,25 @@ int tuned_batched_small_max_n(bool f64, bool path);
 template <typename T>
 hipError_t launch_backward(const T *D, const int32_t *P, const T *G, T *gW, int n, int batch, hipStream_t s);
 
+// C <- min(C, A (x) B): C is M x N (leading dimension ldc), A is M x K (lda), B
+// is K x N (ldb); M, N, K multiples of 64, pointers and leading dimensions
+// 16-byte aligned.  Distances only (no labels).
+template <typename T>
+hipError_t launch_minplus(T *C, int64_t ldc, const T *A, int64_t lda, const T *B, int64_t ldb, int64_t M, int64_t N,
+                          int64_t K, hipStream_t s);
+
+// rows x cols block (leading dimension ld) set to +inf, with 0 on the diagonal
+// if zero_diag (a block of isolated vertices).
+template <typename T>
+hipError_t launch_fill_blank(T *p, int64_t ld, int64_t rows, int64_t cols, bool zero_diag, hipStream_t s);
+
+// Out of core: distances of the n x n matrix H in host memory, super-blocks of
+// edge S (a multiple of 256); returns when H holds the result.  *what names the
+// failing step on error.
+template <typename T>
+hipError_t run_ooc(int64_t n, T *H, int64_t S, hipStream_t user, const char **what);
+int64_t ooc_working_elems(int64_t n, int64_t S);
+
 // Fill n int32 with v.
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 

@@ -497,6 +497,90 @@ __global__ void __launch_bounds__(NT) k_phase4w(T *__restrict__ D, uint16_t *__r
 }
 
 // ---------------------------------------------------------------------------
+// General min-plus update C <- min(C, A (x) B) for the out-of-core driver: C is
+// M x N, A is M x K, B is K x N, each with its own leading dimension (M, N
+// multiples of the tile edges, K of KT).  Same register-blocked tiles as
+// k_phase4, but each workgroup walks all of K in chunks of KT, re-staging the
+// two panel chunks in LDS, so that its C tile is read and written once per
+// product.  Distances only.
+template <typename T, int KT, int BM, int BN>
+__global__ void __launch_bounds__(NT) k_minplus(T *__restrict__ C, int64_t ldc, const T *__restrict__ A, int64_t lda,
+                                               const T *__restrict__ B, int64_t ldb, int64_t K, TileSel sel) {
+    constexpr int RM = BM / 16, RN = BN / 16;
+    using vec = typename V16<T>::type;
+    constexpr int V = V16<T>::n;
+    constexpr int TX = BN / RN, TY = NT / TX;
+    static_assert(TY * RM == BM && RN % V == 0, "tile shape");
+    constexpr int HN = RN / V, CS = BN / HN;
+    constexpr int AST = KT + V;
+    __shared__ __attribute__((aligned(16))) T As[BM * AST];
+    __shared__ __attribute__((aligned(16))) T Bs[KT * BN];
+
+    int bi, bj;
+    if (!select_tile<false>(sel, blockIdx.x, bi, bj)) return;
+    const int64_t I0 = (int64_t)bi * BM, J0 = (int64_t)bj * BN;
+    const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
+
+    T acc[RM][RN];
+#pragma unroll
+    for (int ii = 0; ii < RM; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < RN; ++jj) acc[ii][jj] = inf_v<T>();
+
+    for (int64_t k0 = 0; k0 < K; k0 += KT) {
+        __syncthreads();  // the previous chunk is consumed
+        for (int q = tid; q < BM * (KT / V); q += NT) {
+            const int row = q / (KT / V), kv = q % (KT / V);
+            *(vec *)(As + row * AST + kv * V) = *(const vec *)(A + (I0 + row) * lda + k0 + kv * V);
+        }
+        for (int q = tid; q < KT * (BN / V); q += NT) {
+            const int krow = q / (BN / V), cv = q % (BN / V);
+            *(vec *)(Bs + krow * BN + cv * V) = *(const vec *)(B + (k0 + krow) * ldb + J0 + cv * V);
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int kv = 0; kv < KT / V; ++kv) {
+            vec a[RM];
+#pragma unroll
+            for (int ii = 0; ii < RM; ++ii) a[ii] = *(const vec *)(As + (ty + TY * ii) * AST + kv * V);
+#pragma unroll
+            for (int kk = 0; kk < V; kk += 2) {
+                vec b0[HN], b1[HN];
+#pragma unroll
+                for (int h = 0; h < HN; ++h) {
+                    b0[h] = *(const vec *)(Bs + (kv * V + kk) * BN + h * CS + tx * V);
+                    b1[h] = *(const vec *)(Bs + (kv * V + kk + 1) * BN + h * CS + tx * V);
+                }
+#pragma unroll
+                for (int ii = 0; ii < RM; ++ii)
+#pragma unroll
+                    for (int h = 0; h < HN; ++h)
+#pragma unroll
+                        for (int e = 0; e < V; ++e) {
+                            T &x = acc[ii][h * V + e];
+                            x = vmin(vmin(x, a[ii][kk] + b0[h][e]), a[ii][kk + 1] + b1[h][e]);
+                        }
+            }
+        }
+    }
+#pragma unroll
+    for (int ii = 0; ii < RM; ++ii)
+#pragma unroll
+        for (int h = 0; h < HN; ++h) {
+            T *cp = C + (I0 + ty + TY * ii) * ldc + J0 + h * CS + tx * V;
+            vec nv = *(const vec *)cp;
+            bool ch = false;
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const T s = acc[ii][h * V + e];
+                ch |= s < nv[e];
+                nv[e] = vmin(nv[e], s);
+            }
+            if (ch) *(vec *)cp = nv;
+        }
+}
+
+// ---------------------------------------------------------------------------
 // Label resolution (path mode, after the last round).  Entry (i, j) pending
 // from round r (L = r + 1) last decreased in the last phase of round r, to
 // S = min over k in K_r of A[i][k] + B[k][j].  For every k that attains S, the
@@ -585,6 +669,17 @@ __global__ void __launch_bounds__(NT) k_transpose(const T *__restrict__ D, T *__
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
+}
+
+// rows x cols block with leading dimension ld: +inf, and 0 where row == col if
+// zero_diag.
+template <typename T>
+__global__ void k_fill_blank(T *__restrict__ p, int64_t ld, int64_t rows, int64_t cols, int zero_diag) {
+    const int64_t total = rows * cols;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = x / cols, j = x % cols;
+        p[i * ld + j] = (zero_diag && i == j) ? (T)0 : inf_v<T>();
+    }
 }
 
 template <typename T>
@@ -761,6 +856,18 @@ hipError_t launch_phase4(T *D, uint16_t *L, bool path, int64_t ld, int r, TileCf
 bool lookahead_supported(TileCfg c) { return c.tile_n == c.block && c.tile_m <= c.block; }
 
 template <typename T>
+hipError_t launch_minplus(T *C, int64_t ldc, const T *A, int64_t lda, const T *B, int64_t ldb, int64_t M, int64_t N,
+                          int64_t K, hipStream_t s) {
+    constexpr int KT = 64, BM = 64, BN = 64;
+    if (M % BM || N % BN || K % KT || M <= 0 || N <= 0 || K <= 0) return hipErrorInvalidValue;
+    TileSel sel;
+    if (!make_tile_sel((int)(M / BM), (int)(N / BN), 0, 0, 0, 1, 0, sel)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_minplus<T, KT, BM, BN>), dim3(8 * sel.per_xcd), dim3(NT), 0, s, C, ldc, A, lda, B, ldb, K,
+                       sel);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_resolve(const T *D, T *DT, const uint16_t *L, int32_t *P, int64_t ld, int block, hipStream_t s) {
     hipLaunchKernelGGL((k_transpose<T>), dim3((unsigned)(ld / 64), (unsigned)(ld / 64)), dim3(NT), 0, s, D, DT, ld);
     const dim3 grid((unsigned)((ld + NT - 1) / NT), (unsigned)(ld < 65535 ? ld : 65535));
@@ -770,6 +877,13 @@ hipError_t launch_resolve(const T *D, T *DT, const uint16_t *L, int32_t *P, int6
         hipLaunchKernelGGL((k_resolve<T, 32>), grid, dim3(NT), 0, s, D, DT, L, P, ld);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill_blank(T *p, int64_t ld, int64_t rows, int64_t cols, bool zero_diag, hipStream_t s) {
+    hipLaunchKernelGGL((k_fill_blank<T>), dim3(grid_for(rows * cols)), dim3(NT), 0, s, p, ld, rows, cols,
+                       zero_diag ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -793,6 +907,12 @@ hipError_t launch_pad_out(const T *src, int64_t npad, T *dst, int64_t n, hipStre
 template bool config_supported<float>(TileCfg);
 template bool config_supported<double>(TileCfg);
 template int list_configs<float>(TileCfg *, int);
+template hipError_t launch_fill_blank<float>(float *, int64_t, int64_t, int64_t, bool, hipStream_t);
+template hipError_t launch_fill_blank<double>(double *, int64_t, int64_t, int64_t, bool, hipStream_t);
+template hipError_t launch_minplus<float>(float *, int64_t, const float *, int64_t, const float *, int64_t, int64_t,
+                                          int64_t, int64_t, hipStream_t);
+template hipError_t launch_minplus<double>(double *, int64_t, const double *, int64_t, const double *, int64_t,
+                                           int64_t, int64_t, int64_t, hipStream_t);
 template int list_configs<double>(TileCfg *, int);
 template hipError_t launch_phase123<float>(float *, int32_t *, uint16_t *, int64_t, int, int, hipStream_t);
 template hipError_t launch_phase123<double>(double *, int32_t *, uint16_t *, int64_t, int, int, hipStream_t);

@@ -1,0 +1,159 @@
+// fw_ooc.cpp -- shortest distances for a matrix held in host memory (out of
+// core): the blocked method with super-blocks of edge S sized to a device
+// memory budget.  Super-round R, with K the vertices of super-block R:
+//   1. the diagonal super-block D[K,K] is closed in device memory by the
+//      in-core blocked sweep (fw_apsp);
+//   2. the row band D[K,:] becomes min(D[K,J], D*[K,K] (x) D_old[K,J]) per
+//      super-column J (one min-plus product each, as phases 2 of the blocked
+//      method with the closed diagonal block);
+//   3. the column band D[:,K] likewise, min(D[I,K], D_old[I,K] (x) D*[K,K]);
+//   4. every other super-tile streams through the device once:
+//      D[I,J] <- min(D[I,J], D[I,K] (x) D[K,J]), with its upload, product and
+//      download on three streams and two device buffers, so that transfers in
+//      both directions overlap the products.
+// Distances only.  Edges that do not fill a super-block are padded with +inf
+// (isolated vertices), so every product runs on full S x S blocks.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "../../include/fw_apsp.h"
+#include "fw_internal.h"
+
+namespace fw {
+
+int64_t ooc_working_elems(int64_t n, int64_t S) {
+    const int64_t NS = (n + S - 1) / S, NP = NS * S;
+    return 4 * S * S + 2 * S * NP;  // diagonal, temp, 2 tile buffers; row and column bands
+}
+
+namespace {
+
+struct Streams {
+    hipStream_t cs = nullptr, h2d = nullptr, d2h = nullptr;
+    hipEvent_t loaded[2] = {nullptr, nullptr}, computed[2] = {nullptr, nullptr}, stored[2] = {nullptr, nullptr};
+    hipEvent_t start = nullptr;
+    ~Streams() {
+        for (hipEvent_t e : {loaded[0], loaded[1], computed[0], computed[1], stored[0], stored[1], start})
+            if (e) (void)hipEventDestroy(e);
+        for (hipStream_t s : {cs, h2d, d2h})
+            if (s) (void)hipStreamDestroy(s);
+    }
+    hipError_t create() {
+        hipError_t e;
+        for (hipStream_t *s : {&cs, &h2d, &d2h})
+            if ((e = hipStreamCreateWithFlags(s, hipStreamNonBlocking)) != hipSuccess) return e;
+        for (hipEvent_t *ev : {&loaded[0], &loaded[1], &computed[0], &computed[1], &stored[0], &stored[1], &start})
+            if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess) return e;
+        return hipSuccess;
+    }
+};
+
+struct DeviceBuffer {
+    void *p = nullptr;
+    ~DeviceBuffer() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+#define FW_TRY(x)                                \
+    do {                                         \
+        hipError_t e_ = (x);                     \
+        if (e_ != hipSuccess) {                  \
+            *what = #x;                          \
+            return e_;                           \
+        }                                        \
+    } while (0)
+
+}  // namespace
+
+template <typename T>
+hipError_t run_ooc(int64_t n, T *H, int64_t S, hipStream_t user, const char **what) {
+    const int64_t NS = (n + S - 1) / S, NP = NS * S;
+    const size_t es = sizeof(T);
+    Streams st;
+    FW_TRY(st.create());
+    DeviceBuffer buf;
+    FW_TRY(hipMalloc(&buf.p, (size_t)ooc_working_elems(n, S) * es));
+    T *Dd = (T *)buf.p, *TMP = Dd + S * S, *Cb[2] = {TMP + S * S, TMP + 2 * S * S};
+    T *RB = Cb[1] + S * S;  // S x NP, leading dimension NP
+    T *CB = RB + S * NP;    // NP x S, leading dimension S
+    const hipStream_t cs = st.cs;
+    // Order after the caller's earlier work on its stream.
+    FW_TRY(hipEventRecord(st.start, user));
+    FW_TRY(hipStreamWaitEvent(cs, st.start, 0));
+    // Tile buffers start blank; uploads into them wait for that.
+    FW_TRY(launch_fill_blank<T>(Cb[0], S, S, S, false, cs));
+    FW_TRY(launch_fill_blank<T>(Cb[1], S, S, S, false, cs));
+    FW_TRY(hipEventRecord(st.start, cs));
+    FW_TRY(hipStreamWaitEvent(st.h2d, st.start, 0));
+    auto edge = [&](int64_t b) { return std::min(S, n - b * S); };
+    const hipMemcpyKind H2D = hipMemcpyHostToDevice, D2H = hipMemcpyDeviceToHost, D2D = hipMemcpyDeviceToDevice;
+    const fw_dtype_t dt = sizeof(T) == 4 ? FW_F32 : FW_F64;
+    for (int64_t R = 0; R < NS; ++R) {
+        const int64_t K0 = R * S, SK = edge(R);
+        // 1. diagonal super-block, closed in core
+        FW_TRY(launch_fill_blank<T>(Dd, S, S, S, true, cs));  // padding vertices are isolated
+        FW_TRY(hipMemcpy2DAsync(Dd, S * es, H + K0 * n + K0, n * es, SK * es, SK, H2D, cs));
+        if (fw_apsp(dt, S, Dd, nullptr, cs) != FW_OK) {
+            *what = "in-core closure of the diagonal super-block";
+            return hipErrorUnknown;
+        }
+        FW_TRY(hipMemcpy2DAsync(H + K0 * n + K0, n * es, Dd, S * es, SK * es, SK, D2H, cs));
+        if (NS == 1) break;
+        // 2. row band
+        FW_TRY(launch_fill_blank<T>(RB, NP, S, NP, false, cs));  // padding rows and columns: +inf
+        FW_TRY(hipMemcpy2DAsync(RB, NP * es, H + K0 * n, n * es, n * es, SK, H2D, cs));
+        for (int64_t J = 0; J < NS; ++J) {
+            if (J == R) continue;
+            FW_TRY(hipMemcpy2DAsync(TMP, S * es, RB + J * S, NP * es, S * es, S, D2D, cs));
+            FW_TRY(launch_minplus<T>(RB + J * S, NP, Dd, S, TMP, S, S, S, S, cs));
+        }
+        FW_TRY(hipMemcpy2DAsync(H + K0 * n, n * es, RB, NP * es, n * es, SK, D2H, cs));
+        // 3. column band
+        FW_TRY(launch_fill_blank<T>(CB, S, NP, S, false, cs));
+        FW_TRY(hipMemcpy2DAsync(CB, S * es, H + K0, n * es, SK * es, n, H2D, cs));
+        for (int64_t I = 0; I < NS; ++I) {
+            if (I == R) continue;
+            FW_TRY(hipMemcpyAsync(TMP, CB + I * S * S, (size_t)(S * S) * es, D2D, cs));
+            FW_TRY(launch_minplus<T>(CB + I * S * S, S, TMP, S, Dd, S, S, S, S, cs));
+        }
+        FW_TRY(hipMemcpy2DAsync(H + K0, n * es, CB, S * es, SK * es, n, D2H, cs));
+        // 4. the other super-tiles: upload (h2d) -> product (cs) -> download (d2h).
+        // Uploads may start during steps 1-3: those tiles are disjoint from
+        // the blocks and bands written back there.
+        int64_t t = 0;
+        for (int64_t I = 0; I < NS; ++I) {
+            if (I == R) continue;
+            for (int64_t J = 0; J < NS; ++J) {
+                if (J == R) continue;
+                const int b = (int)(t & 1);
+                const int64_t SI = edge(I), SJ = edge(J);
+                T *h = H + I * S * n + J * S;
+                if (t >= 2) FW_TRY(hipStreamWaitEvent(st.h2d, st.stored[b], 0));  // buffer b is free again
+                FW_TRY(hipMemcpy2DAsync(Cb[b], S * es, h, n * es, SJ * es, SI, H2D, st.h2d));
+                FW_TRY(hipEventRecord(st.loaded[b], st.h2d));
+                FW_TRY(hipStreamWaitEvent(cs, st.loaded[b], 0));
+                FW_TRY(launch_minplus<T>(Cb[b], S, CB + I * S * S, S, RB + J * S, NP, S, S, S, cs));
+                FW_TRY(hipEventRecord(st.computed[b], cs));
+                FW_TRY(hipStreamWaitEvent(st.d2h, st.computed[b], 0));
+                FW_TRY(hipMemcpy2DAsync(h, n * es, Cb[b], S * es, SJ * es, SI, D2H, st.d2h));
+                FW_TRY(hipEventRecord(st.stored[b], st.d2h));
+                ++t;
+            }
+        }
+        // The next super-round reads what this one wrote back: drain all streams.
+        FW_TRY(hipStreamSynchronize(st.d2h));
+        FW_TRY(hipStreamSynchronize(st.h2d));
+        FW_TRY(hipStreamSynchronize(cs));
+    }
+    FW_TRY(hipStreamSynchronize(cs));
+    return hipSuccess;
+}
+
+template hipError_t run_ooc<float>(int64_t, float *, int64_t, hipStream_t, const char **);
+template hipError_t run_ooc<double>(int64_t, double *, int64_t, hipStream_t, const char **);
+
+}  // namespace fw

@@ -316,6 +316,37 @@ int32_t fw_list_configs(fw_dtype_t dt, fw_config_t *out, int32_t cap) {
     return total;
 }
 
+int64_t fw_ooc_superblock(fw_dtype_t dt, int64_t n, size_t device_bytes) {
+    g_err[0] = 0;
+    if (dt != FW_F32 && dt != FW_F64) return fail(FW_EINVAL, "unknown dtype %d", (int)dt);
+    if (n < 1 || n > kMaxN) return fail(FW_EINVAL, "n = %lld outside [1, %lld]", (long long)n, (long long)kMaxN);
+    if (device_bytes == 0) {
+        size_t free_b = 0, total_b = 0;
+        hipError_t e = hipMemGetInfo(&free_b, &total_b);
+        if (e != hipSuccess) return hip_fail(e, "hipMemGetInfo");
+        device_bytes = free_b / 10 * 9;
+    }
+    const size_t es = dt == FW_F32 ? 4 : 8;
+    constexpr int64_t unit = 256;
+    for (int64_t S = (n + unit - 1) / unit * unit; S >= unit; S -= unit)
+        if ((size_t)fw::ooc_working_elems(n, S) * es <= device_bytes) return S;
+    return fail(FW_ENOMEM, "%zu device bytes hold no working set for n = %lld (need %zu for 256-vertex super-blocks)",
+                device_bytes, (long long)n, (size_t)fw::ooc_working_elems(n, unit) * es);
+}
+
+fw_status_t fw_apsp_ooc(fw_dtype_t dt, int64_t n, void *dist_host, size_t device_bytes, void *stream) {
+    g_err[0] = 0;
+    fw_status_t st = check_common(dt, n, dist_host);
+    if (st != FW_OK) return st;
+    const int64_t S = fw_ooc_superblock(dt, n, device_bytes);
+    if (S < 0) return (fw_status_t)S;
+    const char *what = "";
+    hipError_t e = dt == FW_F32 ? fw::run_ooc<float>(n, (float *)dist_host, S, (hipStream_t)stream, &what)
+                                : fw::run_ooc<double>(n, (double *)dist_host, S, (hipStream_t)stream, &what);
+    if (e != hipSuccess) return hip_fail(e, what);
+    return FW_OK;
+}
+
 fw_status_t fw_apsp(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, void *stream) {
     return fw_apsp_config(dt, n, dist, path, nullptr, stream);
 }

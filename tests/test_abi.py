@@ -132,3 +132,21 @@ def test_backward_argument_errors_before_device(fw):
     assert L.fw_apsp_backward(0, 16, 1, 4096, None, 4096, 4096, None) == fw.FW_EINVAL
     assert L.fw_apsp_backward(0, 16, 0, 4096, 4096, 4096, 4096, None) == fw.FW_EINVAL
     assert L.fw_apsp_backward(3, 16, 1, 4096, 4096, 4096, 4096, None) == fw.FW_EINVAL
+
+
+def test_ooc_superblock_choice(fw):
+    """The super-block edge is the largest multiple of 256 whose working set
+    (4 S^2 + 2 S ceil(n/S) S elements) fits the given byte budget."""
+    def elems(n, S):
+        nb = -(-n // S)
+        return 4 * S * S + 2 * S * nb * S
+    for dt, es in ((fw.FW_F32, 4), (fw.FW_F64, 8)):
+        for n in (1, 300, 3000, 16384, 100000):
+            for S_want in (256, 512, 1024, 4096):
+                budget = elems(n, S_want) * es
+                S = fw.fw_ooc_superblock(dt, n, budget)
+                assert S % 256 == 0 and elems(n, S) * es <= budget
+                top = -(-n // 256) * 256
+                assert S == top or elems(n, S + 256) * es > budget
+        assert fw.lib().fw_ooc_superblock(dt, 3000, 1000) == fw.FW_ENOMEM
+    assert fw.lib().fw_ooc_superblock(9, 3000, 1 << 30) == fw.FW_EINVAL
