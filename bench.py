@@ -210,26 +210,28 @@ def time_batched(fw, torch, steps=3, warmup=1):
             "gflops": round(flops / sec / 1e9, 2), "batch": int(ns.size), "n_range": [16, 512]}
 
 
-def time_ooc(fw, torch, n=32768, S=8192):
+def time_ooc(fw, torch, n=32768, S=8192, path=False):
     """Out of core: an n x n float32 complete graph (weights in (0,1)) in pinned host
-    memory, through a device budget that holds super-blocks of edge S (here 4 x 4
-    super-tiles, 4 super-rounds).  One timed call, transfers included."""
+    memory, through a device budget that holds super-blocks of edge S (n / S
+    super-rounds).  One timed call, transfers included."""
     import numpy as np
     import workloads
     nb = -(-n // S)
-    budget = (4 * S * S + 2 * S * nb * S) * 4
-    assert fw.fw_ooc_superblock(fw.FW_F32, n, budget) == S
+    blocks = 4 * S * S + 2 * S * nb * S
+    budget = blocks * 4 + ((blocks + S * S) * 4 if path else 0)
+    assert fw.fw_ooc_superblock(fw.FW_F32, n, path, budget) == S
     H = torch.empty((n, n), dtype=torch.float32, pin_memory=True)
+    HP = torch.empty((n, n), dtype=torch.int32, pin_memory=True) if path else None
     Hn = H.numpy()
     for i0 in range(0, n, 4096):  # the generator writes straight into the pinned rows
         i1 = min(n, i0 + 4096)
         workloads.rows(2, n, i0, i1, 1.0, workloads.W_UNIT_OPEN, 0, np.float32, 0, Hn[i0:i1])
     torch.cuda.synchronize()
     t = time.perf_counter()
-    fw.apsp_ooc_(H, budget)
+    fw.apsp_ooc_(H, HP, budget)
     sec = time.perf_counter() - t
     return {"n": n, "superblock": S, "device_bytes": budget, "seconds": round(sec, 3),
-            "gflops": round(gflops(n, sec), 2), "dtype": "f32", "path": False,
+            "gflops": round(gflops(n, sec), 2), "dtype": "f32", "path": path,
             "note": "matrix in pinned host memory; host-to-device and device-to-host transfers included"}
 
 
@@ -390,6 +392,8 @@ def main():
                             "roofline_frac": roofline(args.n, dt_, st)["frac"]}
         print("[bench] secondary out of core n=32768", file=sys.stderr, flush=True)
         sec_out["ooc_f32_dist"] = time_ooc(fw, torch)
+        print("[bench] secondary out of core n=16384 with the path matrix", file=sys.stderr, flush=True)
+        sec_out["ooc_f32_path"] = time_ooc(fw, torch, n=16384, S=4096, path=True)
         print("[bench] secondary batched 10,000 graphs", file=sys.stderr, flush=True)
         sec_out["batched"] = time_batched(fw, torch)
         print("[bench] secondary forward + backward", file=sys.stderr, flush=True)

@@ -112,25 +112,29 @@ int32_t fw_list_configs(fw_dtype_t dt, fw_config_t *out, int32_t cap);
 fw_status_t fw_query_config(fw_dtype_t dt, int64_t n, int32_t path, fw_config_t *out);
 
 /*
- * Shortest distances for a matrix larger than the device memory to be used
- * (out of core: the paper leaves this as future work for its GPU runs, where the
- * matrix had to fit in device memory).  dist_host is HOST memory, n*n elements
- * row-major, W on entry and D on exit; pinned memory (hipHostMalloc) lets the
- * transfers overlap the computation.  The blocked method runs over super-blocks
- * of edge S (fw_ooc_superblock): each super-round closes its diagonal
- * super-block in device memory with fw_apsp, updates its row and column bands,
- * and streams every other S x S super-tile through the device once.
- * device_bytes bounds the device working set (0: 90% of the free memory).
- * Distances only.  Ordered after earlier work on `stream`; returns when
- * dist_host holds the result.  FW_ENOMEM if device_bytes cannot hold even
+ * All-pairs shortest paths for a matrix larger than the device memory to be
+ * used (out of core: the paper leaves this as future work for its GPU runs,
+ * where the matrix had to fit in device memory).  dist_host is HOST memory,
+ * n*n elements row-major, W on entry and D on exit; path_host (HOST, n*n int32)
+ * receives P, or is NULL for distances only.  Pinned memory (hipHostMalloc)
+ * lets the transfers overlap the computation.  The blocked method runs over
+ * super-blocks of edge S (fw_ooc_superblock): each super-round closes its
+ * diagonal super-block in device memory with fw_apsp, updates its row and
+ * column bands, and streams every other S x S super-tile through the device
+ * once.  P follows the same lexicographic rule as fw_apsp, so both give the
+ * same P for the same D.  device_bytes bounds the device working set (0: 90%
+ * of the free memory).  Ordered after earlier work on `stream`; returns when
+ * the host arrays hold the result.  FW_ENOMEM if device_bytes cannot hold even
  * 256-vertex super-blocks.
  */
-fw_status_t fw_apsp_ooc(fw_dtype_t dt, int64_t n, void *dist_host, size_t device_bytes, void *stream);
+fw_status_t fw_apsp_ooc(fw_dtype_t dt, int64_t n, void *dist_host, int32_t *path_host, size_t device_bytes,
+                        void *stream);
 
-/* The super-block edge fw_apsp_ooc uses for (dt, n, device_bytes): the largest
- * multiple of 256 whose working set, 4*S^2 + 2*S*ceil(n/S)*S elements, fits;
- * or a negative status.  Host only. */
-int64_t fw_ooc_superblock(fw_dtype_t dt, int64_t n, size_t device_bytes);
+/* The super-block edge fw_apsp_ooc uses for (dt, n, path != 0, device_bytes):
+ * the largest multiple of 256 whose working set fits -- 4*S^2 + 2*S*ceil(n/S)*S
+ * elements, plus as many int32 labels and S^2 more with the path matrix -- or
+ * a negative status.  Host only. */
+int64_t fw_ooc_superblock(fw_dtype_t dt, int64_t n, int32_t path, size_t device_bytes);
 
 /*
  * Many independent graphs of uneven size in one persistent launch.

@@ -63,17 +63,23 @@ def apsp(W, path: bool = True, block: int = 0, tile_m: int = 0, tile_n: int = 0,
     return apsp_(D, P, block, tile_m, tile_n, variant, schedule)
 
 
-def apsp_ooc_(W, device_bytes: int = 0):
-    """Distances in place for a square CPU tensor W (float32/float64, contiguous;
-    pinned memory lets transfers overlap the work), through at most device_bytes
-    of device memory (0: 90% of the free memory).  Work is ordered after the
-    current stream; returns when W holds the distances."""
+def apsp_ooc_(W, P=None, device_bytes: int = 0):
+    """In place for a square CPU tensor W (float32/float64, contiguous; pinned
+    memory lets transfers overlap the work): W becomes the distances and P (int32
+    CPU tensor shaped like W, optional) the path matrix, through at most
+    device_bytes of device memory (0: 90% of the free memory).  Work is ordered
+    after the current stream; returns when W and P hold the results."""
     import torch
     if W.is_cuda or W.dim() != 2 or W.shape[0] != W.shape[1] or not W.is_contiguous():
         raise ValueError("W must be a contiguous square CPU tensor")
-    fw_apsp_ooc(_dtype_code(W), W.shape[0], W.data_ptr(), device_bytes,
+    pp = None
+    if P is not None:
+        if P.is_cuda or P.dtype != torch.int32 or P.shape != W.shape or not P.is_contiguous():
+            raise ValueError("P must be a contiguous int32 CPU tensor shaped like W")
+        pp = P.data_ptr()
+    fw_apsp_ooc(_dtype_code(W), W.shape[0], W.data_ptr(), pp, device_bytes,
                 torch.cuda.current_stream().cuda_stream)
-    return W
+    return W, P
 
 
 def apsp_batched_(Dcat, ns, offsets, Pcat=None, small_max_n: int = -1):

@@ -55,9 +55,9 @@ def lib():
     L.fw_apsp_config.argtypes = [ctypes.c_int, i64, vp, vp, ctypes.POINTER(FwConfig), vp]
     L.fw_query_config.argtypes = [ctypes.c_int, i64, i32, ctypes.POINTER(FwConfig)]
     L.fw_query_config.restype = ctypes.c_int
-    L.fw_apsp_ooc.argtypes = [ctypes.c_int, i64, vp, ctypes.c_size_t, vp]
+    L.fw_apsp_ooc.argtypes = [ctypes.c_int, i64, vp, vp, ctypes.c_size_t, vp]
     L.fw_apsp_ooc.restype = ctypes.c_int
-    L.fw_ooc_superblock.argtypes = [ctypes.c_int, i64, ctypes.c_size_t]
+    L.fw_ooc_superblock.argtypes = [ctypes.c_int, i64, i32, ctypes.c_size_t]
     L.fw_ooc_superblock.restype = i64
     L.fw_list_configs.argtypes = [ctypes.c_int, ctypes.POINTER(FwConfig), i32]
     L.fw_list_configs.restype = ctypes.c_int32
@@ -110,13 +110,14 @@ def fw_list_configs(dt: int):
     return [(int(c.block), int(c.tile_m), int(c.tile_n), int(c.variant)) for c in arr]
 
 
-def fw_apsp_ooc(dt, n, dist_host, device_bytes=0, stream=None):
-    """dist_host: host pointer (n*n elements); blocks until the distances are there."""
-    _check(lib().fw_apsp_ooc(dt, n, dist_host, device_bytes, stream), "fw_apsp_ooc")
+def fw_apsp_ooc(dt, n, dist_host, path_host=None, device_bytes=0, stream=None):
+    """dist_host, path_host: host pointers (n*n elements; path_host may be None);
+    blocks until the results are there."""
+    _check(lib().fw_apsp_ooc(dt, n, dist_host, path_host, device_bytes, stream), "fw_apsp_ooc")
 
 
-def fw_ooc_superblock(dt, n, device_bytes=0) -> int:
-    s = lib().fw_ooc_superblock(dt, n, device_bytes)
+def fw_ooc_superblock(dt, n, path=False, device_bytes=0) -> int:
+    s = lib().fw_ooc_superblock(dt, n, 1 if path else 0, device_bytes)
     if s < 0:
         _check(int(s), "fw_ooc_superblock")
     return int(s)

@@ -90,6 +90,17 @@ template <typename T>
 hipError_t launch_minplus(T *C, int64_t ldc, const T *A, int64_t lda, const T *B, int64_t ldb, int64_t M, int64_t N,
                           int64_t K, hipStream_t s);
 
+// (C, PC) <- lexicographic minimum with A (x) B carrying labels: candidate k
+// has length A[i][k] + B[k][j] and label max(PA[i][k], kbase + k, PB[k][j]).
+// M, N multiples of 64, K of 32.
+template <typename T>
+hipError_t launch_minplus_lex(T *C, int32_t *PC, int64_t ldc, const T *A, const int32_t *PA, int64_t lda, const T *B,
+                              const int32_t *PB, int64_t ldb, int64_t M, int64_t N, int64_t K, int32_t kbase,
+                              hipStream_t s);
+
+// P[x] <- base + Plocal[x] where Plocal[x] >= 0 (count entries).
+hipError_t launch_merge_labels(int32_t *P, const int32_t *Plocal, int64_t count, int32_t base, hipStream_t s);
+
 // rows x cols block (leading dimension ld) set to +inf, with 0 on the diagonal
 // if zero_diag (a block of isolated vertices).
 template <typename T>
@@ -99,8 +110,9 @@ hipError_t launch_fill_blank(T *p, int64_t ld, int64_t rows, int64_t cols, bool 
 // edge S (a multiple of 256); returns when H holds the result.  *what names the
 // failing step on error.
 template <typename T>
-hipError_t run_ooc(int64_t n, T *H, int64_t S, hipStream_t user, const char **what);
-int64_t ooc_working_elems(int64_t n, int64_t S);
+hipError_t run_ooc(int64_t n, T *H, int32_t *HP, int64_t S, hipStream_t user, const char **what);
+// Device bytes of the working set for super-block edge S (with labels if path).
+size_t ooc_working_bytes(int64_t n, int64_t S, size_t es, bool path);
 
 // Fill n int32 with v.
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);

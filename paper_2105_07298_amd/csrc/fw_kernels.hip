@@ -580,6 +580,94 @@ __global__ void __launch_bounds__(NT) k_minplus(T *__restrict__ C, int64_t ldc, 
         }
 }
 
+// Lexicographic form of the general update, for the out-of-core driver with
+// path labels: (C, PC) <- lexmin over k of (A[i][k] + B[k][j],
+// max(PA[i][k], kbase + k, PB[k][j])) and the old (C, PC) -- the rule phases 1-3
+// apply, with kbase the global index of A's first column.  64 x 64 tiles, 16 x 16
+// threads with 4 x 4 entries each (rows ty + 16 ii, columns tx + 16 jj), panel
+// chunks of KT values of k with their labels in LDS.
+template <typename T, int KT>
+__global__ void __launch_bounds__(NT) k_minplus_lex(T *__restrict__ C, int32_t *__restrict__ PC, int64_t ldc,
+                                                   const T *__restrict__ A, const int32_t *__restrict__ PA, int64_t lda,
+                                                   const T *__restrict__ B, const int32_t *__restrict__ PB, int64_t ldb,
+                                                   int64_t K, int32_t kbase, TileSel sel) {
+    constexpr int TS = 16, RM = 4, BM = 64, BN = 64, STA = KT + 1, STB = BN + 1;
+    __shared__ T sa[BM * STA];
+    __shared__ int32_t spa[BM * STA];
+    __shared__ T sb[KT * STB];
+    __shared__ int32_t spb[KT * STB];
+    int bi, bj;
+    if (!select_tile<false>(sel, blockIdx.x, bi, bj)) return;
+    const int64_t I0 = (int64_t)bi * BM, J0 = (int64_t)bj * BN;
+    const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
+    T d[RM][RM], d0[RM][RM];
+    int32_t p[RM][RM], p0[RM][RM];
+#pragma unroll
+    for (int ii = 0; ii < RM; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < RM; ++jj) {
+            const int64_t g = (I0 + ty + TS * ii) * ldc + J0 + tx + TS * jj;
+            d[ii][jj] = d0[ii][jj] = C[g];
+            p[ii][jj] = p0[ii][jj] = PC[g];
+        }
+    for (int64_t k0 = 0; k0 < K; k0 += KT) {
+        __syncthreads();  // the previous chunk is consumed
+        for (int q = threadIdx.x; q < BM * KT; q += NT) {
+            const int row = q / KT, kk = q % KT;
+            const int64_t g = (I0 + row) * lda + k0 + kk;
+            sa[row * STA + kk] = A[g];
+            spa[row * STA + kk] = PA[g];
+        }
+        for (int q = threadIdx.x; q < KT * BN; q += NT) {
+            const int kr = q / BN, c = q % BN;
+            const int64_t g = (k0 + kr) * ldb + J0 + c;
+            sb[kr * STB + c] = B[g];
+            spb[kr * STB + c] = PB[g];
+        }
+        __syncthreads();
+        for (int kk = 0; kk < KT; ++kk) {
+            T a[RM], b[RM];
+            int32_t pa[RM], pb[RM];
+#pragma unroll
+            for (int ii = 0; ii < RM; ++ii) {
+                a[ii] = sa[(ty + TS * ii) * STA + kk];
+                pa[ii] = spa[(ty + TS * ii) * STA + kk];
+            }
+#pragma unroll
+            for (int jj = 0; jj < RM; ++jj) {
+                b[jj] = sb[kk * STB + tx + TS * jj];
+                pb[jj] = spb[kk * STB + tx + TS * jj];
+            }
+            const int32_t kg = kbase + (int32_t)(k0 + kk);
+#pragma unroll
+            for (int ii = 0; ii < RM; ++ii)
+#pragma unroll
+                for (int jj = 0; jj < RM; ++jj)
+                    lex_take(d[ii][jj], p[ii][jj], a[ii] + b[jj], max(max(pa[ii], pb[jj]), kg));
+        }
+    }
+#pragma unroll
+    for (int ii = 0; ii < RM; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < RM; ++jj) {
+            if (d[ii][jj] == d0[ii][jj] && p[ii][jj] == p0[ii][jj]) continue;
+            const int64_t g = (I0 + ty + TS * ii) * ldc + J0 + tx + TS * jj;
+            C[g] = d[ii][jj];
+            PC[g] = p[ii][jj];
+        }
+}
+
+// Labels of a block closed in isolation (local vertex indices, -1 where the
+// entry did not change) turned into global ones: unchanged entries keep their
+// old label, changed ones get base + local.
+__global__ void k_merge_labels(int32_t *__restrict__ P, const int32_t *__restrict__ Plocal, int64_t count,
+                               int32_t base) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < count; x += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t l = Plocal[x];
+        if (l >= 0) P[x] = base + l;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Label resolution (path mode, after the last round).  Entry (i, j) pending
 // from round r (L = r + 1) last decreased in the last phase of round r, to
@@ -868,6 +956,24 @@ hipError_t launch_minplus(T *C, int64_t ldc, const T *A, int64_t lda, const T *B
 }
 
 template <typename T>
+hipError_t launch_minplus_lex(T *C, int32_t *PC, int64_t ldc, const T *A, const int32_t *PA, int64_t lda, const T *B,
+                              const int32_t *PB, int64_t ldb, int64_t M, int64_t N, int64_t K, int32_t kbase,
+                              hipStream_t s) {
+    constexpr int KT = 32;
+    if (M % 64 || N % 64 || K % KT || M <= 0 || N <= 0 || K <= 0) return hipErrorInvalidValue;
+    TileSel sel;
+    if (!make_tile_sel((int)(M / 64), (int)(N / 64), 0, 0, 0, 1, 0, sel)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_minplus_lex<T, KT>), dim3(8 * sel.per_xcd), dim3(NT), 0, s, C, PC, ldc, A, PA, lda, B, PB,
+                       ldb, K, kbase, sel);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_labels(int32_t *P, const int32_t *Plocal, int64_t count, int32_t base, hipStream_t s) {
+    hipLaunchKernelGGL(k_merge_labels, dim3(grid_for(count)), dim3(NT), 0, s, P, Plocal, count, base);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_resolve(const T *D, T *DT, const uint16_t *L, int32_t *P, int64_t ld, int block, hipStream_t s) {
     hipLaunchKernelGGL((k_transpose<T>), dim3((unsigned)(ld / 64), (unsigned)(ld / 64)), dim3(NT), 0, s, D, DT, ld);
     const dim3 grid((unsigned)((ld + NT - 1) / NT), (unsigned)(ld < 65535 ? ld : 65535));
@@ -907,6 +1013,12 @@ hipError_t launch_pad_out(const T *src, int64_t npad, T *dst, int64_t n, hipStre
 template bool config_supported<float>(TileCfg);
 template bool config_supported<double>(TileCfg);
 template int list_configs<float>(TileCfg *, int);
+template hipError_t launch_minplus_lex<float>(float *, int32_t *, int64_t, const float *, const int32_t *, int64_t,
+                                              const float *, const int32_t *, int64_t, int64_t, int64_t, int64_t,
+                                              int32_t, hipStream_t);
+template hipError_t launch_minplus_lex<double>(double *, int32_t *, int64_t, const double *, const int32_t *, int64_t,
+                                               const double *, const int32_t *, int64_t, int64_t, int64_t, int64_t,
+                                               int32_t, hipStream_t);
 template hipError_t launch_fill_blank<float>(float *, int64_t, int64_t, int64_t, bool, hipStream_t);
 template hipError_t launch_fill_blank<double>(double *, int64_t, int64_t, int64_t, bool, hipStream_t);
 template hipError_t launch_minplus<float>(float *, int64_t, const float *, int64_t, const float *, int64_t, int64_t,

@@ -11,22 +11,31 @@
 //      D[I,J] <- min(D[I,J], D[I,K] (x) D[K,J]), with its upload, product and
 //      download on three streams and two device buffers, so that transfers in
 //      both directions overlap the products.
-// Distances only.  Edges that do not fill a super-block are padded with +inf
+// With the path matrix, every block carries its labels and the products apply
+// the lexicographic rule (length, largest interior vertex) of phases 1-3 with
+// global vertex indices.  The diagonal closure runs on the block alone, whose
+// labels are local and -1 where an entry did not change: those entries keep
+// their earlier label (below K's first vertex, so it loses no tie), the others
+// get K's first vertex plus the local label.
+// Edges that do not fill a super-block are padded with +inf and label -1
 // (isolated vertices), so every product runs on full S x S blocks.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
 
 #include <algorithm>
+#include <thread>
+#include <vector>
 
 #include "../../include/fw_apsp.h"
 #include "fw_internal.h"
 
 namespace fw {
 
-int64_t ooc_working_elems(int64_t n, int64_t S) {
+size_t ooc_working_bytes(int64_t n, int64_t S, size_t es, bool path) {
     const int64_t NS = (n + S - 1) / S, NP = NS * S;
-    return 4 * S * S + 2 * S * NP;  // diagonal, temp, 2 tile buffers; row and column bands
+    const size_t blocks = (size_t)(4 * S * S + 2 * S * NP);  // diagonal, temp, 2 tile buffers; row and column bands
+    return blocks * es + (path ? blocks * sizeof(int32_t) + (size_t)(S * S) * sizeof(int32_t) : 0);
 }
 
 namespace {
@@ -70,23 +79,41 @@ struct DeviceBuffer {
 }  // namespace
 
 template <typename T>
-hipError_t run_ooc(int64_t n, T *H, int64_t S, hipStream_t user, const char **what) {
+hipError_t run_ooc(int64_t n, T *H, int32_t *HP, int64_t S, hipStream_t user, const char **what) {
     const int64_t NS = (n + S - 1) / S, NP = NS * S;
-    const size_t es = sizeof(T);
+    const size_t es = sizeof(T), is = sizeof(int32_t);
+    const bool path = HP != nullptr;
     Streams st;
     FW_TRY(st.create());
     DeviceBuffer buf;
-    FW_TRY(hipMalloc(&buf.p, (size_t)ooc_working_elems(n, S) * es));
+    FW_TRY(hipMalloc(&buf.p, ooc_working_bytes(n, S, es, path)));
     T *Dd = (T *)buf.p, *TMP = Dd + S * S, *Cb[2] = {TMP + S * S, TMP + 2 * S * S};
     T *RB = Cb[1] + S * S;  // S x NP, leading dimension NP
     T *CB = RB + S * NP;    // NP x S, leading dimension S
+    // Labels, same shapes (path mode), plus the diagonal block's local labels.
+    int32_t *Pd = path ? (int32_t *)(CB + NP * S) : nullptr, *TMPP = path ? Pd + S * S : nullptr;
+    int32_t *CbP[2] = {path ? TMPP + S * S : nullptr, path ? TMPP + 2 * S * S : nullptr};
+    int32_t *RBP = path ? CbP[1] + S * S : nullptr, *CBP = path ? RBP + S * NP : nullptr;
+    int32_t *Ploc = path ? CBP + NP * S : nullptr;
     const hipStream_t cs = st.cs;
+    if (path) {  // P starts as "no interior vertex"
+        const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        std::vector<std::thread> th;
+        const int64_t total = n * n, per = (total + nt - 1) / nt;
+        for (unsigned t = 0; t < nt; ++t)
+            th.emplace_back([=] { std::fill(HP + std::min(total, t * per), HP + std::min(total, (t + 1) * per), -1); });
+        for (auto &x : th) x.join();
+    }
     // Order after the caller's earlier work on its stream.
     FW_TRY(hipEventRecord(st.start, user));
     FW_TRY(hipStreamWaitEvent(cs, st.start, 0));
     // Tile buffers start blank; uploads into them wait for that.
     FW_TRY(launch_fill_blank<T>(Cb[0], S, S, S, false, cs));
     FW_TRY(launch_fill_blank<T>(Cb[1], S, S, S, false, cs));
+    if (path) {
+        FW_TRY(launch_fill_i32(CbP[0], S * S, -1, cs));
+        FW_TRY(launch_fill_i32(CbP[1], S * S, -1, cs));
+    }
     FW_TRY(hipEventRecord(st.start, cs));
     FW_TRY(hipStreamWaitEvent(st.h2d, st.start, 0));
     auto edge = [&](int64_t b) { return std::min(S, n - b * S); };
@@ -97,30 +124,60 @@ hipError_t run_ooc(int64_t n, T *H, int64_t S, hipStream_t user, const char **wh
         // 1. diagonal super-block, closed in core
         FW_TRY(launch_fill_blank<T>(Dd, S, S, S, true, cs));  // padding vertices are isolated
         FW_TRY(hipMemcpy2DAsync(Dd, S * es, H + K0 * n + K0, n * es, SK * es, SK, H2D, cs));
-        if (fw_apsp(dt, S, Dd, nullptr, cs) != FW_OK) {
+        if (path) {
+            FW_TRY(launch_fill_i32(Pd, S * S, -1, cs));
+            FW_TRY(hipMemcpy2DAsync(Pd, S * is, HP + K0 * n + K0, n * is, SK * is, SK, H2D, cs));
+        }
+        if (fw_apsp(dt, S, Dd, Ploc, cs) != FW_OK) {
             *what = "in-core closure of the diagonal super-block";
             return hipErrorUnknown;
         }
         FW_TRY(hipMemcpy2DAsync(H + K0 * n + K0, n * es, Dd, S * es, SK * es, SK, D2H, cs));
+        if (path) {
+            FW_TRY(launch_merge_labels(Pd, Ploc, S * S, (int32_t)K0, cs));
+            FW_TRY(hipMemcpy2DAsync(HP + K0 * n + K0, n * is, Pd, S * is, SK * is, SK, D2H, cs));
+        }
         if (NS == 1) break;
         // 2. row band
         FW_TRY(launch_fill_blank<T>(RB, NP, S, NP, false, cs));  // padding rows and columns: +inf
         FW_TRY(hipMemcpy2DAsync(RB, NP * es, H + K0 * n, n * es, n * es, SK, H2D, cs));
+        if (path) {
+            FW_TRY(launch_fill_i32(RBP, S * NP, -1, cs));
+            FW_TRY(hipMemcpy2DAsync(RBP, NP * is, HP + K0 * n, n * is, n * is, SK, H2D, cs));
+        }
         for (int64_t J = 0; J < NS; ++J) {
             if (J == R) continue;
             FW_TRY(hipMemcpy2DAsync(TMP, S * es, RB + J * S, NP * es, S * es, S, D2D, cs));
-            FW_TRY(launch_minplus<T>(RB + J * S, NP, Dd, S, TMP, S, S, S, S, cs));
+            if (path) {
+                FW_TRY(hipMemcpy2DAsync(TMPP, S * is, RBP + J * S, NP * is, S * is, S, D2D, cs));
+                FW_TRY(launch_minplus_lex<T>(RB + J * S, RBP + J * S, NP, Dd, Pd, S, TMP, TMPP, S, S, S, S,
+                                             (int32_t)K0, cs));
+            } else {
+                FW_TRY(launch_minplus<T>(RB + J * S, NP, Dd, S, TMP, S, S, S, S, cs));
+            }
         }
         FW_TRY(hipMemcpy2DAsync(H + K0 * n, n * es, RB, NP * es, n * es, SK, D2H, cs));
+        if (path) FW_TRY(hipMemcpy2DAsync(HP + K0 * n, n * is, RBP, NP * is, n * is, SK, D2H, cs));
         // 3. column band
         FW_TRY(launch_fill_blank<T>(CB, S, NP, S, false, cs));
         FW_TRY(hipMemcpy2DAsync(CB, S * es, H + K0, n * es, SK * es, n, H2D, cs));
+        if (path) {
+            FW_TRY(launch_fill_i32(CBP, NP * S, -1, cs));
+            FW_TRY(hipMemcpy2DAsync(CBP, S * is, HP + K0, n * is, SK * is, n, H2D, cs));
+        }
         for (int64_t I = 0; I < NS; ++I) {
             if (I == R) continue;
             FW_TRY(hipMemcpyAsync(TMP, CB + I * S * S, (size_t)(S * S) * es, D2D, cs));
-            FW_TRY(launch_minplus<T>(CB + I * S * S, S, TMP, S, Dd, S, S, S, S, cs));
+            if (path) {
+                FW_TRY(hipMemcpyAsync(TMPP, CBP + I * S * S, (size_t)(S * S) * is, D2D, cs));
+                FW_TRY(launch_minplus_lex<T>(CB + I * S * S, CBP + I * S * S, S, TMP, TMPP, S, Dd, Pd, S, S, S, S,
+                                             (int32_t)K0, cs));
+            } else {
+                FW_TRY(launch_minplus<T>(CB + I * S * S, S, TMP, S, Dd, S, S, S, S, cs));
+            }
         }
         FW_TRY(hipMemcpy2DAsync(H + K0, n * es, CB, S * es, SK * es, n, D2H, cs));
+        if (path) FW_TRY(hipMemcpy2DAsync(HP + K0, n * is, CBP, S * is, SK * is, n, D2H, cs));
         // 4. the other super-tiles: upload (h2d) -> product (cs) -> download (d2h).
         // Uploads may start during steps 1-3: those tiles are disjoint from
         // the blocks and bands written back there.
@@ -132,14 +189,21 @@ hipError_t run_ooc(int64_t n, T *H, int64_t S, hipStream_t user, const char **wh
                 const int b = (int)(t & 1);
                 const int64_t SI = edge(I), SJ = edge(J);
                 T *h = H + I * S * n + J * S;
+                int32_t *hp = path ? HP + I * S * n + J * S : nullptr;
                 if (t >= 2) FW_TRY(hipStreamWaitEvent(st.h2d, st.stored[b], 0));  // buffer b is free again
                 FW_TRY(hipMemcpy2DAsync(Cb[b], S * es, h, n * es, SJ * es, SI, H2D, st.h2d));
+                if (path) FW_TRY(hipMemcpy2DAsync(CbP[b], S * is, hp, n * is, SJ * is, SI, H2D, st.h2d));
                 FW_TRY(hipEventRecord(st.loaded[b], st.h2d));
                 FW_TRY(hipStreamWaitEvent(cs, st.loaded[b], 0));
-                FW_TRY(launch_minplus<T>(Cb[b], S, CB + I * S * S, S, RB + J * S, NP, S, S, S, cs));
+                if (path)
+                    FW_TRY(launch_minplus_lex<T>(Cb[b], CbP[b], S, CB + I * S * S, CBP + I * S * S, S, RB + J * S,
+                                                 RBP + J * S, NP, S, S, S, (int32_t)K0, cs));
+                else
+                    FW_TRY(launch_minplus<T>(Cb[b], S, CB + I * S * S, S, RB + J * S, NP, S, S, S, cs));
                 FW_TRY(hipEventRecord(st.computed[b], cs));
                 FW_TRY(hipStreamWaitEvent(st.d2h, st.computed[b], 0));
                 FW_TRY(hipMemcpy2DAsync(h, n * es, Cb[b], S * es, SJ * es, SI, D2H, st.d2h));
+                if (path) FW_TRY(hipMemcpy2DAsync(hp, n * is, CbP[b], S * is, SJ * is, SI, D2H, st.d2h));
                 FW_TRY(hipEventRecord(st.stored[b], st.d2h));
                 ++t;
             }
@@ -153,7 +217,7 @@ hipError_t run_ooc(int64_t n, T *H, int64_t S, hipStream_t user, const char **wh
     return hipSuccess;
 }
 
-template hipError_t run_ooc<float>(int64_t, float *, int64_t, hipStream_t, const char **);
-template hipError_t run_ooc<double>(int64_t, double *, int64_t, hipStream_t, const char **);
+template hipError_t run_ooc<float>(int64_t, float *, int32_t *, int64_t, hipStream_t, const char **);
+template hipError_t run_ooc<double>(int64_t, double *, int32_t *, int64_t, hipStream_t, const char **);
 
 }  // namespace fw

@@ -316,7 +316,7 @@ int32_t fw_list_configs(fw_dtype_t dt, fw_config_t *out, int32_t cap) {
     return total;
 }
 
-int64_t fw_ooc_superblock(fw_dtype_t dt, int64_t n, size_t device_bytes) {
+int64_t fw_ooc_superblock(fw_dtype_t dt, int64_t n, int32_t path, size_t device_bytes) {
     g_err[0] = 0;
     if (dt != FW_F32 && dt != FW_F64) return fail(FW_EINVAL, "unknown dtype %d", (int)dt);
     if (n < 1 || n > kMaxN) return fail(FW_EINVAL, "n = %lld outside [1, %lld]", (long long)n, (long long)kMaxN);
@@ -329,20 +329,21 @@ int64_t fw_ooc_superblock(fw_dtype_t dt, int64_t n, size_t device_bytes) {
     const size_t es = dt == FW_F32 ? 4 : 8;
     constexpr int64_t unit = 256;
     for (int64_t S = (n + unit - 1) / unit * unit; S >= unit; S -= unit)
-        if ((size_t)fw::ooc_working_elems(n, S) * es <= device_bytes) return S;
+        if (fw::ooc_working_bytes(n, S, es, path != 0) <= device_bytes) return S;
     return fail(FW_ENOMEM, "%zu device bytes hold no working set for n = %lld (need %zu for 256-vertex super-blocks)",
-                device_bytes, (long long)n, (size_t)fw::ooc_working_elems(n, unit) * es);
+                device_bytes, (long long)n, fw::ooc_working_bytes(n, unit, es, path != 0));
 }
 
-fw_status_t fw_apsp_ooc(fw_dtype_t dt, int64_t n, void *dist_host, size_t device_bytes, void *stream) {
+fw_status_t fw_apsp_ooc(fw_dtype_t dt, int64_t n, void *dist_host, int32_t *path_host, size_t device_bytes,
+                        void *stream) {
     g_err[0] = 0;
     fw_status_t st = check_common(dt, n, dist_host);
     if (st != FW_OK) return st;
-    const int64_t S = fw_ooc_superblock(dt, n, device_bytes);
+    const int64_t S = fw_ooc_superblock(dt, n, path_host != nullptr, device_bytes);
     if (S < 0) return (fw_status_t)S;
     const char *what = "";
-    hipError_t e = dt == FW_F32 ? fw::run_ooc<float>(n, (float *)dist_host, S, (hipStream_t)stream, &what)
-                                : fw::run_ooc<double>(n, (double *)dist_host, S, (hipStream_t)stream, &what);
+    hipError_t e = dt == FW_F32 ? fw::run_ooc<float>(n, (float *)dist_host, path_host, S, (hipStream_t)stream, &what)
+                                : fw::run_ooc<double>(n, (double *)dist_host, path_host, S, (hipStream_t)stream, &what);
     if (e != hipSuccess) return hip_fail(e, what);
     return FW_OK;
 }

@@ -135,18 +135,21 @@ def test_backward_argument_errors_before_device(fw):
 
 
 def test_ooc_superblock_choice(fw):
-    """The super-block edge is the largest multiple of 256 whose working set
-    (4 S^2 + 2 S ceil(n/S) S elements) fits the given byte budget."""
-    def elems(n, S):
+    """The super-block edge is the largest multiple of 256 whose working set fits
+    the byte budget: 4 S^2 + 2 S ceil(n/S) S elements, and with the path matrix
+    as many int32 labels plus S^2 more."""
+    def need(n, S, es, path):
         nb = -(-n // S)
-        return 4 * S * S + 2 * S * nb * S
+        blocks = 4 * S * S + 2 * S * nb * S
+        return blocks * es + ((blocks + S * S) * 4 if path else 0)
     for dt, es in ((fw.FW_F32, 4), (fw.FW_F64, 8)):
-        for n in (1, 300, 3000, 16384, 100000):
-            for S_want in (256, 512, 1024, 4096):
-                budget = elems(n, S_want) * es
-                S = fw.fw_ooc_superblock(dt, n, budget)
-                assert S % 256 == 0 and elems(n, S) * es <= budget
-                top = -(-n // 256) * 256
-                assert S == top or elems(n, S + 256) * es > budget
-        assert fw.lib().fw_ooc_superblock(dt, 3000, 1000) == fw.FW_ENOMEM
-    assert fw.lib().fw_ooc_superblock(9, 3000, 1 << 30) == fw.FW_EINVAL
+        for path in (False, True):
+            for n in (1, 300, 3000, 16384, 100000):
+                for S_want in (256, 512, 1024, 4096):
+                    budget = need(n, S_want, es, path)
+                    S = fw.fw_ooc_superblock(dt, n, path, budget)
+                    assert S % 256 == 0 and need(n, S, es, path) <= budget
+                    top = -(-n // 256) * 256
+                    assert S == top or need(n, S + 256, es, path) > budget
+            assert fw.lib().fw_ooc_superblock(dt, 3000, 1 if path else 0, 1000) == fw.FW_ENOMEM
+    assert fw.lib().fw_ooc_superblock(9, 3000, 0, 1 << 30) == fw.FW_EINVAL
