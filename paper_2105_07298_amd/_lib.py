@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libfwapsp.so")
 FW_F32, FW_F64 = 0, 1
 FW_OK, FW_EINVAL, FW_ENOMEM, FW_EHIP, FW_EUNSUPPORTED = 0, -1, -2, -3, -4
 FW_P4_PANELS, FW_P4_WAVEROWS = 1, 2
-FW_SCHED_SERIAL, FW_SCHED_LOOKAHEAD = 1, 2
+FW_SCHED_SERIAL, FW_SCHED_LOOKAHEAD, FW_SCHED_PAIRS = 1, 2, 3
 
 EXPORTS = ("fw_apsp", "fw_apsp_config", "fw_query_config", "fw_list_configs", "fw_apsp_ooc", "fw_ooc_superblock",
            "fw_apsp_batched", "fw_apsp_batched_config",
@@ -170,3 +170,11 @@ def lookahead_applies(block: int, tile_m: int, tile_n: int, n: int) -> bool:
     unit = max(block, tile_m, tile_n)
     npad = -(-n // unit) * unit
     return tile_n == block and block % tile_m == 0 and npad // block >= 3
+
+
+def pairs_applies(block: int, tile_m: int, tile_n: int, variant: int, n: int) -> bool:
+    """Whether FW_SCHED_PAIRS changes anything for this configuration (else it runs serially):
+    LDS-panel tiles exactly one block square and at least 2 rounds after padding."""
+    unit = max(block, tile_m, tile_n)
+    npad = -(-n // unit) * unit
+    return variant == FW_P4_PANELS and tile_m == block and tile_n == block and npad // block >= 2

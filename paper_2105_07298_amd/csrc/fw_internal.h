@@ -12,6 +12,7 @@ constexpr int FW_VARIANT_WAVEROWS = 2;
 // Round schedules: one stream, or lookahead on an auxiliary stream.
 constexpr int FW_SCHEDULE_SERIAL = 1;
 constexpr int FW_SCHEDULE_LOOKAHEAD = 2;
+constexpr int FW_SCHEDULE_PAIRS = 3;
 
 // Round depth (the paper's TB), last-phase output tile (rows x columns),
 // last-phase kernel and round schedule.
@@ -34,18 +35,26 @@ template <typename T>
 hipError_t launch_phase123(T *D, int32_t *P, uint16_t *L, int64_t ld, int r, int block, hipStream_t s);
 
 // Phase 4 of round r over a selection of its tiles:
-//   all    every tile outside block row and column r;
-//   cross  the tiles of block row and column r + 1 (outside block row and
-//          column r): what phases 1-3 of round r + 1 read and write;
-//   rest   every tile outside block rows and columns r and r + 1.
-// cross and rest need lookahead_supported(cfg) and r + 1 < ld / block.
-enum class P4Mode { all, cross, rest };
+//   all        every tile outside block row and column r;
+//   cross      the tiles of block row and column r + 1 (outside block row and
+//              column r): what phases 1-3 of round r + 1 read and write;
+//   rest       every tile outside block rows and columns r and r + 1;
+//   crossprev  the tiles of block row and column r - 1 outside block row and
+//              column r (round r applied to the block before it);
+//   pair       rounds r and r + 1 in one pass over the rest tiles (both
+//              rounds' panels final; pairs_supported(cfg)).
+// cross, rest, crossprev and pair need lookahead_supported(cfg) and a next
+// round (crossprev: r >= 1).
+enum class P4Mode { all, cross, rest, crossprev, pair };
 template <typename T>
 hipError_t launch_phase4(T *D, uint16_t *L, bool path, int64_t ld, int r, TileCfg cfg, P4Mode mode, hipStream_t s);
 
 // Tiles exactly one block wide and at most one block tall, so that block row
 // and column r + 1 are whole tiles.
 bool lookahead_supported(TileCfg cfg);
+
+// LDS-panel tiles exactly one block square: the fused pair launch exists.
+bool pairs_supported(TileCfg cfg);
 
 // Compiled (block, tile_m, tile_n, variant) combinations for element type T.
 template <typename T>

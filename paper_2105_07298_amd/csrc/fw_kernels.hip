@@ -266,7 +266,7 @@ __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__re
 // marked pending (L = r + 1) and resolved by k_resolve.  L is read with the old
 // tile and, for each 16-byte vector of D that changed, the matching run of L
 // (8 bytes for float, 4 for double) is written back whole.
-template <typename T, int TB, int BM, int BN, bool PATH, bool CROSS>
+template <typename T, int TB, int BM, int BN, bool PATH, bool CROSS, bool FUSE = false>
 __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__restrict__ L, int64_t ld, int r,
                                               TileSel sel) {
     constexpr int RM = BM / 16, RN = BN / 16;  // 16 x 16 threads
@@ -287,8 +287,6 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
     int bi, bj;
     if (!select_tile<CROSS>(sel, blockIdx.x, bi, bj)) return;
     const int64_t I0 = (int64_t)bi * BM, J0 = (int64_t)bj * BN, k0 = (int64_t)r * TB;
-    const bool mask_rows = sel.nsr == 0 && (I0 <= k0) && (k0 < I0 + BM);
-    const bool mask_cols = sel.nsc == 0 && (J0 <= k0) && (k0 < J0 + BN);
 
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
     auto c_ptr = [&](int ii, int h) { return D + (I0 + ty + TY * ii) * ld + J0 + h * CS + tx * V; };
@@ -309,50 +307,75 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
             }
     }
 
-    const vec vinf = inf_v<T>();
-    for (int q = tid; q < BM * (TB / V); q += NT) {
-        const int row = q / (TB / V), kv = q % (TB / V);
-        vec v = *(const vec *)(D + (I0 + row) * ld + k0 + kv * V);
-        if (mask_rows && (uint64_t)(I0 + row - k0) < (uint64_t)TB) v = vinf;
-        *(vec *)(As + row * AST + kv * V) = v;
-    }
-    for (int q = tid; q < TB * (BN / V); q += NT) {
-        const int krow = q / (BN / V), cv = q % (BN / V);
-        vec v = *(const vec *)(D + (k0 + krow) * ld + J0 + cv * V);
-        if (mask_cols && (uint64_t)(J0 + cv * V - k0) < (uint64_t)TB) v = vinf;
-        *(vec *)(Bs + krow * BN + cv * V) = v;
-    }
-    __syncthreads();
-
-    T acc[RM][RN];
-#pragma unroll
-    for (int ii = 0; ii < RM; ++ii)
-#pragma unroll
-        for (int jj = 0; jj < RN; ++jj) acc[ii][jj] = inf_v<T>();
-
-#pragma unroll 2
-    for (int kv = 0; kv < TB / V; ++kv) {
-        vec a[RM];
-#pragma unroll
-        for (int ii = 0; ii < RM; ++ii) a[ii] = *(const vec *)(As + (ty + TY * ii) * AST + kv * V);
-#pragma unroll
-        for (int kk = 0; kk < V; kk += 2) {
-            vec b0[HN], b1[HN];
-#pragma unroll
-            for (int h = 0; h < HN; ++h) {
-                b0[h] = *(const vec *)(Bs + (kv * V + kk) * BN + h * CS + tx * V);
-                b1[h] = *(const vec *)(Bs + (kv * V + kk + 1) * BN + h * CS + tx * V);
-            }
-#pragma unroll
-            for (int ii = 0; ii < RM; ++ii)
-#pragma unroll
-                for (int h = 0; h < HN; ++h)
-#pragma unroll
-                    for (int e = 0; e < V; ++e) {
-                        T &x = acc[ii][h * V + e];
-                        x = vmin(vmin(x, a[ii][kk] + b0[h][e]), a[ii][kk + 1] + b1[h][e]);
-                    }
+    // Stage the column panel D[I, K] and row panel D[K, J] of the block that
+    // starts at kb; the block's own rows / columns are masked in a tile wider
+    // than the block.
+    auto stage = [&](int64_t kb) {
+        const bool mask_rows = sel.nsr == 0 && (I0 <= kb) && (kb < I0 + BM);
+        const bool mask_cols = sel.nsc == 0 && (J0 <= kb) && (kb < J0 + BN);
+        const vec vinf = inf_v<T>();
+        for (int q = tid; q < BM * (TB / V); q += NT) {
+            const int row = q / (TB / V), kv = q % (TB / V);
+            vec v = *(const vec *)(D + (I0 + row) * ld + kb + kv * V);
+            if (mask_rows && (uint64_t)(I0 + row - kb) < (uint64_t)TB) v = vinf;
+            *(vec *)(As + row * AST + kv * V) = v;
         }
+        for (int q = tid; q < TB * (BN / V); q += NT) {
+            const int krow = q / (BN / V), cv = q % (BN / V);
+            vec v = *(const vec *)(D + (kb + krow) * ld + J0 + cv * V);
+            if (mask_cols && (uint64_t)(J0 + cv * V - kb) < (uint64_t)TB) v = vinf;
+            *(vec *)(Bs + krow * BN + cv * V) = v;
+        }
+    };
+
+    // acc <- min over the staged block of A[i][k] + B[k][j].
+    T acc[RM][RN];
+    auto sweep = [&]() {
+#pragma unroll
+        for (int ii = 0; ii < RM; ++ii)
+#pragma unroll
+            for (int jj = 0; jj < RN; ++jj) acc[ii][jj] = inf_v<T>();
+#pragma unroll 2
+        for (int kv = 0; kv < TB / V; ++kv) {
+            vec a[RM];
+#pragma unroll
+            for (int ii = 0; ii < RM; ++ii) a[ii] = *(const vec *)(As + (ty + TY * ii) * AST + kv * V);
+#pragma unroll
+            for (int kk = 0; kk < V; kk += 2) {
+                vec b0[HN], b1[HN];
+#pragma unroll
+                for (int h = 0; h < HN; ++h) {
+                    b0[h] = *(const vec *)(Bs + (kv * V + kk) * BN + h * CS + tx * V);
+                    b1[h] = *(const vec *)(Bs + (kv * V + kk + 1) * BN + h * CS + tx * V);
+                }
+#pragma unroll
+                for (int ii = 0; ii < RM; ++ii)
+#pragma unroll
+                    for (int h = 0; h < HN; ++h)
+#pragma unroll
+                        for (int e = 0; e < V; ++e) {
+                            T &x = acc[ii][h * V + e];
+                            x = vmin(vmin(x, a[ii][kk] + b0[h][e]), a[ii][kk + 1] + b1[h][e]);
+                        }
+            }
+        }
+    };
+
+    stage(k0);
+    __syncthreads();
+    sweep();
+    // A fused pair (rounds r and r + 1, tiles outside both blocks): keep round
+    // r's minimum, then sweep round r + 1's panels, which are final by now.
+    T acc0[FUSE ? RM : 1][FUSE ? RN : 1];
+    if constexpr (FUSE) {
+#pragma unroll
+        for (int ii = 0; ii < RM; ++ii)
+#pragma unroll
+            for (int jj = 0; jj < RN; ++jj) acc0[ii][jj] = acc[ii][jj];
+        __syncthreads();  // every thread is done with round r's panels
+        stage(k0 + TB);
+        __syncthreads();
+        sweep();
     }
 
     if constexpr (!PREFETCH_C) {
@@ -366,28 +389,40 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
     }
 
     // New distances: store the 16-byte vectors in which some entry decreased;
-    // in path mode mark each decreased entry pending from this round.
+    // in path mode mark each decreased entry pending from the last round in
+    // which it decreased (r, or r + 1 for a fused pair).
     const uint16_t pend = (uint16_t)(r + 1);
 #pragma unroll
     for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
         for (int h = 0; h < HN; ++h) {
             vec nv = c[ii][h];
-            bool lt[V];
+            uint16_t mk[V];
             bool ch = false;
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 const T s = acc[ii][h * V + e];
-                lt[e] = s < nv[e];
-                ch |= lt[e];
-                nv[e] = lt[e] ? s : nv[e];
+                if constexpr (FUSE) {
+                    const T s0 = acc0[ii][h * V + e];
+                    const bool lt0 = s0 < nv[e];
+                    const T c1 = lt0 ? s0 : nv[e];
+                    const bool lt1 = s < c1;
+                    nv[e] = lt1 ? s : c1;
+                    mk[e] = lt1 ? (uint16_t)(pend + 1) : (lt0 ? pend : (uint16_t)0);
+                    ch |= lt0 || lt1;
+                } else {
+                    const bool lt = s < nv[e];
+                    nv[e] = lt ? s : nv[e];
+                    mk[e] = lt ? pend : (uint16_t)0;
+                    ch |= lt;
+                }
             }
             if (ch) {
                 *(vec *)c_ptr(ii, h) = nv;
                 if constexpr (PATH) {
                     lvec nl = lm[ii][h];
 #pragma unroll
-                    for (int e = 0; e < V; ++e) nl[e] = lt[e] ? pend : nl[e];
+                    for (int e = 0; e < V; ++e) nl[e] = mk[e] ? mk[e] : nl[e];
                     *(lvec *)l_ptr(ii, h) = nl;
                 }
             }
@@ -808,41 +843,64 @@ void launch_p123(T *D, int32_t *P, uint16_t *L, int64_t ld, int r, hipStream_t s
         hipLaunchKernelGGL((k_phase23<T, TB, false>), dim3(2 * (nb - 1)), dim3(NT), 0, s, D, P, L, ld, r, nb);
 }
 
-// One last-phase launch (mode all / rest / cross, see TileSel) with the
-// LDS-panel kernel (WAVE = false) or the wave-row kernel (BM = 4 * RM).
+// One last-phase launch (mode all / cross / rest / crossprev / pair, see
+// P4Mode) with the LDS-panel kernel (WAVE = false) or the wave-row kernel
+// (BM = 4 * RM).  r is the round applied (the first of the two for a pair).
 template <typename T, int TB, int BM, int BN, bool WAVE>
 hipError_t p4_impl(T *D, uint16_t *L, bool path, int64_t ld, int r, P4Mode mode, hipStream_t s) {
     const int rb = BM <= TB ? TB / BM : 0;  // tile rows per block; 0: the block row is masked
     const int cb = BN == TB ? 1 : 0;        // likewise for columns
+    int sel_mode = 0, sel_r = r;
+    switch (mode) {
+    case P4Mode::all: sel_mode = 0; break;
+    case P4Mode::cross: sel_mode = 1; break;
+    case P4Mode::rest: sel_mode = 2; break;
+    case P4Mode::crossprev: sel_mode = 3; sel_r = r - 1; break;  // block r - 1, skipping block r
+    case P4Mode::pair: sel_mode = 2; break;                      // the rest of rounds r and r + 1
+    }
+    if (sel_r < 0) return hipErrorInvalidValue;
+    if (mode == P4Mode::pair && (WAVE || r + 2 > (int)(ld / TB))) return hipErrorInvalidValue;
     TileSel sel;
-    int64_t upd;
-    if (!make_tile_sel((int)(ld / BM), (int)(ld / BN), rb, cb, r, (int)(ld / TB), (int)mode, sel))
+    if (!make_tile_sel((int)(ld / BM), (int)(ld / BN), rb, cb, sel_r, (int)(ld / TB), sel_mode, sel))
         return hipErrorInvalidValue;
     if (sel.ntiles == 0) return hipSuccess;
-    {
-        const int64_t w = mode == P4Mode::rest ? 2 : 1;
-        upd = (ld - w * TB) * (ld - w * TB) * TB;  // algorithmic min-plus updates (all / rest)
-    }
+    const bool cross = mode == P4Mode::cross || mode == P4Mode::crossprev;
+    int64_t upd = 0;  // algorithmic min-plus updates of the bulk launches (timed)
+    if (mode == P4Mode::all) upd = (ld - TB) * (ld - TB) * TB;
+    if (mode == P4Mode::rest) upd = (ld - 2 * TB) * (ld - 2 * TB) * TB;
+    if (mode == P4Mode::pair) upd = 2 * (ld - 2 * TB) * (ld - 2 * TB) * TB;
     const dim3 grid(8 * sel.per_xcd);
     constexpr int RM = BM / (NT / 64), RN = BN / 64;
-#define FW_P4_LAUNCH(PATHV, CROSSV)                                                                          \
-    do {                                                                                                  \
-        if constexpr (WAVE)                                                                               \
-            hipLaunchKernelGGL((k_phase4w<T, TB, RM, RN, PATHV, CROSSV>), grid, dim3(NT), 0, s, D, L, ld, r, sel); \
-        else                                                                                              \
-            hipLaunchKernelGGL((k_phase4<T, TB, BM, BN, PATHV, CROSSV>), grid, dim3(NT), 0, s, D, L, ld, r, sel);  \
+#define FW_P4_LAUNCH(PATHV, CROSSV, FUSEV)                                                                          \
+    do {                                                                                                         \
+        if constexpr (WAVE) {                                                                                    \
+            if constexpr (!FUSEV)                                                                                \
+                hipLaunchKernelGGL((k_phase4w<T, TB, RM, RN, PATHV, CROSSV>), grid, dim3(NT), 0, s, D, L, ld, r,   \
+                                   sel);                                                                         \
+        } else {                                                                                                 \
+            hipLaunchKernelGGL((k_phase4<T, TB, BM, BN, PATHV, CROSSV, FUSEV>), grid, dim3(NT), 0, s, D, L, ld, r, \
+                               sel);                                                                             \
+        }                                                                                                        \
     } while (0)
-    if (mode == P4Mode::cross) {
+    if (cross) {
         if (path)
-            FW_P4_LAUNCH(true, true);
+            FW_P4_LAUNCH(true, true, false);
         else
-            FW_P4_LAUNCH(false, true);
+            FW_P4_LAUNCH(false, true, false);
     } else {
         prof_begin_p4(s);
-        if (path)
-            FW_P4_LAUNCH(true, false);
-        else
-            FW_P4_LAUNCH(false, false);
+        if (mode == P4Mode::pair) {
+            if constexpr (!WAVE && BM == TB && BN == TB) {
+                if (path)
+                    FW_P4_LAUNCH(true, false, true);
+                else
+                    FW_P4_LAUNCH(false, false, true);
+            }
+        } else if (path) {
+            FW_P4_LAUNCH(true, false, false);
+        } else {
+            FW_P4_LAUNCH(false, false, false);
+        }
         prof_end_p4(s, upd);
     }
 #undef FW_P4_LAUNCH
@@ -942,6 +1000,10 @@ hipError_t launch_phase4(T *D, uint16_t *L, bool path, int64_t ld, int r, TileCf
 }
 
 bool lookahead_supported(TileCfg c) { return c.tile_n == c.block && c.tile_m <= c.block; }
+
+bool pairs_supported(TileCfg c) {
+    return c.variant == FW_VARIANT_PANELS && c.tile_m == c.block && c.tile_n == c.block;
+}
 
 template <typename T>
 hipError_t launch_minplus(T *C, int64_t ldc, const T *A, int64_t lda, const T *B, int64_t ldb, int64_t M, int64_t N,

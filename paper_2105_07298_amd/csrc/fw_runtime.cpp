@@ -17,7 +17,8 @@
 
 static_assert(fw::FW_VARIANT_PANELS == FW_P4_PANELS && fw::FW_VARIANT_WAVEROWS == FW_P4_WAVEROWS,
               "variant codes of the C ABI");
-static_assert(fw::FW_SCHEDULE_SERIAL == FW_SCHED_SERIAL && fw::FW_SCHEDULE_LOOKAHEAD == FW_SCHED_LOOKAHEAD,
+static_assert(fw::FW_SCHEDULE_SERIAL == FW_SCHED_SERIAL && fw::FW_SCHEDULE_LOOKAHEAD == FW_SCHED_LOOKAHEAD &&
+                  fw::FW_SCHEDULE_PAIRS == FW_SCHED_PAIRS,
               "schedule codes of the C ABI");
 
 namespace {
@@ -136,6 +137,21 @@ hipError_t run_rounds(T *D, int32_t *P, uint16_t *L, int64_t ld, fw::TileCfg cfg
     hipError_t e;
     int dev = -1;
     Aux *aux = nullptr;
+    if (cfg.schedule == fw::FW_SCHEDULE_PAIRS && R >= 2 && fw::pairs_supported(cfg)) {
+        // Pairs of rounds on one stream: round r's last phase on block r + 1,
+        // phases 1-3 of round r + 1, both rounds' last phase on every other tile
+        // in one pass, then round r + 1's on block r (after that pass has read
+        // block r as round r's panels).
+        for (int r = 0; r < R; r += 2) {
+            if ((e = fw::launch_phase123<T>(D, P, L, ld, r, cfg.block, s)) != hipSuccess) return e;
+            if (r + 1 == R) return fw::launch_phase4<T>(D, L, path, ld, r, cfg, P4Mode::all, s);
+            if ((e = fw::launch_phase4<T>(D, L, path, ld, r, cfg, P4Mode::cross, s)) != hipSuccess) return e;
+            if ((e = fw::launch_phase123<T>(D, P, L, ld, r + 1, cfg.block, s)) != hipSuccess) return e;
+            if ((e = fw::launch_phase4<T>(D, L, path, ld, r, cfg, P4Mode::pair, s)) != hipSuccess) return e;
+            if ((e = fw::launch_phase4<T>(D, L, path, ld, r + 1, cfg, P4Mode::crossprev, s)) != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
     if (cfg.schedule == fw::FW_SCHEDULE_LOOKAHEAD && R >= kLookaheadMinRounds && fw::lookahead_supported(cfg) &&
         hipGetDevice(&dev) == hipSuccess)
         aux = acquire_aux(dev);
@@ -270,9 +286,9 @@ fw_status_t fw_apsp_config(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, 
     fw::TileCfg tc = default_cfg(dt, n, path != nullptr);
     if (cfg) {
         if (cfg->block < 0 || cfg->tile_m < 0 || cfg->tile_n < 0 || cfg->variant < 0 ||
-            cfg->variant > FW_P4_WAVEROWS || cfg->schedule < 0 || cfg->schedule > FW_SCHED_LOOKAHEAD)
+            cfg->variant > FW_P4_WAVEROWS || cfg->schedule < 0 || cfg->schedule > FW_SCHED_PAIRS)
             return fail(FW_EINVAL, "config fields must be 0 (tuned) or positive, variant at most %d, schedule at most %d",
-                        FW_P4_WAVEROWS, FW_SCHED_LOOKAHEAD);
+                        FW_P4_WAVEROWS, FW_SCHED_PAIRS);
         if (cfg->block) tc.block = cfg->block;
         if (cfg->tile_m) tc.tile_m = cfg->tile_m;
         if (cfg->tile_n) tc.tile_n = cfg->tile_n;

@@ -14,18 +14,21 @@ namespace fw {
 //   Normal selection: every tile outside tile rows [sr, sr + nsr) and tile
 //   columns [sc, sc + nsc).  A block row (column) of the round that is narrower
 //   than a tile is not skipped (nsr or nsc = 0) but masked inside its tile.
-//   Cross selection (lookahead; tiles one block wide, rb tile rows per block):
-//   the tiles of block row and block column c = cross, except those in block
-//   row / column c - 1, whose round this is.  Together with a normal selection
-//   that skips block rows and columns c - 1 and c it covers the round.
+//   Cross selection (tiles one block wide, rb tile rows per block): the tiles
+//   of block row and block column c = cross, except those in block row /
+//   column xs = c - 1 or c + 1.  With xs = c - 1 (round c - 1, lookahead) and a
+//   normal selection that skips block rows and columns c - 1 and c, it covers
+//   round c - 1; with xs = c + 1 (round c + 1 applied to block c) and the same
+//   normal selection, it covers round c + 1.
 struct TileSel {
     int gm, gn;
     int sr, nsr, sc, nsc;
-    int cross, rb;
+    int cross, xs, rb;
     int per_xcd, ntiles;
 };
 
-// Launch modes (the values of P4Mode): 0 all, 1 cross, 2 rest.
+// Launch modes (the values of P4Mode): 0 all, 1 cross (block r + 1, skipping
+// r), 2 rest (skipping blocks r and r + 1), 3 cross of block r skipping r + 1.
 // rb / cb: tile rows / columns per block (0 when a tile is wider than the
 // block).  Fills sel for round r of nblocks; false if the mode does not apply.
 FW_TILE_FN bool make_tile_sel(int gm, int gn, int rb, int cb, int r, int nblocks, int mode, TileSel &sel) {
@@ -36,11 +39,13 @@ FW_TILE_FN bool make_tile_sel(int gm, int gn, int rb, int cb, int r, int nblocks
     sel.sc = gn;
     sel.nsc = 0;
     sel.cross = -1;
+    sel.xs = -1;
     sel.rb = rb;
     int64_t ntiles;
-    if (mode == 1) {
+    if (mode == 1 || mode == 3) {
         if (rb == 0 || cb != 1 || r + 1 >= nblocks) return false;
-        sel.cross = r + 1;
+        sel.cross = mode == 1 ? r + 1 : r;
+        sel.xs = mode == 1 ? r : r + 1;
         sel.nsr = rb;
         sel.nsc = 1;
         ntiles = (int64_t)rb * (gn - 1) + (gm - 2 * rb);
@@ -73,14 +78,14 @@ FW_TILE_FN bool select_tile(const TileSel &t, int wg, int &bi, int &bj) {
     const int lin = (wg % 8) * t.per_xcd + wg / 8;
     if (lin >= t.ntiles) return false;
     if (CROSS) {
-        const int c = t.cross, p = c - 1, nrow = t.rb * (t.gn - 1);
+        const int c = t.cross, xs = t.xs, lo = c < xs ? c : xs, nrow = t.rb * (t.gn - 1);
         if (lin < nrow) {
             bi = c * t.rb + lin % t.rb;
             const int jj = lin / t.rb;
-            bj = jj < p ? jj : jj + 1;
+            bj = jj < xs ? jj : jj + 1;
         } else {
             const int ii = lin - nrow;
-            bi = ii < p * t.rb ? ii : ii + 2 * t.rb;
+            bi = ii < lo * t.rb ? ii : ii + 2 * t.rb;  // blocks c and xs are adjacent
             bj = c;
         }
         return true;

@@ -5,7 +5,7 @@ table compiled into the library).
 Run on the GPU:  python -m paper_2105_07298_amd.tune --out DIR
 It times, with HIP events on the current stream,
   * fw_apsp for every compiled (block, tile_m, tile_n, variant), under each round schedule
-    that applies to it (serial; lookahead), at one representative n per size
+    that applies to it (serial; lookahead; pairs), at one representative n per size
     range, for float32/float64 with and without the path matrix, on complete
     graphs with weights uniform in (0, 1);
   * fw_apsp_batched on batches of equal-size graphs (weights in [1, 10],
@@ -55,8 +55,10 @@ def tune_apsp(fw, torch, log):
                 P = torch.empty((n, n), dtype=torch.int32, device=W.device) if path else None
                 best = None
                 cands = [(b, tm, tn, var, sch) for b, tm, tn, var in fw.fw_list_configs(
-                    fw.FW_F32 if dt == "f32" else fw.FW_F64) for sch in (fw.FW_SCHED_SERIAL, fw.FW_SCHED_LOOKAHEAD)
-                    if sch == fw.FW_SCHED_SERIAL or fw.lookahead_applies(b, tm, tn, n)]
+                    fw.FW_F32 if dt == "f32" else fw.FW_F64)
+                    for sch in (fw.FW_SCHED_SERIAL, fw.FW_SCHED_LOOKAHEAD, fw.FW_SCHED_PAIRS)
+                    if sch == fw.FW_SCHED_SERIAL or (sch == fw.FW_SCHED_LOOKAHEAD and fw.lookahead_applies(b, tm, tn, n))
+                    or (sch == fw.FW_SCHED_PAIRS and fw.pairs_applies(b, tm, tn, var, n))]
                 for block, tm, tn, var, sch in cands:
                     def run():
                         D.copy_(W)

@@ -136,13 +136,20 @@ def test_model_real_weights_tolerance():
     oracle.check_invariants(W, Dm, Pm, exact=False, rtol=1e-12)
 
 
-def blocked_model_deferred(W, TB):
+def blocked_model_deferred(W, TB, schedule="serial"):
     """The GPU's path-mode schedule: phases 1-3 apply the lexicographic rule to P
     (which holds an older label while an entry is pending) and clear the entry's
     mark L when they change it; the last phase only marks strict improvements
     (L = r + 1); one pass after the last round resolves every pending label from
     the final D, in place, skipping the k whose entries are pending from a later
-    round."""
+    round.
+
+    schedule "pairs" runs rounds two at a time as the library's pairs schedule
+    does: round r's last phase on block row / column r + 1, phases 1-3 of round
+    r + 1, then both rounds' last phase in one pass over the tiles outside blocks
+    r and r + 1 (round r's minimum kept apart, the mark naming the last round in
+    which the entry decreased), and only then round r + 1's last phase on block
+    row / column r."""
     n = W.shape[0]
     npad = -(-n // TB) * TB
     D = np.full((npad, npad), np.inf)
@@ -151,9 +158,11 @@ def blocked_model_deferred(W, TB):
     P = np.full((npad, npad), -1, dtype=np.int64)
     L = np.zeros((npad, npad), dtype=np.int64)
     R = npad // TB
-    for r in range(R):
+    blk = lambda b: slice(b * TB, (b + 1) * TB)
+
+    def phases123(r):
         K = np.arange(r * TB, (r + 1) * TB)
-        ks = slice(r * TB, (r + 1) * TB)
+        ks = blk(r)
         D0, P0 = D[ks, ks].copy(), P[ks, ks].copy()
         for k in K:
             s = D[ks, k:k + 1] + D[k:k + 1, ks]
@@ -161,9 +170,8 @@ def blocked_model_deferred(W, TB):
             D[ks, ks], P[ks, ks] = lex_update(D[ks, ks], P[ks, ks], s, m)
         L[ks, ks] = np.where((D[ks, ks] != D0) | (P[ks, ks] != P0), 0, L[ks, ks])
         Dkk, Pkk = D[ks, ks].copy(), P[ks, ks].copy()
-        others = [b for b in range(R) if b != r]
-        for b in others:
-            js = slice(b * TB, (b + 1) * TB)
+        for b in [b for b in range(R) if b != r]:
+            js = blk(b)
             for (rs, cs, A, PA, B, PB) in ((ks, js, Dkk, Pkk, None, None), (js, ks, None, None, Dkk, Pkk)):
                 Dold, Pold = D[rs, cs].copy(), P[rs, cs].copy()
                 if A is not None:
@@ -172,15 +180,48 @@ def blocked_model_deferred(W, TB):
                     Dn, Pn = product_lex(Dold, Pold, B, PB, K, Dold, Pold)
                 D[rs, cs], P[rs, cs] = Dn, Pn
                 L[rs, cs] = np.where((Dn != Dold) | (Pn != Pold), 0, L[rs, cs])
-        for bi in others:
-            for bj in others:
-                is_, js = slice(bi * TB, (bi + 1) * TB), slice(bj * TB, (bj + 1) * TB)
-                S = np.full((TB, TB), np.inf)
-                for t in range(TB):
-                    S = np.minimum(S, D[is_, r * TB + t:r * TB + t + 1] + D[r * TB + t:r * TB + t + 1, js])
-                imp = S < D[is_, js]
-                D[is_, js] = np.where(imp, S, D[is_, js])
-                L[is_, js] = np.where(imp, r + 1, L[is_, js])
+
+    def block_min(r, bi, bj):
+        S = np.full((TB, TB), np.inf)
+        for t in range(TB):
+            S = np.minimum(S, D[blk(bi), r * TB + t:r * TB + t + 1] + D[r * TB + t:r * TB + t + 1, blk(bj)])
+        return S
+
+    def last_phase(r, tiles):
+        for bi, bj in tiles:
+            S = block_min(r, bi, bj)
+            imp = S < D[blk(bi), blk(bj)]
+            D[blk(bi), blk(bj)] = np.where(imp, S, D[blk(bi), blk(bj)])
+            L[blk(bi), blk(bj)] = np.where(imp, r + 1, L[blk(bi), blk(bj)])
+
+    def fused_pair(r, tiles):
+        for bi, bj in tiles:
+            S0 = block_min(r, bi, bj)
+            S1 = block_min(r + 1, bi, bj)
+            C = D[blk(bi), blk(bj)]
+            lt0 = S0 < C
+            C1 = np.where(lt0, S0, C)
+            lt1 = S1 < C1
+            D[blk(bi), blk(bj)] = np.where(lt1, S1, C1)
+            L[blk(bi), blk(bj)] = np.where(lt1, r + 2, np.where(lt0, r + 1, L[blk(bi), blk(bj)]))
+
+    def outside(*bs):
+        return [(bi, bj) for bi in range(R) for bj in range(R) if bi not in bs and bj not in bs]
+
+    if schedule == "serial":
+        for r in range(R):
+            phases123(r)
+            last_phase(r, outside(r))
+    else:
+        for r in range(0, R, 2):
+            phases123(r)
+            if r + 1 == R:
+                last_phase(r, outside(r))
+                break
+            last_phase(r, [t for t in outside(r) if t[0] == r + 1 or t[1] == r + 1])
+            phases123(r + 1)
+            fused_pair(r, outside(r, r + 1))
+            last_phase(r + 1, [t for t in outside(r + 1) if t[0] == r or t[1] == r])
     # resolution, in place, entries in an arbitrary order
     order = np.argwhere(L > 0)
     np.random.default_rng(0).shuffle(order)
@@ -211,5 +252,20 @@ def test_deferred_labels_c1_like():
     W = workloads.int_graph(n=128, p=0.5, wmax=1000, seed=1)
     D, P = oracle.fw(W)
     Dm, Pm = blocked_model_deferred(W.astype(np.float64), 16)
+    np.testing.assert_array_equal(Dm, D)
+    np.testing.assert_array_equal(Pm, P)
+
+
+@pytest.mark.parametrize("TB", [1, 2, 3, 4, 8])
+@pytest.mark.parametrize("seed", range(6))
+def test_pairs_schedule_equals_classic(TB, seed):
+    """The pairs schedule (two rounds' last phase fused on the tiles outside both
+    blocks) gives the classic loop's D and canonical P, ties included, for odd and
+    even round counts."""
+    rng = np.random.default_rng(seed + 90)
+    n = int(rng.integers(5, 48))
+    W = workloads.int_graph(n=n, p=float(rng.uniform(0.05, 0.6)), wmax=int(rng.integers(1, 4)), seed=seed + 270)
+    D, P = oracle.fw(W)
+    Dm, Pm = blocked_model_deferred(W.astype(np.float64), TB, schedule="pairs")
     np.testing.assert_array_equal(Dm, D)
     np.testing.assert_array_equal(Pm, P)

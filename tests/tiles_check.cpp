@@ -62,7 +62,9 @@ int main() {
                         const bool la = rb > 0 && cb == 1 && r + 1 < nb;
                         const bool okc = fw::make_tile_sel(gm, gn, rb, cb, r, nb, 1, cr);
                         const bool okr = fw::make_tile_sel(gm, gn, rb, cb, r, nb, 2, rest);
-                        CHECK(okc == la && okr == la, "lookahead applicability TB=%d BM=%d BN=%d ld=%d r=%d", TB, BM, BN, ld, r);
+                        fw::TileSel tmp;
+                        const bool okp = fw::make_tile_sel(gm, gn, rb, cb, r, nb, 3, tmp);
+                        CHECK(okc == la && okr == la && okp == la, "lookahead applicability TB=%d BM=%d BN=%d ld=%d r=%d", TB, BM, BN, ld, r);
                         if (!la) continue;
                         std::set<Tile> gc, gr;
                         CHECK(visit(cr, true, gc), "cross: tile twice or out of range TB=%d BM=%d ld=%d r=%d", TB, BM, ld, r);
@@ -72,6 +74,22 @@ int main() {
                             (row_in(t.first, r + 1) || col_in(t.second, r + 1) ? wc : wr).insert(t);
                         CHECK(gc == wc, "cross: wrong set TB=%d BM=%d ld=%d r=%d (%zu vs %zu)", TB, BM, ld, r, gc.size(), wc.size());
                         CHECK(gr == wr, "rest: wrong set TB=%d BM=%d ld=%d r=%d (%zu vs %zu)", TB, BM, ld, r, gr.size(), wr.size());
+                        // Pairs: round r + 1 on block r (skipping block r + 1) plus the same
+                        // rest selection covers every tile outside block row / column r + 1.
+                        fw::TileSel cp;
+                        CHECK(fw::make_tile_sel(gm, gn, rb, cb, r, nb, 3, cp), "cross-prev rejected ld=%d r=%d", ld, r);
+                        std::set<Tile> gp;
+                        CHECK(visit(cp, true, gp), "cross-prev: tile twice or out of range TB=%d BM=%d ld=%d r=%d", TB, BM, ld, r);
+                        std::set<Tile> want1, wp;
+                        for (int bi = 0; bi < gm; ++bi)
+                            for (int bj = 0; bj < gn; ++bj)
+                                if (!row_in(bi, r + 1) && !col_in(bj, r + 1)) want1.insert({bi, bj});
+                        for (const Tile &t : want1)
+                            if (row_in(t.first, r) || col_in(t.second, r)) wp.insert(t);
+                        CHECK(gp == wp, "cross-prev: wrong set TB=%d BM=%d ld=%d r=%d (%zu vs %zu)", TB, BM, ld, r, gp.size(), wp.size());
+                        std::set<Tile> uni = gp;
+                        uni.insert(gr.begin(), gr.end());
+                        CHECK(uni == want1 && uni.size() == gp.size() + gr.size(), "pair cover TB=%d BM=%d ld=%d r=%d", TB, BM, ld, r);
                     }
                 }
             }
