@@ -19,6 +19,7 @@
 // and columns beyond n read as isolated padding vertices (+inf off the
 // diagonal, 0 on it, label -1) and are never written.
 #include "fw_internal.h"
+#include "fw_lex.h"
 
 namespace fw {
 namespace {
@@ -38,22 +39,24 @@ struct GraphTiles {
     int32_t *P;
     int n;
 
+    // Lengths pass through canon() in path mode (lex_take_u's key needs +0.0).
     __device__ T ld_d(int i, int j) const {
-        if (i < n && j < n) return D[(int64_t)i * n + j];
+        if (i < n && j < n) return PATH ? canon(D[(int64_t)i * n + j]) : D[(int64_t)i * n + j];
         return i == j ? (T)0 : inf_b<T>();
     }
-    __device__ int32_t ld_p(int i, int j) const {
-        return (i < n && j < n) ? P[(int64_t)i * n + j] : -1;
+    // Labels are held as label + 1 between load and store.
+    __device__ uint32_t ld_p(int i, int j) const {
+        return (i < n && j < n) ? (uint32_t)(P[(int64_t)i * n + j] + 1) : 0u;
     }
     // Stage tile (I0, J0) into LDS (values, and labels in path mode).
-    __device__ void stage(T *sd, int32_t *sp, int I0, int J0) const {
+    __device__ void stage(T *sd, uint32_t *sp, int I0, int J0) const {
         for (int q = threadIdx.x; q < TB * TB; q += NT) {
             const int rr = q / TB, cc = q % TB;
             sd[rr * ST + cc] = ld_d(I0 + rr, J0 + cc);
             if (PATH) sp[rr * ST + cc] = ld_p(I0 + rr, J0 + cc);
         }
     }
-    __device__ void load_regs(T (&d)[RM][RM], int32_t (&p)[RM][RM], int I0, int J0, int tx, int ty) const {
+    __device__ void load_regs(T (&d)[RM][RM], uint32_t (&p)[RM][RM], int I0, int J0, int tx, int ty) const {
 #pragma unroll
         for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
@@ -62,7 +65,7 @@ struct GraphTiles {
                 if (PATH) p[ii][jj] = ld_p(I0 + ty + TS * ii, J0 + tx + TS * jj);
             }
     }
-    __device__ void store_regs(const T (&d)[RM][RM], const int32_t (&p)[RM][RM], int I0, int J0, int tx,
+    __device__ void store_regs(const T (&d)[RM][RM], const uint32_t (&p)[RM][RM], int I0, int J0, int tx,
                                int ty) const {
 #pragma unroll
         for (int ii = 0; ii < RM; ++ii)
@@ -71,22 +74,23 @@ struct GraphTiles {
                 const int i = I0 + ty + TS * ii, j = J0 + tx + TS * jj;
                 if (i < n && j < n) {
                     D[(int64_t)i * n + j] = d[ii][jj];
-                    if (PATH) P[(int64_t)i * n + j] = p[ii][jj];
+                    if (PATH) P[(int64_t)i * n + j] = (int32_t)p[ii][jj] - 1;
                 }
             }
     }
 };
 
-template <typename T>
-__device__ __forceinline__ void take(T &d, int32_t &p, T s, int32_t m, bool path) {
-    const bool t = path ? ((s < d) || (s == d && m < p)) : (s < d);
-    d = t ? s : d;
-    p = t ? m : p;
+template <typename T, bool PATH>
+__device__ __forceinline__ void take(T &d, uint32_t &p, T s, uint32_t m) {
+    if (PATH)
+        lex_take_u(d, p, s, m);
+    else
+        d = s < d ? s : d;
 }
 
 // One graph, whole method, by the calling workgroup.
 template <typename T, int TB, bool PATH>
-__device__ void solve_graph(GraphTiles<T, TB, PATH> g, T *sa, T *sb, int32_t *spa, int32_t *spb) {
+__device__ void solve_graph(GraphTiles<T, TB, PATH> g, T *sa, T *sb, uint32_t *spa, uint32_t *spb) {
     using G = GraphTiles<T, TB, PATH>;
     constexpr int TS = G::TS, RM = G::RM, ST = G::ST;
     const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
@@ -97,7 +101,7 @@ __device__ void solve_graph(GraphTiles<T, TB, PATH> g, T *sa, T *sb, int32_t *sp
     __syncthreads();
     const int R = (n + TB - 1) / TB;
     T d[RM][RM];
-    int32_t p[RM][RM];
+    uint32_t p[RM][RM];
     for (int r = 0; r < R; ++r) {
         const int k0 = r * TB;
         // Phase 1: close the diagonal block in LDS.  Row k and column k do not
@@ -109,7 +113,7 @@ __device__ void solve_graph(GraphTiles<T, TB, PATH> g, T *sa, T *sb, int32_t *sp
         g.load_regs(d, p, k0, k0, tx, ty);
         for (int k = 0; k < TB; ++k) {
             T a[RM], b[RM];
-            int32_t pa[RM], pb[RM];
+            uint32_t pa[RM], pb[RM];
 #pragma unroll
             for (int ii = 0; ii < RM; ++ii) {
                 a[ii] = sa[(ty + TS * ii) * ST + k];
@@ -125,10 +129,10 @@ __device__ void solve_graph(GraphTiles<T, TB, PATH> g, T *sa, T *sb, int32_t *sp
 #pragma unroll
                 for (int jj = 0; jj < RM; ++jj) {
                     const T s = a[ii] + b[jj];
-                    const int32_t m = PATH ? max(max(pa[ii], pb[jj]), k0 + k) : 0;
+                    const uint32_t m = PATH ? max(max(pa[ii], pb[jj]), (uint32_t)(k0 + k + 1)) : 0u;
                     const T d0 = d[ii][jj];
-                    const int32_t p0 = p[ii][jj];
-                    take(d[ii][jj], p[ii][jj], s, m, PATH);
+                    const uint32_t p0 = p[ii][jj];
+                    take<T, PATH>(d[ii][jj], p[ii][jj], s, m);
                     if (d[ii][jj] != d0 || (PATH && p[ii][jj] != p0)) {
                         sa[(ty + TS * ii) * ST + tx + TS * jj] = d[ii][jj];
                         if (PATH) spa[(ty + TS * ii) * ST + tx + TS * jj] = p[ii][jj];
@@ -152,15 +156,15 @@ __device__ void solve_graph(GraphTiles<T, TB, PATH> g, T *sa, T *sb, int32_t *sp
             __syncthreads();
             const T *A = rowp ? sa : sb;
             const T *B = rowp ? sb : sa;
-            const int32_t *PA = rowp ? spa : spb;
-            const int32_t *PB = rowp ? spb : spa;
+            const uint32_t *PA = rowp ? spa : spb;
+            const uint32_t *PB = rowp ? spb : spa;
             for (int k = 0; k < TB; ++k) {
                 T a[RM], b[RM];
-                int32_t pa[RM], pb[RM];
+                uint32_t pa[RM], pb[RM];
 #pragma unroll
                 for (int ii = 0; ii < RM; ++ii) {
                     a[ii] = A[(ty + TS * ii) * ST + k];
-                    if (PATH) pa[ii] = max(PA[(ty + TS * ii) * ST + k], k0 + k);
+                    if (PATH) pa[ii] = max(PA[(ty + TS * ii) * ST + k], (uint32_t)(k0 + k + 1));
                 }
 #pragma unroll
                 for (int jj = 0; jj < RM; ++jj) {
@@ -171,7 +175,7 @@ __device__ void solve_graph(GraphTiles<T, TB, PATH> g, T *sa, T *sb, int32_t *sp
                 for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
                     for (int jj = 0; jj < RM; ++jj)
-                        take(d[ii][jj], p[ii][jj], a[ii] + b[jj], PATH ? max(pa[ii], pb[jj]) : 0, PATH);
+                        take<T, PATH>(d[ii][jj], p[ii][jj], a[ii] + b[jj], PATH ? max(pa[ii], pb[jj]) : 0u);
             }
             g.store_regs(d, p, I0, J0, tx, ty);
             __syncthreads();
@@ -188,11 +192,11 @@ __device__ void solve_graph(GraphTiles<T, TB, PATH> g, T *sa, T *sb, int32_t *sp
             __syncthreads();
             for (int k = 0; k < TB; ++k) {
                 T a[RM], b[RM];
-                int32_t pa[RM], pb[RM];
+                uint32_t pa[RM], pb[RM];
 #pragma unroll
                 for (int ii = 0; ii < RM; ++ii) {
                     a[ii] = sa[(ty + TS * ii) * ST + k];
-                    if (PATH) pa[ii] = max(spa[(ty + TS * ii) * ST + k], k0 + k);
+                    if (PATH) pa[ii] = max(spa[(ty + TS * ii) * ST + k], (uint32_t)(k0 + k + 1));
                 }
 #pragma unroll
                 for (int jj = 0; jj < RM; ++jj) {
@@ -203,7 +207,7 @@ __device__ void solve_graph(GraphTiles<T, TB, PATH> g, T *sa, T *sb, int32_t *sp
                 for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
                     for (int jj = 0; jj < RM; ++jj)
-                        take(d[ii][jj], p[ii][jj], a[ii] + b[jj], PATH ? max(pa[ii], pb[jj]) : 0, PATH);
+                        take<T, PATH>(d[ii][jj], p[ii][jj], a[ii] + b[jj], PATH ? max(pa[ii], pb[jj]) : 0u);
             }
             g.store_regs(d, p, I0, J0, tx, ty);
             __syncthreads();
@@ -223,8 +227,8 @@ __global__ void __launch_bounds__(NT) k_batched(T *__restrict__ dist, int32_t *_
     constexpr int ST = 64 + 1;
     __shared__ T sa[64 * ST];
     __shared__ T sb[64 * ST];
-    __shared__ int32_t spa[PATH ? 64 * ST : 1];
-    __shared__ int32_t spb[PATH ? 64 * ST : 1];
+    __shared__ uint32_t spa[PATH ? 64 * ST : 1];  // labels + 1
+    __shared__ uint32_t spb[PATH ? 64 * ST : 1];
     __shared__ int s_job;
     unsigned long long *counter = (unsigned long long *)jobs;
     for (;;) {

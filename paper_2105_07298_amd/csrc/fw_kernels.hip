@@ -31,6 +31,7 @@
 #include "fw_internal.h"
 #define FW_TILE_FN __host__ __device__ __forceinline__
 #include "fw_tiles.h"
+#include "fw_lex.h"
 
 #include <limits.h>
 
@@ -64,6 +65,7 @@ __device__ __forceinline__ void lex_take(T &d, int32_t &p, T s, int32_t m) {
     p = take ? m : p;
 }
 
+
 // ---------------------------------------------------------------------------
 // Phase 1: close the diagonal block.  The block and its P stay in LDS; thread
 // (ty, tx) owns rows ty + 16*ii and columns tx + 16*jj.  At step k, row k and
@@ -79,11 +81,11 @@ __global__ void __launch_bounds__(P1_TS *P1_TS) k_phase1(T *__restrict__ D, int3
                                                         uint16_t *__restrict__ L, int64_t ld, int r) {
     constexpr int TS = P1_TS, RM = TB / TS, ST = TB + 1;
     __shared__ T sd[TB * ST];
-    __shared__ int32_t sp[PATH ? TB * ST : 1];
+    __shared__ uint32_t sp[PATH ? TB * ST : 1];  // labels + 1
     const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
     const int64_t k0 = (int64_t)r * TB;
     T d[RM][RM];
-    int32_t p[RM][RM];
+    uint32_t p[RM][RM];
     bool changed[RM][RM];
 #pragma unroll
     for (int ii = 0; ii < RM; ++ii)
@@ -91,18 +93,18 @@ __global__ void __launch_bounds__(P1_TS *P1_TS) k_phase1(T *__restrict__ D, int3
         for (int jj = 0; jj < RM; ++jj) {
             const int row = ty + TS * ii, col = tx + TS * jj;
             const int64_t g = (k0 + row) * ld + k0 + col;
-            d[ii][jj] = D[g];
+            d[ii][jj] = PATH ? canon(D[g]) : D[g];
             sd[row * ST + col] = d[ii][jj];
             changed[ii][jj] = false;
             if (PATH) {
-                p[ii][jj] = P[g];
+                p[ii][jj] = (uint32_t)(P[g] + 1);
                 sp[row * ST + col] = p[ii][jj];
             }
         }
     __syncthreads();
     for (int k = 0; k < TB; ++k) {
         T a[RM], b[RM];
-        int32_t pa[RM], pb[RM];
+        uint32_t pa[RM], pb[RM];
 #pragma unroll
         for (int ii = 0; ii < RM; ++ii) {
             a[ii] = sd[(ty + TS * ii) * ST + k];
@@ -113,7 +115,7 @@ __global__ void __launch_bounds__(P1_TS *P1_TS) k_phase1(T *__restrict__ D, int3
             b[jj] = sd[k * ST + tx + TS * jj];
             if (PATH) pb[jj] = sp[k * ST + tx + TS * jj];
         }
-        const int32_t kg = (int32_t)(k0 + k);
+        const uint32_t kg1 = (uint32_t)(k0 + k + 1);
 #pragma unroll
         for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
@@ -121,12 +123,12 @@ __global__ void __launch_bounds__(P1_TS *P1_TS) k_phase1(T *__restrict__ D, int3
                 const T s = a[ii] + b[jj];
                 const int idx = (ty + TS * ii) * ST + tx + TS * jj;
                 if (PATH) {
-                    const int32_t m = max(max(pa[ii], pb[jj]), kg);
-                    if ((s < d[ii][jj]) || (s == d[ii][jj] && m < p[ii][jj])) {
-                        d[ii][jj] = s;
-                        p[ii][jj] = m;
-                        sd[idx] = s;
-                        sp[idx] = m;
+                    const T d0 = d[ii][jj];
+                    const uint32_t p0 = p[ii][jj];
+                    lex_take_u(d[ii][jj], p[ii][jj], s, max(max(pa[ii], pb[jj]), kg1));
+                    if (p[ii][jj] != p0 || d[ii][jj] != d0) {
+                        sd[idx] = d[ii][jj];
+                        sp[idx] = p[ii][jj];
                         changed[ii][jj] = true;
                     }
                 } else if (s < d[ii][jj]) {
@@ -145,7 +147,7 @@ __global__ void __launch_bounds__(P1_TS *P1_TS) k_phase1(T *__restrict__ D, int3
             const int64_t g = (k0 + ty + TS * ii) * ld + k0 + tx + TS * jj;
             D[g] = d[ii][jj];
             if (PATH) {
-                P[g] = p[ii][jj];
+                P[g] = (int32_t)p[ii][jj] - 1;
                 L[g] = 0;
             }
         }
@@ -168,8 +170,8 @@ __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__re
     constexpr int TS = 16, RM = TB / TS, ST = TB + 1;
     __shared__ T sa[TB * ST];
     __shared__ T sb[TB * ST];
-    __shared__ int32_t spa[PATH ? TB * ST : 1];
-    __shared__ int32_t spb[PATH ? TB * ST : 1];
+    __shared__ uint32_t spa[PATH ? TB * ST : 1];  // labels + 1
+    __shared__ uint32_t spb[PATH ? TB * ST : 1];
     const int w = blockIdx.x;
     const bool rowp = w < nb - 1;
     const int t = rowp ? w : w - (nb - 1);
@@ -181,28 +183,28 @@ __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__re
         const int rr = q / TB, cc = q % TB;
         const int64_t ga = (I0 + rr) * ld + k0 + cc;  // A = D[I0.., K]
         const int64_t gb = (k0 + rr) * ld + J0 + cc;  // B = D[K, J0..]
-        sa[rr * ST + cc] = D[ga];
-        sb[rr * ST + cc] = D[gb];
+        sa[rr * ST + cc] = PATH ? canon(D[ga]) : D[ga];
+        sb[rr * ST + cc] = PATH ? canon(D[gb]) : D[gb];
         if (PATH) {
-            spa[rr * ST + cc] = P[ga];
-            spb[rr * ST + cc] = P[gb];
+            spa[rr * ST + cc] = (uint32_t)(P[ga] + 1);
+            spb[rr * ST + cc] = (uint32_t)(P[gb] + 1);
         }
     }
     const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
     T d[RM][RM], d0[RM][RM];
-    int32_t p[RM][RM], p0[RM][RM];
+    uint32_t p[RM][RM], p0[RM][RM];
 #pragma unroll
     for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
         for (int jj = 0; jj < RM; ++jj) {
             const int64_t g = (I0 + ty + TS * ii) * ld + J0 + tx + TS * jj;
-            d[ii][jj] = d0[ii][jj] = D[g];
-            if (PATH) p[ii][jj] = p0[ii][jj] = P[g];
+            d[ii][jj] = d0[ii][jj] = PATH ? canon(D[g]) : D[g];
+            if (PATH) p[ii][jj] = p0[ii][jj] = (uint32_t)(P[g] + 1);
         }
     __syncthreads();
     for (int k = 0; k < TB; ++k) {
         T a[RM], b[RM];
-        int32_t pa[RM], pb[RM];
+        uint32_t pa[RM], pb[RM];
 #pragma unroll
         for (int ii = 0; ii < RM; ++ii) {
             a[ii] = sa[(ty + TS * ii) * ST + k];
@@ -213,14 +215,14 @@ __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__re
             b[jj] = sb[k * ST + tx + TS * jj];
             if (PATH) pb[jj] = spb[k * ST + tx + TS * jj];
         }
-        const int32_t kg = (int32_t)(k0 + k);
+        const uint32_t kg1 = (uint32_t)(k0 + k + 1);
 #pragma unroll
         for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
             for (int jj = 0; jj < RM; ++jj) {
                 const T s = a[ii] + b[jj];
                 if (PATH)
-                    lex_take(d[ii][jj], p[ii][jj], s, max(max(pa[ii], pb[jj]), kg));
+                    lex_take_u(d[ii][jj], p[ii][jj], s, max(max(pa[ii], pb[jj]), kg1));
                 else
                     d[ii][jj] = vmin(d[ii][jj], s);
             }
@@ -233,7 +235,7 @@ __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__re
             const int64_t g = (I0 + ty + TS * ii) * ld + J0 + tx + TS * jj;
             D[g] = d[ii][jj];
             if (PATH) {
-                P[g] = p[ii][jj];
+                P[g] = (int32_t)p[ii][jj] - 1;
                 L[g] = 0;
             }
         }

@@ -1,0 +1,37 @@
+// fw_lex.h -- the lexicographic (length, label) update in its fast form, shared
+// by the device kernels that carry the path matrix (paper Sect. 2.1: a shorter
+// candidate through k replaces the entry and its intermediate vertex; equal
+// lengths are broken towards the smaller largest-interior-vertex label, which
+// makes the labels independent of the order of the k steps).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fw {
+
+// The same rule on labels kept offset by one (label + 1: "no interior vertex"
+// is 0, and labels compare as unsigned numbers).  For float the pair is one
+// 64-bit unsigned key, length bits above label: non-negative floats (+0 to
+// +inf) order like their bit patterns, so one compare and two selects replace
+// the three compares and two mask operations of the two-key test.  Lengths
+// must not be -0.0 (see canon()).
+__device__ __forceinline__ void lex_take_u(float &d, uint32_t &p, float s, uint32_t m) {
+    const uint64_t ks = ((uint64_t)__float_as_uint(s) << 32) | m;
+    const uint64_t kd = ((uint64_t)__float_as_uint(d) << 32) | p;
+    const bool take = ks < kd;
+    d = take ? s : d;
+    p = take ? m : p;
+}
+__device__ __forceinline__ void lex_take_u(double &d, uint32_t &p, double s, uint32_t m) {
+    const bool take = (s < d) || (s == d && m < p);
+    d = take ? s : d;
+    p = take ? m : p;
+}
+// A length as read from memory, with -0.0 turned into +0.0 (equal as numbers,
+// but its bit pattern would sort above +inf in lex_take_u's key).
+template <typename T>
+__device__ __forceinline__ T canon(T x) {
+    return x + (T)0;
+}
+
+}  // namespace fw
