@@ -40,9 +40,12 @@ METRIC = "APSP GFLOPS=2n³/t at n=16384 FP32/FP64; batched graphs/s; fwd+bwd vs 
 # v_min3_f32, v_add_f64 and v_min_f64.  float32 spends one v_add_f32 and half a
 # v_min3_f32 per update (1/32 + 0.5/16 = 1/16 SIMD-clk per lane-update), float64
 # one v_add_f64 and one v_min_f64 (1/8).  Hence 64 (float32) and 32 (float64)
-# updates per CU per clock.
+# updates per CU per clock.  binary16 (FW_F16) updates two entries per packed
+# instruction: two v_pk_add_f16 and one v_pk_minimum3_f16 (16 lanes/clk each)
+# per 4 updates, 3/64 SIMD-clk per lane-update, 85.3 updates per CU per clock.
 CU_CLK = 256 * 2.4e9
-PEAK_TFLOPS = {"f32": CU_CLK * 64 * 2 / 1e12, "f64": CU_CLK * 32 * 2 / 1e12}
+PEAK_TFLOPS = {"f32": CU_CLK * 64 * 2 / 1e12, "f64": CU_CLK * 32 * 2 / 1e12, "f16": CU_CLK * 256 / 3 * 2 / 1e12}
+DT_CODE = {"f32": 0, "f64": 1, "f16": 2}
 KERNEL_SRC = os.path.join(ROOT, "paper_2105_07298_amd", "csrc", "fw_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
@@ -141,9 +144,12 @@ def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False, config=None,
     config: (block, tile_m, tile_n, variant, schedule), default the tuned choice."""
     import numpy as np
     import workloads
-    npdt = np.float32 if dtype == "f32" else np.float64
-    block, tm, tn, var, sch = config or fw.fw_query_config(fw.FW_F32 if dtype == "f32" else fw.FW_F64, n, path)
-    Wd = torch.from_numpy(workloads.unit_complete(n, dtype=npdt, seed=2)).cuda()
+    block, tm, tn, var, sch = config or fw.fw_query_config(DT_CODE[dtype], n, path)
+    if dtype == "f16":  # integer weights in [1, 1000]: every distance is exact in binary16
+        Wd = torch.from_numpy(workloads.int_graph(n, 1.0, 1000, seed=2).astype(np.float16)).cuda()
+    else:
+        npdt = np.float32 if dtype == "f32" else np.float64
+        Wd = torch.from_numpy(workloads.unit_complete(n, dtype=npdt, seed=2)).cuda()
     D = torch.empty_like(Wd)
     P = torch.empty((n, n), dtype=torch.int32, device=Wd.device) if path else None
 
@@ -275,7 +281,7 @@ def time_fwd_bwd(fw, torch, steps=5, warmup=2):
     return {"n2048": single, "batch256_n128": batch}
 
 
-def roofline(n, dtype, stats):
+def roofline(n, dtype, stats, path=True):
     block = stats["block"]
     upd = stats["updates_per_launch"]  # algorithmic min-plus updates per timed last-phase launch
     achieved = 2.0 * upd / (stats["mean_ms"] / 1e3) / 1e12
@@ -284,7 +290,7 @@ def roofline(n, dtype, stats):
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
-        key = f"{dtype}_n{n}_path"
+        key = f"{dtype}_n{n}_{'path' if path else 'dist'}"
         if t.get("kernel_hash") == kernel_hash() and key in t:
             traffic = t[key]["bytes_per_launch"]
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TFLOP/s",
@@ -329,7 +335,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=16384)
-    ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--dtype", choices=["f32", "f64", "f16"], default="f32")
     ap.add_argument("--no-path", action="store_true", help="distances only (P = NULL)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-energy", action="store_true", help="skip the amdsmi energy reading")
@@ -363,12 +369,13 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
         "data": "synthetic",
-        "config": {"workload": f"complete directed graph n={args.n}, weights uniform real in (0,1), "
-                               f"{'float32' if args.dtype == 'f32' else 'float64'}, "
-                               f"{'distances + path matrix' if path else 'distances only'}",
+        "config": {"workload": f"complete directed graph n={args.n}, "
+                               + ("integer weights in [1, 1000], binary16, " if args.dtype == "f16" else
+                                  f"weights uniform real in (0,1), {'float32' if args.dtype == 'f32' else 'float64'}, ")
+                               + ("distances + path matrix" if path else "distances only"),
                    "n": args.n, "path": path, "block": stats["block"], "tile": stats["tile"],
                    "parallelism": "single GPU"},
-        "roofline": roofline(args.n, args.dtype, stats),
+        "roofline": roofline(args.n, args.dtype, stats, path),
         "energy": meter.result if meter is not None else None,
     }
     if args.calib_copy_mib:
@@ -382,14 +389,16 @@ def main():
         out["calib_copy_bytes"] = nb
     if not args.no_secondary:
         sec_out = {}
-        for dt_, pth in (("f64", True), ("f32", False), ("f64", False)):
+        for dt_, pth in (("f64", True), ("f32", False), ("f64", False), ("f16", True), ("f16", False)):
             if dt_ == args.dtype and pth == path:
                 continue
             print(f"[bench] secondary n={args.n} {dt_} path={pth}", file=sys.stderr, flush=True)
             s, st = time_apsp(fw, torch, args.n, dt_, pth, 2, 1, prof=True)
             key = f"{dt_}_{'path' if pth else 'dist'}"
             sec_out[key] = {"gflops": round(gflops(args.n, s), 2), "ms_per_step": round(s * 1e3, 2),
-                            "roofline_frac": roofline(args.n, dt_, st)["frac"]}
+                            "roofline_frac": roofline(args.n, dt_, st, pth)["frac"]}
+            if dt_ == "f16":
+                sec_out[key]["workload"] = "complete graph, integer weights in [1, 1000] (exact in binary16)"
         print("[bench] secondary out of core n=32768", file=sys.stderr, flush=True)
         sec_out["ooc_f32_dist"] = time_ooc(fw, torch)
         print("[bench] secondary out of core n=16384 with the path matrix", file=sys.stderr, flush=True)

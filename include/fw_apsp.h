@@ -38,7 +38,16 @@
 extern "C" {
 #endif
 
-typedef enum { FW_F32 = 0, FW_F64 = 1 } fw_dtype_t;
+/* Element type of the distance matrix.  FW_F16 (IEEE binary16, _Float16) is the
+ * half-width variant for small integer weights: the last phase updates two
+ * entries per packed instruction.  Binary16 holds every integer up to 2048
+ * exactly, so when weights are integers (or multiples of one power of two, in
+ * units where they are integers) and every finite shortest distance is below
+ * 2048 units, D and P equal those of the exact computation; larger lengths are
+ * rounded and may change which candidates tie.  FW_F16 is accepted by fw_apsp,
+ * fw_apsp_config, fw_query_config and fw_list_configs only (FW_EINVAL
+ * elsewhere). */
+typedef enum { FW_F32 = 0, FW_F64 = 1, FW_F16 = 2 } fw_dtype_t;
 
 typedef enum {
     FW_OK = 0,
@@ -51,7 +60,8 @@ typedef enum {
 /*
  * All-pairs shortest paths of one graph, in place (paper Sect. 2.2, Algorithm 1
  * and the blocked method).
- *   dt    FW_F32 (float) or FW_F64 (double): element type of dist.
+ *   dt    FW_F32 (float), FW_F64 (double) or FW_F16 (_Float16): element type
+ *         of dist.
  *   n     vertex count, 1 <= n <= 2^20.
  *   dist  device, n*n elements: W on entry, shortest distances on exit.
  *   path  device, n*n int32: receives P; NULL computes distances only.
@@ -67,7 +77,8 @@ fw_status_t fw_apsp(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, void *s
  *   block    round depth (the paper's TB), 32 or 64.
  *   variant  the last-phase kernel:
  *            FW_P4_PANELS    both operand panels staged in LDS; tile_m and
- *                            tile_n each 64 or 128 and a multiple of block.
+ *                            tile_n each 64 or 128 and a multiple of block
+ *                            (FW_F16: tile_n 128 or 256, tile_m 32 to 128).
  *            FW_P4_WAVEROWS  each wave of 4 takes tile_m / 4 rows of the tile
  *                            and reads their column-panel values with scalar
  *                            loads; only the row panel is staged in LDS.
@@ -83,7 +94,7 @@ fw_status_t fw_apsp(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, void *s
  *            the caller's stream, which waits for them before round r + 1.
  *            The call stays stream-ordered on the caller's stream.
  *            FW_SCHED_PAIRS (LDS-panel tiles exactly one block square; otherwise
- *            serial): rounds in pairs on the caller's stream; the last phase of
+ *            serial, which includes every FW_F16 configuration): rounds in pairs on the caller's stream; the last phase of
  *            both rounds of a pair is applied to every tile outside their two
  *            blocks in one pass, so those tiles move through memory once per
  *            two rounds.

@@ -8,7 +8,7 @@ PyTorch provides device memory and streams only; no step of the method runs in i
 """
 from __future__ import annotations
 
-from ._lib import (FW_EHIP, FW_EINVAL, FW_ENOMEM, FW_EUNSUPPORTED, FW_F32, FW_F64, FW_OK,  # noqa: F401
+from ._lib import (FW_EHIP, FW_EINVAL, FW_ENOMEM, FW_EUNSUPPORTED, FW_F16, FW_F32, FW_F64, FW_OK,  # noqa: F401
                    FW_P4_PANELS, FW_P4_WAVEROWS, FW_SCHED_LOOKAHEAD, FW_SCHED_PAIRS, FW_SCHED_SERIAL, FwError, fw_apsp, fw_apsp_backward, fw_apsp_batched,
                    fw_apsp_batched_config, fw_apsp_config, fw_apsp_ooc, fw_last_error, fw_list_configs, fw_ooc_superblock,
                    fw_prof_enable,
@@ -22,7 +22,9 @@ def _dtype_code(t):
         return FW_F32
     if t.dtype == torch.float64:
         return FW_F64
-    raise TypeError(f"unsupported dtype {t.dtype} (float32 or float64)")
+    if t.dtype == torch.float16:
+        return FW_F16
+    raise TypeError(f"unsupported dtype {t.dtype} (float32, float64 or float16)")
 
 
 def _stream_ptr(device):
@@ -31,7 +33,10 @@ def _stream_ptr(device):
 
 
 def apsp_(D, P=None, block: int = 0, tile_m: int = 0, tile_n: int = 0, variant: int = 0, schedule: int = 0):
-    """In-place APSP of the square device tensor D (float32/float64, contiguous).
+    """In-place APSP of the square device tensor D (float32/float64/float16, contiguous).
+
+    float16 is the half-width variant: exact for integer weights when every finite
+    shortest distance is below 2048.
 
     D holds the weight matrix (0 diagonal, +inf = no edge) and is overwritten with
     shortest distances; P (int32, same shape) receives the path matrix if given.

@@ -11,7 +11,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfwapsp.so")
 
-FW_F32, FW_F64 = 0, 1
+FW_F32, FW_F64, FW_F16 = 0, 1, 2
 FW_OK, FW_EINVAL, FW_ENOMEM, FW_EHIP, FW_EUNSUPPORTED = 0, -1, -2, -3, -4
 FW_P4_PANELS, FW_P4_WAVEROWS = 1, 2
 FW_SCHED_SERIAL, FW_SCHED_LOOKAHEAD, FW_SCHED_PAIRS = 1, 2, 3

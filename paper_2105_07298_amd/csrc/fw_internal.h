@@ -84,7 +84,7 @@ int batched_occupancy(bool path);
 
 // Tuning table lookup (tune_table.inc): tile configuration for fw_apsp and the
 // small-graph split of fw_apsp_batched.
-TileCfg tuned_config(bool f64, bool path, int64_t n);
+TileCfg tuned_config(int dtype, bool path, int64_t n);  // dtype: an fw_dtype_t code
 int tuned_batched_small_max_n(bool f64, bool path);
 
 // Gradient dL/dW (zeroed here) from (D, P) and G = dL/dD for batch graphs of n

@@ -10,6 +10,9 @@
 //              column panel D[I, K] and row panel D[K, J], both staged in LDS;
 //   k_phase4w  the same product with one row of the column panel per wave and
 //              k, read into scalar registers, and only the row panel in LDS.
+// Every kernel is written for float32 and float64; phases 1-3, k_phase4 and the
+// label resolution also exist for binary16 (_Float16), where k_phase4 works on
+// pairs of columns with packed half-precision instructions.
 //
 // Path matrix: every candidate through k carries the label
 // (length, max(P[i][k], k, P[k][j])); an entry takes a candidate whose label is
@@ -34,6 +37,7 @@
 #include "fw_lex.h"
 
 #include <limits.h>
+#include <type_traits>
 
 namespace fw {
 namespace {
@@ -49,13 +53,21 @@ template <> struct V16<double> {
     typedef double type __attribute__((ext_vector_type(2)));
     static constexpr int n = 2;
 };
+template <> struct V16<_Float16> {
+    typedef _Float16 type __attribute__((ext_vector_type(8)));
+    static constexpr int n = 8;
+};
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+template <typename T> constexpr bool is_half_v = std::is_same_v<T, _Float16>;
 
 template <typename T> __device__ __forceinline__ T inf_v();
 template <> __device__ __forceinline__ float inf_v<float>() { return __builtin_inff(); }
 template <> __device__ __forceinline__ double inf_v<double>() { return __builtin_inf(); }
+template <> __device__ __forceinline__ _Float16 inf_v<_Float16>() { return (_Float16)__builtin_inff(); }
 
 __device__ __forceinline__ float vmin(float a, float b) { return __builtin_fminf(a, b); }
 __device__ __forceinline__ double vmin(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ _Float16 vmin(_Float16 a, _Float16 b) { return __builtin_elementwise_min(a, b); }
 
 // Lexicographic label update: take (s, m) when it is smaller than (d, p).
 template <typename T>
@@ -330,13 +342,20 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
         }
     };
 
-    // acc <- min over the staged block of A[i][k] + B[k][j].
-    T acc[RM][RN];
+    // acc <- min over the staged block of A[i][k] + B[k][j].  binary16 keeps
+    // two adjacent columns per register (AW = 2): per pair of k, two packed
+    // adds (the A value reaches both halves through the operand-select bits)
+    // and one packed three-way minimum update two entries for two k each.  The
+    // IEEE minimum (v_pk_minimum3_f16) differs from min only for NaN and the
+    // order of -0 and +0, neither of which occurs in lengths >= +0.
+    constexpr int AW = is_half_v<T> ? 2 : 1;
+    using AccV = std::conditional_t<is_half_v<T>, half2_t, T>;
+    AccV acc[RM][RN / AW];
     auto sweep = [&]() {
 #pragma unroll
         for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
-            for (int jj = 0; jj < RN; ++jj) acc[ii][jj] = inf_v<T>();
+            for (int jj = 0; jj < RN / AW; ++jj) acc[ii][jj] = inf_v<T>();
 #pragma unroll 2
         for (int kv = 0; kv < TB / V; ++kv) {
             vec a[RM];
@@ -353,14 +372,32 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
 #pragma unroll
                 for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
-                    for (int h = 0; h < HN; ++h)
+                    for (int h = 0; h < HN; ++h) {
+                        if constexpr (is_half_v<T>) {
+                            const half2_t a0 = {a[ii][kk], a[ii][kk]}, a1 = {a[ii][kk + 1], a[ii][kk + 1]};
 #pragma unroll
-                        for (int e = 0; e < V; ++e) {
-                            T &x = acc[ii][h * V + e];
-                            x = vmin(vmin(x, a[ii][kk] + b0[h][e]), a[ii][kk + 1] + b1[h][e]);
+                            for (int e = 0; e < V; e += 2) {
+                                half2_t &x = acc[ii][(h * V + e) / 2];
+                                const half2_t s0 = a0 + half2_t{b0[h][e], b0[h][e + 1]};
+                                const half2_t s1 = a1 + half2_t{b1[h][e], b1[h][e + 1]};
+                                x = __builtin_elementwise_minimum(__builtin_elementwise_minimum(x, s0), s1);
+                            }
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < V; ++e) {
+                                T &x = acc[ii][h * V + e];
+                                x = vmin(vmin(x, a[ii][kk] + b0[h][e]), a[ii][kk + 1] + b1[h][e]);
+                            }
                         }
+                    }
             }
         }
+    };
+    auto acc_at = [&](const AccV (&src)[RM][RN / AW], int ii, int jj) -> T {
+        if constexpr (is_half_v<T>)
+            return src[ii][jj / 2][jj % 2];
+        else
+            return src[ii][jj];
     };
 
     stage(k0);
@@ -368,12 +405,12 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
     sweep();
     // A fused pair (rounds r and r + 1, tiles outside both blocks): keep round
     // r's minimum, then sweep round r + 1's panels, which are final by now.
-    T acc0[FUSE ? RM : 1][FUSE ? RN : 1];
+    AccV acc0[RM][RN / AW];
     if constexpr (FUSE) {
 #pragma unroll
         for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
-            for (int jj = 0; jj < RN; ++jj) acc0[ii][jj] = acc[ii][jj];
+            for (int jj = 0; jj < RN / AW; ++jj) acc0[ii][jj] = acc[ii][jj];
         __syncthreads();  // every thread is done with round r's panels
         stage(k0 + TB);
         __syncthreads();
@@ -403,9 +440,9 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
             bool ch = false;
 #pragma unroll
             for (int e = 0; e < V; ++e) {
-                const T s = acc[ii][h * V + e];
+                const T s = acc_at(acc, ii, h * V + e);
                 if constexpr (FUSE) {
-                    const T s0 = acc0[ii][h * V + e];
+                    const T s0 = acc_at(acc0, ii, h * V + e);
                     const bool lt0 = s0 < nv[e];
                     const T c1 = lt0 ? s0 : nv[e];
                     const bool lt1 = s < c1;
@@ -922,23 +959,41 @@ hipError_t p4_impl(T *D, uint16_t *L, bool path, int64_t ld, int r, P4Mode mode,
     X(32, 16, 256) X(32, 32, 128) X(32, 32, 256) X(64, 16, 256) X(64, 32, 128) X(64, 32, 256) X(64, 64, 128) \
     X(64, 64, 256)
 #define FW_P4W_CONFIGS_F64(X) X(32, 16, 128) X(32, 32, 64) X(32, 32, 128) X(64, 32, 64) X(64, 32, 128) X(64, 64, 128)
+// binary16: LDS-panel last phase only; a 16-byte vector holds 8 columns, so
+// tiles are at least 128 wide (8 columns per thread, 16 threads across).
+#define FW_P4_CONFIGS_F16(X) X(32, 64, 128) X(32, 128, 128) X(64, 32, 128) X(64, 64, 128) X(64, 128, 128) X(64, 64, 256)
+#define FW_P4W_CONFIGS_F16(X)
+
+// FW_FOR_DTYPE(T, PANELS, WAVE, X): expand X over the panel (PANELS true) or
+// wave-row configurations compiled for element type T.
+#define FW_FOR_DTYPE(T, PANELS, X)                       \
+    do {                                                 \
+        if constexpr (std::is_same_v<T, float>) {        \
+            if constexpr (PANELS) {                      \
+                FW_P4_CONFIGS_F32(X)                     \
+            } else {                                     \
+                FW_P4W_CONFIGS_F32(X)                    \
+            }                                            \
+        } else if constexpr (std::is_same_v<T, double>) { \
+            if constexpr (PANELS) {                      \
+                FW_P4_CONFIGS_F64(X)                     \
+            } else {                                     \
+                FW_P4W_CONFIGS_F64(X)                    \
+            }                                            \
+        } else {                                         \
+            if constexpr (PANELS) {                      \
+                FW_P4_CONFIGS_F16(X)                     \
+            } else {                                     \
+                FW_P4W_CONFIGS_F16(X)                    \
+            }                                            \
+        }                                                \
+    } while (0)
 
 template <typename T>
 bool config_supported(TileCfg c) {
 #define FW_MATCH(B, M, N) if (c.block == B && c.tile_m == M && c.tile_n == N) return true;
-    if (c.variant == FW_VARIANT_PANELS) {
-        if (sizeof(T) == 4) {
-            FW_P4_CONFIGS_F32(FW_MATCH)
-        } else {
-            FW_P4_CONFIGS_F64(FW_MATCH)
-        }
-    } else if (c.variant == FW_VARIANT_WAVEROWS) {
-        if (sizeof(T) == 4) {
-            FW_P4W_CONFIGS_F32(FW_MATCH)
-        } else {
-            FW_P4W_CONFIGS_F64(FW_MATCH)
-        }
-    }
+    if (c.variant == FW_VARIANT_PANELS) FW_FOR_DTYPE(T, true, FW_MATCH);
+    else if (c.variant == FW_VARIANT_WAVEROWS) FW_FOR_DTYPE(T, false, FW_MATCH);
 #undef FW_MATCH
     return false;
 }
@@ -953,13 +1008,8 @@ int list_configs(TileCfg *out, int cap) {
     }
 #define FW_PUT_P(B, M, N) FW_PUT(B, M, N, FW_VARIANT_PANELS)
 #define FW_PUT_W(B, M, N) FW_PUT(B, M, N, FW_VARIANT_WAVEROWS)
-    if constexpr (sizeof(T) == 4) {
-        FW_P4_CONFIGS_F32(FW_PUT_P)
-        FW_P4W_CONFIGS_F32(FW_PUT_W)
-    } else {
-        FW_P4_CONFIGS_F64(FW_PUT_P)
-        FW_P4W_CONFIGS_F64(FW_PUT_W)
-    }
+    FW_FOR_DTYPE(T, true, FW_PUT_P);
+    FW_FOR_DTYPE(T, false, FW_PUT_W);
 #undef FW_PUT
 #undef FW_PUT_P
 #undef FW_PUT_W
@@ -983,19 +1033,8 @@ hipError_t launch_phase4(T *D, uint16_t *L, bool path, int64_t ld, int r, TileCf
     if (c.block == B && c.tile_m == M && c.tile_n == N) return p4_impl<T, B, M, N, false>(D, L, path, ld, r, mode, s);
 #define FW_DISPATCH_W(B, M, N) \
     if (c.block == B && c.tile_m == M && c.tile_n == N) return p4_impl<T, B, M, N, true>(D, L, path, ld, r, mode, s);
-    if (c.variant == FW_VARIANT_PANELS) {
-        if constexpr (sizeof(T) == 4) {
-            FW_P4_CONFIGS_F32(FW_DISPATCH)
-        } else {
-            FW_P4_CONFIGS_F64(FW_DISPATCH)
-        }
-    } else if (c.variant == FW_VARIANT_WAVEROWS) {
-        if constexpr (sizeof(T) == 4) {
-            FW_P4W_CONFIGS_F32(FW_DISPATCH_W)
-        } else {
-            FW_P4W_CONFIGS_F64(FW_DISPATCH_W)
-        }
-    }
+    if (c.variant == FW_VARIANT_PANELS) FW_FOR_DTYPE(T, true, FW_DISPATCH);
+    else if (c.variant == FW_VARIANT_WAVEROWS) FW_FOR_DTYPE(T, false, FW_DISPATCH_W);
 #undef FW_DISPATCH
 #undef FW_DISPATCH_W
     return hipErrorInvalidValue;
@@ -1101,5 +1140,13 @@ template hipError_t launch_pad_in<double>(const double *, int64_t, double *, int
 template hipError_t launch_pad_out<float>(const float *, int64_t, float *, int64_t, hipStream_t);
 template hipError_t launch_pad_out<double>(const double *, int64_t, double *, int64_t, hipStream_t);
 template hipError_t launch_pad_out<int32_t>(const int32_t *, int64_t, int32_t *, int64_t, hipStream_t);
+template bool config_supported<_Float16>(TileCfg);
+template int list_configs<_Float16>(TileCfg *, int);
+template hipError_t launch_phase123<_Float16>(_Float16 *, int32_t *, uint16_t *, int64_t, int, int, hipStream_t);
+template hipError_t launch_phase4<_Float16>(_Float16 *, uint16_t *, bool, int64_t, int, TileCfg, P4Mode, hipStream_t);
+template hipError_t launch_resolve<_Float16>(const _Float16 *, _Float16 *, const uint16_t *, int32_t *, int64_t, int,
+                                             hipStream_t);
+template hipError_t launch_pad_in<_Float16>(const _Float16 *, int64_t, _Float16 *, int64_t, hipStream_t);
+template hipError_t launch_pad_out<_Float16>(const _Float16 *, int64_t, _Float16 *, int64_t, hipStream_t);
 
 }  // namespace fw

@@ -13,11 +13,19 @@ namespace fw {
 // is 0, and labels compare as unsigned numbers).  For float the pair is one
 // 64-bit unsigned key, length bits above label: non-negative floats (+0 to
 // +inf) order like their bit patterns, so one compare and two selects replace
-// the three compares and two mask operations of the two-key test.  Lengths
-// must not be -0.0 (see canon()).
+// the three compares and two mask operations of the two-key test (binary16
+// likewise, its 16 bits above the label).  Lengths must not be -0.0 (see
+// canon()).
 __device__ __forceinline__ void lex_take_u(float &d, uint32_t &p, float s, uint32_t m) {
     const uint64_t ks = ((uint64_t)__float_as_uint(s) << 32) | m;
     const uint64_t kd = ((uint64_t)__float_as_uint(d) << 32) | p;
+    const bool take = ks < kd;
+    d = take ? s : d;
+    p = take ? m : p;
+}
+__device__ __forceinline__ void lex_take_u(_Float16 &d, uint32_t &p, _Float16 s, uint32_t m) {
+    const uint64_t ks = ((uint64_t)__builtin_bit_cast(uint16_t, s) << 32) | m;
+    const uint64_t kd = ((uint64_t)__builtin_bit_cast(uint16_t, d) << 32) | p;
     const bool take = ks < kd;
     d = take ? s : d;
     p = take ? m : p;

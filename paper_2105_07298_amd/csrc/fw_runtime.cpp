@@ -71,11 +71,16 @@ void *g_stage = nullptr;
 size_t g_stage_cap = 0;
 hipEvent_t g_stage_ev = nullptr;
 
-struct TuneEntry { int f64, path; long long n_lo, n_hi; int block, tile_m, tile_n, variant, schedule; };
-struct TuneBatchedEntry { int f64, path, small_max_n; };
+struct TuneEntry { int dtype, path; long long n_lo, n_hi; int block, tile_m, tile_n, variant, schedule; };
+struct TuneBatchedEntry { int dtype, path, small_max_n; };
 #include "tune_table.inc"
 
-fw::TileCfg default_cfg(fw_dtype_t dt, int64_t n, bool path) { return fw::tuned_config(dt == FW_F64, path, n); }
+fw::TileCfg default_cfg(fw_dtype_t dt, int64_t n, bool path) { return fw::tuned_config((int)dt, path, n); }
+
+bool supported_for(fw_dtype_t dt, fw::TileCfg c) {
+    return dt == FW_F32 ? fw::config_supported<float>(c)
+                        : dt == FW_F64 ? fw::config_supported<double>(c) : fw::config_supported<_Float16>(c);
+}
 
 // ---- lookahead ---------------------------------------------------------------
 // Phases 1-3 of round r + 1 only read and write block row and column r + 1.  The
@@ -237,8 +242,17 @@ fw_status_t run_apsp(int64_t n, T *dist, int32_t *path, fw::TileCfg cfg, hipStre
     return FW_OK;
 }
 
-fw_status_t check_common(fw_dtype_t dt, int64_t n, const void *dist) {
-    if (dt != FW_F32 && dt != FW_F64) return fail(FW_EINVAL, "unknown dtype %d", (int)dt);
+// dt codes accepted by the single-graph entry points (and, when two_only, by
+// the ones that have no binary16 form).
+fw_status_t check_dtype(fw_dtype_t dt, bool two_only) {
+    if (dt == FW_F32 || dt == FW_F64) return FW_OK;
+    if (dt == FW_F16 && !two_only) return FW_OK;
+    if (dt == FW_F16) return fail(FW_EINVAL, "FW_F16 is supported by fw_apsp / fw_apsp_config only");
+    return fail(FW_EINVAL, "unknown dtype %d", (int)dt);
+}
+
+fw_status_t check_common(fw_dtype_t dt, int64_t n, const void *dist, bool two_only) {
+    if (fw_status_t st = check_dtype(dt, two_only); st != FW_OK) return st;
     if (n < 1 || n > kMaxN) return fail(FW_EINVAL, "n = %lld outside [1, %lld]", (long long)n, (long long)kMaxN);
     if (dist == nullptr) return fail(FW_EINVAL, "dist is NULL");
     return FW_OK;
@@ -247,15 +261,16 @@ fw_status_t check_common(fw_dtype_t dt, int64_t n, const void *dist) {
 }  // namespace
 
 namespace fw {
-TileCfg tuned_config(bool f64, bool path, int64_t n) {
+TileCfg tuned_config(int dtype, bool path, int64_t n) {
     for (const TuneEntry &t : kTuneApsp)
-        if (t.f64 == (int)f64 && t.path == (int)path && n >= t.n_lo && n < t.n_hi)
+        if (t.dtype == dtype && t.path == (int)path && n >= t.n_lo && n < t.n_hi)
             return {t.block, t.tile_m, t.tile_n, t.variant, t.schedule};
+    if (dtype == FW_F16) return {64, 64, 128, FW_VARIANT_PANELS, FW_SCHEDULE_SERIAL};
     return {64, 64, 64, FW_VARIANT_PANELS, FW_SCHEDULE_SERIAL};
 }
 int tuned_batched_small_max_n(bool f64, bool path) {
     for (const TuneBatchedEntry &t : kTuneBatched)
-        if (t.f64 == (int)f64 && t.path == (int)path) return t.small_max_n;
+        if (t.dtype == (f64 ? FW_F64 : FW_F32) && t.path == (int)path) return t.small_max_n;
     return 0;
 }
 
@@ -281,7 +296,7 @@ extern "C" {
 
 fw_status_t fw_apsp_config(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, const fw_config_t *cfg, void *stream) {
     g_err[0] = 0;
-    fw_status_t st = check_common(dt, n, dist);
+    fw_status_t st = check_common(dt, n, dist, false);
     if (st != FW_OK) return st;
     fw::TileCfg tc = default_cfg(dt, n, path != nullptr);
     if (cfg) {
@@ -295,7 +310,7 @@ fw_status_t fw_apsp_config(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, 
         if (cfg->variant) tc.variant = cfg->variant;
         if (cfg->schedule) tc.schedule = cfg->schedule;
     }
-    if (!(dt == FW_F32 ? fw::config_supported<float>(tc) : fw::config_supported<double>(tc)))
+    if (!supported_for(dt, tc))
         return fail(FW_EUNSUPPORTED, "block %d / tile %d x %d / variant %d not compiled in", tc.block, tc.tile_m,
                     tc.tile_n, tc.variant);
     int dev = -1;
@@ -303,12 +318,13 @@ fw_status_t fw_apsp_config(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, 
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     hipStream_t s = (hipStream_t)stream;
     if (dt == FW_F32) return run_apsp<float>(n, (float *)dist, path, tc, s);
+    if (dt == FW_F16) return run_apsp<_Float16>(n, (_Float16 *)dist, path, tc, s);
     return run_apsp<double>(n, (double *)dist, path, tc, s);
 }
 
 fw_status_t fw_query_config(fw_dtype_t dt, int64_t n, int32_t path, fw_config_t *out) {
     g_err[0] = 0;
-    if (dt != FW_F32 && dt != FW_F64) return fail(FW_EINVAL, "unknown dtype %d", (int)dt);
+    if (fw_status_t st = check_dtype(dt, false); st != FW_OK) return st;
     if (n < 1 || n > kMaxN) return fail(FW_EINVAL, "n = %lld outside [1, %lld]", (long long)n, (long long)kMaxN);
     if (!out) return fail(FW_EINVAL, "out is NULL");
     const fw::TileCfg c = default_cfg(dt, n, path != 0);
@@ -322,19 +338,21 @@ fw_status_t fw_query_config(fw_dtype_t dt, int64_t n, int32_t path, fw_config_t 
 
 int32_t fw_list_configs(fw_dtype_t dt, fw_config_t *out, int32_t cap) {
     g_err[0] = 0;
-    if (dt != FW_F32 && dt != FW_F64) return fail(FW_EINVAL, "unknown dtype %d", (int)dt);
+    if (fw_status_t st = check_dtype(dt, false); st != FW_OK) return st;
     if (cap < 0 || (cap > 0 && !out)) return fail(FW_EINVAL, "out must hold cap >= 0 entries");
-    std::vector<fw::TileCfg> all((size_t)(dt == FW_F32 ? fw::list_configs<float>(nullptr, 0)
-                                                       : fw::list_configs<double>(nullptr, 0)));
-    const int total = dt == FW_F32 ? fw::list_configs<float>(all.data(), (int)all.size())
-                                   : fw::list_configs<double>(all.data(), (int)all.size());
+    auto list = [dt](fw::TileCfg *o, int c) {
+        return dt == FW_F32 ? fw::list_configs<float>(o, c)
+                            : dt == FW_F64 ? fw::list_configs<double>(o, c) : fw::list_configs<_Float16>(o, c);
+    };
+    std::vector<fw::TileCfg> all((size_t)list(nullptr, 0));
+    const int total = list(all.data(), (int)all.size());
     for (int k = 0; k < total && k < cap; ++k) out[k] = {all[k].block, all[k].tile_m, all[k].tile_n, all[k].variant, 0};
     return total;
 }
 
 int64_t fw_ooc_superblock(fw_dtype_t dt, int64_t n, int32_t path, size_t device_bytes) {
     g_err[0] = 0;
-    if (dt != FW_F32 && dt != FW_F64) return fail(FW_EINVAL, "unknown dtype %d", (int)dt);
+    if (fw_status_t st = check_dtype(dt, true); st != FW_OK) return st;
     if (n < 1 || n > kMaxN) return fail(FW_EINVAL, "n = %lld outside [1, %lld]", (long long)n, (long long)kMaxN);
     if (device_bytes == 0) {
         size_t free_b = 0, total_b = 0;
@@ -353,7 +371,7 @@ int64_t fw_ooc_superblock(fw_dtype_t dt, int64_t n, int32_t path, size_t device_
 fw_status_t fw_apsp_ooc(fw_dtype_t dt, int64_t n, void *dist_host, int32_t *path_host, size_t device_bytes,
                         void *stream) {
     g_err[0] = 0;
-    fw_status_t st = check_common(dt, n, dist_host);
+    fw_status_t st = check_common(dt, n, dist_host, true);
     if (st != FW_OK) return st;
     const int64_t S = fw_ooc_superblock(dt, n, path_host != nullptr, device_bytes);
     if (S < 0) return (fw_status_t)S;
@@ -372,7 +390,7 @@ fw_status_t fw_apsp_batched_config(fw_dtype_t dt, int32_t batch, const int32_t *
                                    void *dist, int32_t *path, const fw_batched_config_t *cfg, void *stream) {
     g_err[0] = 0;
     if (cfg && (cfg->reserved0 || cfg->reserved1 || cfg->reserved2)) return fail(FW_EINVAL, "reserved config fields must be 0");
-    if (dt != FW_F32 && dt != FW_F64) return fail(FW_EINVAL, "unknown dtype %d", (int)dt);
+    if (fw_status_t st = check_dtype(dt, true); st != FW_OK) return st;
     if (batch < 1) return fail(FW_EINVAL, "batch = %d < 1", batch);
     if (!n_host || !off_host || !dist) return fail(FW_EINVAL, "NULL argument");
     for (int32_t b = 0; b < batch; ++b) {
@@ -439,7 +457,7 @@ fw_status_t fw_apsp_batched(fw_dtype_t dt, int32_t batch, const int32_t *n_host,
 fw_status_t fw_apsp_backward(fw_dtype_t dt, int64_t n, int32_t batch, const void *dist, const int32_t *path,
                              const void *grad_dist, void *grad_w, void *stream) {
     g_err[0] = 0;
-    if (dt != FW_F32 && dt != FW_F64) return fail(FW_EINVAL, "unknown dtype %d", (int)dt);
+    if (fw_status_t st = check_dtype(dt, true); st != FW_OK) return st;
     if (n < 1 || n > kMaxBackwardN) return fail(FW_EINVAL, "n = %lld outside [1, %d]", (long long)n, kMaxBackwardN);
     if (batch < 1 || batch > 65535) return fail(FW_EINVAL, "batch = %d outside [1, 65535]", batch);
     if (!dist || !path || !grad_dist || !grad_w) return fail(FW_EINVAL, "NULL argument (path is required)");

@@ -7,7 +7,8 @@ It times, with HIP events on the current stream,
   * fw_apsp for every compiled (block, tile_m, tile_n, variant), under each round schedule
     that applies to it (serial; lookahead; pairs), at one representative n per size
     range, for float32/float64 with and without the path matrix, on complete
-    graphs with weights uniform in (0, 1);
+    graphs with weights uniform in (0, 1), and for binary16 on complete graphs
+    with integer weights in [1, 1000] (its exact range);
   * fw_apsp_batched on batches of equal-size graphs (weights in [1, 10],
     density 0.5) in 32 x 32 tiles and in 64 x 64 tiles, for the sizes from 16
     to 512 that both tilings pad alike; the split point small_max_n is the
@@ -42,20 +43,23 @@ def _timeit(fn, torch, reps, warmup=1):
     return t0.elapsed_time(t1) / reps
 
 
-def tune_apsp(fw, torch, log):
+def tune_apsp(fw, torch, log, dtypes=("f32", "f64", "f16")):
     import numpy as np
     import workloads
     table = []
-    for dt in ("f32", "f64"):
-        npdt = np.float32 if dt == "f32" else np.float64
+    codes = {"f32": fw.FW_F32, "f64": fw.FW_F64, "f16": fw.FW_F16}
+    for dt in dtypes:
         for lo, hi, n in BUCKETS:
-            W = torch.from_numpy(workloads.unit_complete(n, dtype=npdt, seed=2)).cuda()
+            if dt == "f16":
+                W = torch.from_numpy(workloads.int_graph(n, 1.0, 1000, seed=2).astype(np.float16)).cuda()
+            else:
+                npdt = np.float32 if dt == "f32" else np.float64
+                W = torch.from_numpy(workloads.unit_complete(n, dtype=npdt, seed=2)).cuda()
             D = torch.empty_like(W)
             for path in (False, True):
                 P = torch.empty((n, n), dtype=torch.int32, device=W.device) if path else None
                 best = None
-                cands = [(b, tm, tn, var, sch) for b, tm, tn, var in fw.fw_list_configs(
-                    fw.FW_F32 if dt == "f32" else fw.FW_F64)
+                cands = [(b, tm, tn, var, sch) for b, tm, tn, var in fw.fw_list_configs(codes[dt])
                     for sch in (fw.FW_SCHED_SERIAL, fw.FW_SCHED_LOOKAHEAD, fw.FW_SCHED_PAIRS)
                     if sch == fw.FW_SCHED_SERIAL or (sch == fw.FW_SCHED_LOOKAHEAD and fw.lookahead_applies(b, tm, tn, n))
                     or (sch == fw.FW_SCHED_PAIRS and fw.pairs_applies(b, tm, tn, var, n))]
@@ -71,7 +75,7 @@ def tune_apsp(fw, torch, log):
                           f"schedule={sch}: {ms:.3f} ms", flush=True)
                     if best is None or ms < best[0]:
                         best = (ms, block, tm, tn, var, sch)
-                table.append({"f64": dt == "f64", "path": path, "n_lo": lo, "n_hi": hi, "block": best[1],
+                table.append({"dtype": codes[dt], "path": path, "n_lo": lo, "n_hi": hi, "block": best[1],
                               "tile_m": best[2], "tile_n": best[3], "variant": best[4], "schedule": best[5]})
             del W, D
             torch.cuda.empty_cache()
@@ -113,7 +117,8 @@ def tune_batched(fw, torch, log):
                 else:
                     done = True
                 del W, D, P
-            table.append({"f64": dt == "f64", "path": path, "small_max_n": small_max_n})
+            table.append({"dtype": fw.FW_F64 if dt == "f64" else fw.FW_F32, "path": path,
+                          "small_max_n": small_max_n})
     return table
 
 
@@ -121,19 +126,19 @@ def write_inc(path, apsp_table, batched_table, arch):
     lines = [
         "// Tile configuration table.  Generated by paper_2105_07298_amd/tune.py from",
         f"// timings on {arch} (do not edit by hand; rerun the tuner instead).",
-        "// fw_apsp:          {f64, path, n_lo, n_hi, block, tile_m, tile_n, variant, schedule}  n_lo <= n < n_hi",
-        "// fw_apsp_batched:  {f64, path, small_max_n}",
+        "// fw_apsp:          {dtype, path, n_lo, n_hi, block, tile_m, tile_n, variant, schedule}  n_lo <= n < n_hi",
+        "// fw_apsp_batched:  {dtype, path, small_max_n}      dtype: 0 float32, 1 float64, 2 binary16",
         f"// generated {time.strftime('%Y-%m-%d')}",
         "static const TuneEntry kTuneApsp[] = {",
     ]
     for t in apsp_table:
         hi = "1LL << 40" if t["n_hi"] >= (1 << 40) else str(t["n_hi"])
-        lines.append(f"    {{{int(t['f64'])}, {int(t['path'])}, {t['n_lo']}, {hi}, {t['block']}, {t['tile_m']}, "
+        lines.append(f"    {{{int(t['dtype'])}, {int(t['path'])}, {t['n_lo']}, {hi}, {t['block']}, {t['tile_m']}, "
                      f"{t['tile_n']}, {t['variant']}, {t['schedule']}}},")
     lines.append("};")
     lines.append("static const TuneBatchedEntry kTuneBatched[] = {")
     for t in batched_table:
-        lines.append(f"    {{{int(t['f64'])}, {int(t['path'])}, {t['small_max_n']}}},")
+        lines.append(f"    {{{int(t['dtype'])}, {int(t['path'])}, {t['small_max_n']}}},")
     lines.append("};")
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -143,6 +148,10 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--out", required=True)
     ap.add_argument("--skip-apsp", action="store_true")
+    ap.add_argument("--dtypes", default="f32,f64,f16", help="element types to time for fw_apsp")
+    ap.add_argument("--keep", default="", help="tune_table.json whose rows are kept for the element types "
+                    "not timed (and whose batched rows are kept with --skip-batched)")
+    ap.add_argument("--skip-batched", action="store_true")
     args = ap.parse_args()
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     sys.path.insert(0, root)
@@ -152,8 +161,19 @@ def main():
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     os.makedirs(args.out, exist_ok=True)
     log = []
-    apsp_table = [] if args.skip_apsp else tune_apsp(fw, torch, log)
-    batched_table = tune_batched(fw, torch, log)
+    dtypes = tuple(d for d in args.dtypes.split(",") if d)
+    apsp_table = [] if args.skip_apsp else tune_apsp(fw, torch, log, dtypes)
+    batched_table = [] if args.skip_batched else tune_batched(fw, torch, log)
+    if args.keep:
+        with open(args.keep) as f:
+            old = json.load(f)
+        codes = {"f32": fw.FW_F32, "f64": fw.FW_F64, "f16": fw.FW_F16}
+        timed = {codes[d] for d in dtypes} if not args.skip_apsp else set()
+        apsp_table = [t for t in old["apsp"] if t["dtype"] not in timed] + apsp_table
+        apsp_table.sort(key=lambda t: (t["dtype"], t["n_lo"], t["path"]))
+        if args.skip_batched:
+            batched_table = old["batched"]
+        log = [t for t in old["timings"] if not (t["kind"] == "apsp" and codes[t["dtype"]] in timed)] + log
     with open(os.path.join(args.out, "tune_table.json"), "w") as f:
         json.dump({"arch": arch, "apsp": apsp_table, "batched": batched_table, "timings": log}, f, indent=1)
     write_inc(os.path.join(args.out, "tune_table.inc"), apsp_table, batched_table, arch)

@@ -89,8 +89,36 @@ def test_list_configs(fw):
     assert fw.lib().fw_list_configs(0, None, 3) == fw.FW_EINVAL
 
 
+def test_list_configs_f16(fw):
+    """binary16: LDS-panel kernels only, 8 columns per thread (tile_n >= 128)."""
+    cfgs = fw.fw_list_configs(fw.FW_F16)
+    assert len(cfgs) == len(set(cfgs)) >= 4
+    for b, tm, tn, var in cfgs:
+        assert var == fw.FW_P4_PANELS and b in (32, 64)
+        assert tn in (128, 256) and tm % 16 == 0 and tn % b == 0
+    L = fw.lib()
+    for bad in ((64, 64, 64, 1), (64, 64, 128, 2)):
+        cfg = fw._lib.FwConfig(*bad)
+        assert L.fw_apsp_config(fw.FW_F16, 128, 4096, None, ctypes.byref(cfg), None) == fw.FW_EUNSUPPORTED, bad
+
+
+def test_f16_only_where_declared(fw):
+    """FW_F16 is an fw_apsp dtype; the batched, backward and out-of-core entry
+    points refuse it before touching a device."""
+    import numpy as np
+    L = fw.lib()
+    ns = np.array([4], dtype=np.int32)
+    offs = np.array([0], dtype=np.int64)
+    assert L.fw_apsp_batched(fw.FW_F16, 1, ns.ctypes.data, offs.ctypes.data, 4096, None, None) == fw.FW_EINVAL
+    assert "FW_F16" in fw.fw_last_error()
+    assert L.fw_apsp_backward(fw.FW_F16, 16, 1, 4096, 4096, 4096, 4096, None) == fw.FW_EINVAL
+    assert L.fw_apsp_ooc(fw.FW_F16, 16, 4096, None, 1 << 20, None) == fw.FW_EINVAL
+    assert L.fw_ooc_superblock(fw.FW_F16, 3000, 0, 1 << 30) == fw.FW_EINVAL
+    assert L.fw_apsp(3, 16, 4096, None, None) == fw.FW_EINVAL
+
+
 def test_query_config(fw):
-    for dt in (0, 1):
+    for dt in (0, 1, 2):
         compiled = set(fw.fw_list_configs(dt))
         for n in (1, 100, 1000, 5000, 16384, 65536):
             for path in (False, True):

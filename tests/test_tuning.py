@@ -23,16 +23,18 @@ def entries():
 def test_apsp_table_covers_every_size_once():
     import paper_2105_07298_amd as fw
     rows, _ = entries()
-    supported = {f64: set(fw.fw_list_configs(f64)) for f64 in (0, 1)}
-    for f64 in (0, 1):
+    dtypes = (fw.FW_F32, fw.FW_F64, fw.FW_F16)
+    supported = {dt: set(fw.fw_list_configs(dt)) for dt in dtypes}
+    assert {r[0] for r in rows} == set(dtypes)
+    for dt in dtypes:
         for path in (0, 1):
-            rs = sorted((r for r in rows if r[0] == f64 and r[1] == path), key=lambda r: r[2])
-            assert rs, (f64, path)
+            rs = sorted((r for r in rows if r[0] == dt and r[1] == path), key=lambda r: r[2])
+            assert rs, (dt, path)
             assert rs[0][2] == 0 and rs[-1][3] >= (1 << 40)
             for a, b in zip(rs[:-1], rs[1:]):
                 assert a[3] == b[2], "size ranges must tile [0, inf)"
             for r in rs:
-                assert (r[4], r[5], r[6], r[7]) in supported[f64], r
+                assert (r[4], r[5], r[6], r[7]) in supported[dt], r
                 assert r[8] in (fw.FW_SCHED_SERIAL, fw.FW_SCHED_LOOKAHEAD, fw.FW_SCHED_PAIRS), r
 
 
