@@ -280,6 +280,17 @@ __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__re
 // marked pending (L = r + 1) and resolved by k_resolve.  L is read with the old
 // tile and, for each 16-byte vector of D that changed, the matching run of L
 // (8 bytes for float, 4 for double) is written back whole.
+// k per staged chunk of the last phase's panels: the whole block, halved while
+// the two panels of a chunk take more than 40 KB of LDS (four workgroups per CU
+// need at most 40 KB each of the 160 KB).
+template <typename T>
+constexpr int p4_kchunk(int TB, int BM, int BN) {
+    int kc = TB;
+    const int v = 16 / (int)sizeof(T);
+    while (kc > 2 * v && (BM * (kc + v) + kc * BN) * (int)sizeof(T) > 40 * 1024) kc /= 2;
+    return kc;
+}
+
 template <typename T, int TB, int BM, int BN, bool PATH, bool CROSS, bool FUSE = false>
 __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__restrict__ L, int64_t ld, int r,
                                               TileSel sel) {
@@ -290,13 +301,18 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
     static_assert(TY * RM == BM, "tile rows");
     static_assert(RN % V == 0, "micro-tile width");
     constexpr int HN = RN / V, CS = BN / HN;
-    constexpr int AST = TB + V;
+    // The panels of a round are staged KC values of k at a time (KC = TB unless
+    // both panels of the whole block would take more than 40 KB of LDS, which
+    // would leave room for fewer than four workgroups per CU).
+    constexpr int KC = p4_kchunk<T>(TB, BM, BN);
+    static_assert(TB % KC == 0 && KC % V == 0, "k chunk");
+    constexpr int AST = KC + V;
     // Old C values are requested before the panel loads when they fit the
     // register budget (up to 128 bytes per thread), else after the k-loop.
     constexpr bool PREFETCH_C = RM * RN * (int)sizeof(T) <= 128;
 
     __shared__ __attribute__((aligned(16))) T As[BM * AST];
-    __shared__ __attribute__((aligned(16))) T Bs[TB * BN];
+    __shared__ __attribute__((aligned(16))) T Bs[KC * BN];
 
     int bi, bj;
     if (!select_tile<CROSS>(sel, blockIdx.x, bi, bj)) return;
@@ -321,22 +337,22 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
             }
     }
 
-    // Stage the column panel D[I, K] and row panel D[K, J] of the block that
-    // starts at kb; the block's own rows / columns are masked in a tile wider
-    // than the block.
-    auto stage = [&](int64_t kb) {
+    // Stage columns kb + kc .. kb + kc + KC - 1 of the column panel D[I, K] and
+    // the same rows of the row panel D[K, J], for the block that starts at kb;
+    // the block's own rows / columns are masked in a tile wider than the block.
+    auto stage = [&](int64_t kb, int kc) {
         const bool mask_rows = sel.nsr == 0 && (I0 <= kb) && (kb < I0 + BM);
         const bool mask_cols = sel.nsc == 0 && (J0 <= kb) && (kb < J0 + BN);
         const vec vinf = inf_v<T>();
-        for (int q = tid; q < BM * (TB / V); q += NT) {
-            const int row = q / (TB / V), kv = q % (TB / V);
-            vec v = *(const vec *)(D + (I0 + row) * ld + kb + kv * V);
+        for (int q = tid; q < BM * (KC / V); q += NT) {
+            const int row = q / (KC / V), kv = q % (KC / V);
+            vec v = *(const vec *)(D + (I0 + row) * ld + kb + kc + kv * V);
             if (mask_rows && (uint64_t)(I0 + row - kb) < (uint64_t)TB) v = vinf;
             *(vec *)(As + row * AST + kv * V) = v;
         }
-        for (int q = tid; q < TB * (BN / V); q += NT) {
+        for (int q = tid; q < KC * (BN / V); q += NT) {
             const int krow = q / (BN / V), cv = q % (BN / V);
-            vec v = *(const vec *)(D + (kb + krow) * ld + J0 + cv * V);
+            vec v = *(const vec *)(D + (kb + kc + krow) * ld + J0 + cv * V);
             if (mask_cols && (uint64_t)(J0 + cv * V - kb) < (uint64_t)TB) v = vinf;
             *(vec *)(Bs + krow * BN + cv * V) = v;
         }
@@ -352,12 +368,8 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
     using AccV = std::conditional_t<is_half_v<T>, half2_t, T>;
     AccV acc[RM][RN / AW];
     auto sweep = [&]() {
-#pragma unroll
-        for (int ii = 0; ii < RM; ++ii)
-#pragma unroll
-            for (int jj = 0; jj < RN / AW; ++jj) acc[ii][jj] = inf_v<T>();
 #pragma unroll 2
-        for (int kv = 0; kv < TB / V; ++kv) {
+        for (int kv = 0; kv < KC / V; ++kv) {
             vec a[RM];
 #pragma unroll
             for (int ii = 0; ii < RM; ++ii) a[ii] = *(const vec *)(As + (ty + TY * ii) * AST + kv * V);
@@ -400,9 +412,21 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
             return src[ii][jj];
     };
 
-    stage(k0);
-    __syncthreads();
-    sweep();
+    // acc <- min over block kb (every chunk) of the staged products.
+    auto round = [&](int64_t kb) {
+#pragma unroll
+        for (int ii = 0; ii < RM; ++ii)
+#pragma unroll
+            for (int jj = 0; jj < RN / AW; ++jj) acc[ii][jj] = inf_v<T>();
+        for (int kc = 0; kc < TB; kc += KC) {
+            if (kc) __syncthreads();  // every thread is done with the previous chunk
+            stage(kb, kc);
+            __syncthreads();
+            sweep();
+        }
+    };
+
+    round(k0);
     // A fused pair (rounds r and r + 1, tiles outside both blocks): keep round
     // r's minimum, then sweep round r + 1's panels, which are final by now.
     AccV acc0[RM][RN / AW];
@@ -412,9 +436,7 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
 #pragma unroll
             for (int jj = 0; jj < RN / AW; ++jj) acc0[ii][jj] = acc[ii][jj];
         __syncthreads();  // every thread is done with round r's panels
-        stage(k0 + TB);
-        __syncthreads();
-        sweep();
+        round(k0 + TB);
     }
 
     if constexpr (!PREFETCH_C) {
