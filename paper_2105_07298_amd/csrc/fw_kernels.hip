@@ -253,10 +253,22 @@ __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__re
         }
 }
 
+// k per staged chunk of the last phase's panels: the whole block, halved while
+// the two panels of a chunk take more than 40 KB of LDS (four workgroups per CU
+// need at most 40 KB each of the 160 KB).
+template <typename T>
+constexpr int p4_kchunk(int TB, int BM, int BN) {
+    int kc = TB;
+    const int v = 16 / (int)sizeof(T);
+    while (kc > 2 * v && (BM * (kc + v) + kc * BN) * (int)sizeof(T) > 40 * 1024) kc /= 2;
+    return kc;
+}
+
 // ---------------------------------------------------------------------------
 // Phase 4: C = D[I0:I0+BM, J0:J0+BN] <- min(C, D[I, K] (x) D[K, J]) for every
 // tile outside block row / column r.  The panels are final for the round, so the
-// k-loop has no barrier.  Thread layout: TX x TY threads, each owning an RM x RN
+// k-loop has no barrier (beyond one per staged chunk of KC values of k, see
+// p4_kchunk).  Thread layout: TX x TY threads, each owning an RM x RN
 // micro-tile in registers: rows ty + TY*ii, columns h*CS + tx*V + e (V
 // consecutive elements = one 16-byte vector, HN vectors per thread spread CS
 // apart so that a wave's LDS and global accesses are contiguous).
@@ -277,20 +289,9 @@ __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__re
 // candidate through block r has a label of at least k0.  So a candidate that
 // merely ties the old length never changes the label, and an entry that strictly
 // improves gets a label decided entirely by this round's candidates: it is
-// marked pending (L = r + 1) and resolved by k_resolve.  L is read with the old
-// tile and, for each 16-byte vector of D that changed, the matching run of L
-// (8 bytes for float, 4 for double) is written back whole.
-// k per staged chunk of the last phase's panels: the whole block, halved while
-// the two panels of a chunk take more than 40 KB of LDS (four workgroups per CU
-// need at most 40 KB each of the 160 KB).
-template <typename T>
-constexpr int p4_kchunk(int TB, int BM, int BN) {
-    int kc = TB;
-    const int v = 16 / (int)sizeof(T);
-    while (kc > 2 * v && (BM * (kc + v) + kc * BN) * (int)sizeof(T) > 40 * 1024) kc /= 2;
-    return kc;
-}
-
+// marked pending (L = r + 1) and resolved by k_resolve.  Each such mark is
+// written on its own (a 2-byte store under the entry's own condition), so this
+// phase never reads L.
 template <typename T, int TB, int BM, int BN, bool PATH, bool CROSS, bool FUSE = false>
 __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__restrict__ L, int64_t ld, int r,
                                               TileSel sel) {
@@ -321,20 +322,15 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
     auto c_ptr = [&](int ii, int h) { return D + (I0 + ty + TY * ii) * ld + J0 + h * CS + tx * V; };
 
-    typedef uint16_t lvec __attribute__((ext_vector_type(V)));
     auto l_ptr = [&](int ii, int h) { return L + (c_ptr(ii, h) - D); };
     vec c[RM][HN];
-    lvec lm[PATH ? RM : 1][PATH ? HN : 1];
     if constexpr (PREFETCH_C) {
-        // Old C values (and marks), requested first so their latency overlaps
-        // the panel loads.
+        // Old C values, requested first so their latency overlaps the panel
+        // loads.
 #pragma unroll
         for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
-            for (int h = 0; h < HN; ++h) {
-                c[ii][h] = *(const vec *)c_ptr(ii, h);
-                if constexpr (PATH) lm[ii][h] = *(const lvec *)l_ptr(ii, h);
-            }
+            for (int h = 0; h < HN; ++h) c[ii][h] = *(const vec *)c_ptr(ii, h);
     }
 
     // Stage columns kb + kc .. kb + kc + KC - 1 of the column panel D[I, K] and
@@ -443,10 +439,7 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
 #pragma unroll
         for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
-            for (int h = 0; h < HN; ++h) {
-                c[ii][h] = *(const vec *)c_ptr(ii, h);
-                if constexpr (PATH) lm[ii][h] = *(const lvec *)l_ptr(ii, h);
-            }
+            for (int h = 0; h < HN; ++h) c[ii][h] = *(const vec *)c_ptr(ii, h);
     }
 
     // New distances: store the 16-byte vectors in which some entry decreased;
@@ -481,10 +474,10 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
             if (ch) {
                 *(vec *)c_ptr(ii, h) = nv;
                 if constexpr (PATH) {
-                    lvec nl = lm[ii][h];
+                    uint16_t *lp = l_ptr(ii, h);
 #pragma unroll
-                    for (int e = 0; e < V; ++e) nl[e] = mk[e] ? mk[e] : nl[e];
-                    *(lvec *)l_ptr(ii, h) = nl;
+                    for (int e = 0; e < V; ++e)
+                        if (mk[e]) lp[e] = mk[e];
                 }
             }
         }
@@ -513,7 +506,6 @@ __global__ void __launch_bounds__(NT) k_phase4w(T *__restrict__ D, uint16_t *__r
     constexpr int V = V16<T>::n;
     static_assert(BN % V == 0, "row panel width");
     typedef T cvec __attribute__((ext_vector_type(RN)));
-    typedef uint16_t lvec __attribute__((ext_vector_type(RN)));
     typedef const T __attribute__((address_space(4))) CT;  // scalar (constant) loads
     __shared__ __attribute__((aligned(16))) T Bs[TB * BN];
 
@@ -527,14 +519,10 @@ __global__ void __launch_bounds__(NT) k_phase4w(T *__restrict__ D, uint16_t *__r
     T *crow = D + i0 * ld + J0 + lane * RN;
     uint16_t *lrow = L + (crow - D);
 
-    // Old C values (and marks) first, so their latency overlaps the staging.
+    // Old C values first, so their latency overlaps the staging.
     cvec c[RM];
-    lvec lm[PATH ? RM : 1];
 #pragma unroll
-    for (int ii = 0; ii < RM; ++ii) {
-        c[ii] = *(const cvec *)(crow + ii * ld);
-        if constexpr (PATH) lm[ii] = *(const lvec *)(lrow + ii * ld);
-    }
+    for (int ii = 0; ii < RM; ++ii) c[ii] = *(const cvec *)(crow + ii * ld);
     const vec vinf = inf_v<T>();
     for (int q = threadIdx.x; q < TB * (BN / V); q += NT) {
         const int krow = q / (BN / V), cv = q % (BN / V);
@@ -576,18 +564,20 @@ __global__ void __launch_bounds__(NT) k_phase4w(T *__restrict__ D, uint16_t *__r
 #pragma unroll
     for (int ii = 0; ii < RM; ++ii) {
         cvec nv = c[ii];
-        lvec nl = lm[PATH ? ii : 0];
-        bool ch = false;
+        bool ch = false, lt[RN];
 #pragma unroll
         for (int e = 0; e < RN; ++e) {
-            const bool lt = acc[ii][e] < nv[e];
-            ch |= lt;
-            nv[e] = lt ? acc[ii][e] : nv[e];
-            if constexpr (PATH) nl[e] = lt ? pend : nl[e];
+            lt[e] = acc[ii][e] < nv[e];
+            ch |= lt[e];
+            nv[e] = lt[e] ? acc[ii][e] : nv[e];
         }
         if (ch) {
             *(cvec *)(crow + ii * ld) = nv;
-            if constexpr (PATH) *(lvec *)(lrow + ii * ld) = nl;
+            if constexpr (PATH) {
+#pragma unroll
+                for (int e = 0; e < RN; ++e)
+                    if (lt[e]) lrow[ii * ld + e] = pend;
+            }
         }
     }
 }
