@@ -258,8 +258,13 @@ def time_fwd_bwd(fw, torch, steps=5, warmup=2):
             D, P = fw._forward(Wd)
             return fw.apsp_backward(D, P, Gd)
 
+        D0, P0 = fw._forward(Wd)
+
+        def bwd():
+            return fw.apsp_backward(D0, P0, Gd)
+
         res = {}
-        for name, fn in (("fwd", fwd), ("fwd_bwd", fwd_bwd)):
+        for name, fn in (("fwd", fwd), ("fwd_bwd", fwd_bwd), ("bwd", bwd)):
             for _ in range(warmup):
                 fn()
             t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -278,7 +283,13 @@ def time_fwd_bwd(fw, torch, steps=5, warmup=2):
     Ws = np.stack([workloads.grad_graph(n=128, seed=5, g=b)[0] for b in range(256)])
     Gs = np.stack([workloads.grad_graph(n=128, seed=5, g=b)[1] for b in range(256)])
     batch = measure(Ws, Gs)
-    return {"n2048": single, "batch256_n128": batch}
+    # The complete graph with weights in [1, 2) has D = W (every shortest path is its
+    # direct edge), so its backward is a one-level scatter.  The same weights at edge
+    # density 0.05 give multi-hop shortest paths and deep subtrees.
+    Wsp, Gsp = workloads.grad_graph(n=2048, seed=5, p=0.05)
+    sparse = measure(Wsp, Gsp)
+    return {"n2048": single, "batch256_n128": batch,
+            "n2048_density0.05": dict(sparse, note="non-degenerate: multi-hop shortest paths")}
 
 
 def roofline(n, dtype, stats, path=True):
