@@ -9,15 +9,24 @@
 // graphs start first and the small ones fill the gaps at the end.
 //
 // Inside a workgroup a graph is processed TB x TB tile by tile through LDS (TB =
-// 32 or 64 per graph, by size, from the tuning table): the
-// diagonal block is closed by TB sequential k-steps; panel and remaining tiles
-// are min-plus products of two LDS-resident operand tiles with the old tile
-// held in registers.  Every step applies the lexicographic label rule
+// 32 or 64 per graph, by size, from the tuning table): the diagonal block is
+// closed by TB sequential k-steps; panel and remaining tiles are min-plus
+// products of two LDS-resident operand tiles with the old tile held in
+// registers.  Every step applies the lexicographic label rule
 // (length, max(P[i][k], k, P[k][j])), so D and P equal the single-graph result
 // (and the classic loop's, for exact weights) whatever TB is.  Graphs are stored
-// unpadded (leading dimension n, any offset), so tile loads are guarded: rows
-// and columns beyond n read as isolated padding vertices (+inf off the
-// diagonal, 0 on it, label -1) and are never written.
+// unpadded (leading dimension n, any offset), so global accesses are guarded
+// element by element: rows and columns beyond n read as isolated padding
+// vertices (+inf off the diagonal, 0 on it, label -1) and are never written.
+//
+// The tile products follow the single-graph last phase: thread (ty, tx) of a
+// 16 x 16 layout owns rows ty + 16*ii and a run of VB contiguous columns per
+// vector; operand tiles sit in LDS row-major with a row stride of TB + V
+// elements, so a thread reads V consecutive k of a row, or VB consecutive
+// columns of a k row, with one vector load; without labels two k are folded per
+// three-way minimum.  In the last phase the column-panel tile of a block row
+// stays staged while the row's tiles are swept.  Labels are held in LDS as
+// 16-bit label + 1 (n <= 4096).
 #include "fw_internal.h"
 #include "fw_lex.h"
 
@@ -30,189 +39,256 @@ template <typename T> __device__ __forceinline__ T inf_b();
 template <> __device__ __forceinline__ float inf_b<float>() { return __builtin_inff(); }
 template <> __device__ __forceinline__ double inf_b<double>() { return __builtin_inf(); }
 
-// One graph's tile machinery.  Thread (ty, tx) of the 16 x 16 layout owns rows
-// ty + 16*ii and columns tx + 16*jj of a TB x TB tile (RM = TB/16 per side).
+__device__ __forceinline__ float bmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ double bmin(double a, double b) { return __builtin_fmin(a, b); }
+
+template <typename T, int W> struct VecT {
+    typedef T type __attribute__((ext_vector_type(W)));
+};
+
+// One graph and its TB x TB tiles.  Thread (ty, tx) of the 16 x 16 layout owns
+// rows ty + 16*ii (RM of them) and, per vector h, the VB contiguous columns from
+// h*CS + tx*VB (RN columns in all).
 template <typename T, int TB, bool PATH>
-struct GraphTiles {
-    static constexpr int TS = 16, RM = TB / TS, ST = TB + 1;
+struct Graph {
+    static constexpr int V = 16 / (int)sizeof(T);  // k per A-operand vector
+    static constexpr int RM = TB / 16, RN = TB / 16;
+    static constexpr int VB = RN < V ? RN : V;     // columns per B-operand vector
+    static constexpr int HN = RN / VB, CS = TB / HN;
+    static constexpr int ST = TB + V;              // LDS row stride (elements)
+    using vecA = typename VecT<T, V>::type;
+    using vecB = typename VecT<T, VB>::type;
+    using lvA = typename VecT<uint16_t, V>::type;
+    using lvB = typename VecT<uint16_t, VB>::type;
+
     T *D;
     int32_t *P;
     int n;
 
-    // Lengths pass through canon() in path mode (lex_take_u's key needs +0.0).
+    __device__ static int row(int ty, int ii) { return ty + 16 * ii; }
+    __device__ static int col(int tx, int h) { return h * CS + tx * VB; }
+
+    // Lengths pass through canon() in path mode (lex_take_u's key needs +0.0);
+    // labels are read as label + 1.
+    // (Indices within one graph are below 4096^2, so 32-bit offsets from the
+    // graph's base pointer suffice.)
     __device__ T ld_d(int i, int j) const {
-        if (i < n && j < n) return PATH ? canon(D[(int64_t)i * n + j]) : D[(int64_t)i * n + j];
+        if (i < n && j < n) return PATH ? canon(D[i * n + j]) : D[i * n + j];
         return i == j ? (T)0 : inf_b<T>();
     }
-    // Labels are held as label + 1 between load and store.
-    __device__ uint32_t ld_p(int i, int j) const {
-        return (i < n && j < n) ? (uint32_t)(P[(int64_t)i * n + j] + 1) : 0u;
-    }
-    // Stage tile (I0, J0) into LDS (values, and labels in path mode).
-    __device__ void stage(T *sd, uint32_t *sp, int I0, int J0) const {
+    __device__ uint32_t ld_p(int i, int j) const { return (i < n && j < n) ? (uint32_t)(P[i * n + j] + 1) : 0u; }
+    // Tile (I0, J0) into LDS, row-major with stride ST (labels likewise).
+    __device__ void stage(T *s, uint16_t *l, int I0, int J0) const {
         for (int q = threadIdx.x; q < TB * TB; q += NT) {
             const int rr = q / TB, cc = q % TB;
-            sd[rr * ST + cc] = ld_d(I0 + rr, J0 + cc);
-            if (PATH) sp[rr * ST + cc] = ld_p(I0 + rr, J0 + cc);
+            s[rr * ST + cc] = ld_d(I0 + rr, J0 + cc);
+            if (PATH) l[rr * ST + cc] = (uint16_t)ld_p(I0 + rr, J0 + cc);
         }
     }
-    __device__ void load_regs(T (&d)[RM][RM], uint32_t (&p)[RM][RM], int I0, int J0, int tx, int ty) const {
+    // The thread's entries of tile (I0, J0): from global memory ...
+    __device__ void load(T (&d)[RM][RN], uint32_t (&p)[RM][RN], int I0, int J0, int tx, int ty) const {
 #pragma unroll
         for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
-            for (int jj = 0; jj < RM; ++jj) {
-                d[ii][jj] = ld_d(I0 + ty + TS * ii, J0 + tx + TS * jj);
-                if (PATH) p[ii][jj] = ld_p(I0 + ty + TS * ii, J0 + tx + TS * jj);
-            }
+            for (int h = 0; h < HN; ++h)
+#pragma unroll
+                for (int e = 0; e < VB; ++e) {
+                    const int i = I0 + row(ty, ii), j = J0 + col(tx, h) + e;
+                    d[ii][h * VB + e] = ld_d(i, j);
+                    if (PATH) p[ii][h * VB + e] = ld_p(i, j);
+                }
     }
-    __device__ void store_regs(const T (&d)[RM][RM], const uint32_t (&p)[RM][RM], int I0, int J0, int tx,
-                               int ty) const {
+    // ... or from a staged copy.
+    __device__ static void load_lds(T (&d)[RM][RN], uint32_t (&p)[RM][RN], const T *s, const uint16_t *l, int tx,
+                                    int ty) {
 #pragma unroll
         for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
-            for (int jj = 0; jj < RM; ++jj) {
-                const int i = I0 + ty + TS * ii, j = J0 + tx + TS * jj;
-                if (i < n && j < n) {
-                    D[(int64_t)i * n + j] = d[ii][jj];
-                    if (PATH) P[(int64_t)i * n + j] = (int32_t)p[ii][jj] - 1;
+            for (int h = 0; h < HN; ++h)
+#pragma unroll
+                for (int e = 0; e < VB; ++e) {
+                    const int x = row(ty, ii) * ST + col(tx, h) + e;
+                    d[ii][h * VB + e] = s[x];
+                    if (PATH) p[ii][h * VB + e] = l[x];
+                }
+    }
+    __device__ void store(const T (&d)[RM][RN], const uint32_t (&p)[RM][RN], int I0, int J0, int tx, int ty) const {
+#pragma unroll
+        for (int ii = 0; ii < RM; ++ii)
+#pragma unroll
+            for (int h = 0; h < HN; ++h)
+#pragma unroll
+                for (int e = 0; e < VB; ++e) {
+                    const int i = I0 + row(ty, ii), j = J0 + col(tx, h) + e;
+                    if (i < n && j < n) {
+                        D[i * n + j] = d[ii][h * VB + e];
+                        if (PATH) P[i * n + j] = (int32_t)p[ii][h * VB + e] - 1;
+                    }
+                }
+    }
+
+    // (d, p) <- lexmin over k in the block of (d, p) and the candidates through k:
+    // A[i][k] + B[k][j] with label max(LA[i][k], kbase + k, LB[k][j]) (labels +
+    // 1); distances only: d <- min(d, A[i][k] + B[k][j]), two k per v_min3.
+    __device__ static void product(T (&d)[RM][RN], uint32_t (&p)[RM][RN], const T *A, const uint16_t *LA,
+                                   const T *B, const uint16_t *LB, int kbase, int tx, int ty) {
+#pragma unroll 2
+        for (int kv = 0; kv < TB / V; ++kv) {
+            vecA a[RM];
+            lvA pa[PATH ? RM : 1];
+#pragma unroll
+            for (int ii = 0; ii < RM; ++ii) {
+                a[ii] = *(const vecA *)(A + row(ty, ii) * ST + kv * V);
+                if (PATH) pa[ii] = *(const lvA *)(LA + row(ty, ii) * ST + kv * V);
+            }
+            if constexpr (PATH) {
+#pragma unroll
+                for (int kk = 0; kk < V; ++kk) {
+                    vecB b[HN];
+                    lvB pb[HN];
+#pragma unroll
+                    for (int h = 0; h < HN; ++h) {
+                        b[h] = *(const vecB *)(B + (kv * V + kk) * ST + col(tx, h));
+                        pb[h] = *(const lvB *)(LB + (kv * V + kk) * ST + col(tx, h));
+                    }
+                    const uint32_t kg1 = (uint32_t)(kbase + kv * V + kk + 1);
+#pragma unroll
+                    for (int ii = 0; ii < RM; ++ii) {
+                        const uint32_t mi = max((uint32_t)pa[ii][kk], kg1);
+#pragma unroll
+                        for (int h = 0; h < HN; ++h)
+#pragma unroll
+                            for (int e = 0; e < VB; ++e)
+                                lex_take_u(d[ii][h * VB + e], p[ii][h * VB + e], a[ii][kk] + b[h][e],
+                                           max(mi, (uint32_t)pb[h][e]));
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < V; kk += 2) {
+                    vecB b0[HN], b1[HN];
+#pragma unroll
+                    for (int h = 0; h < HN; ++h) {
+                        b0[h] = *(const vecB *)(B + (kv * V + kk) * ST + col(tx, h));
+                        b1[h] = *(const vecB *)(B + (kv * V + kk + 1) * ST + col(tx, h));
+                    }
+#pragma unroll
+                    for (int ii = 0; ii < RM; ++ii)
+#pragma unroll
+                        for (int h = 0; h < HN; ++h)
+#pragma unroll
+                            for (int e = 0; e < VB; ++e) {
+                                T &x = d[ii][h * VB + e];
+                                x = bmin(bmin(x, a[ii][kk] + b0[h][e]), a[ii][kk + 1] + b1[h][e]);
+                            }
                 }
             }
+        }
     }
 };
 
-template <typename T, bool PATH>
-__device__ __forceinline__ void take(T &d, uint32_t &p, T s, uint32_t m) {
-    if (PATH)
-        lex_take_u(d, p, s, m);
-    else
-        d = s < d ? s : d;
-}
-
-// One graph, whole method, by the calling workgroup.
+// One graph, whole method, by the calling workgroup.  sa / sb (and la / lb) are
+// LDS tiles of TB x ST elements.
 template <typename T, int TB, bool PATH>
-__device__ void solve_graph(GraphTiles<T, TB, PATH> g, T *sa, T *sb, uint32_t *spa, uint32_t *spb) {
-    using G = GraphTiles<T, TB, PATH>;
-    constexpr int TS = G::TS, RM = G::RM, ST = G::ST;
-    const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
+__device__ void solve_graph(Graph<T, TB, PATH> g, T *sa, T *sb, uint16_t *la, uint16_t *lb) {
+    using G = Graph<T, TB, PATH>;
+    constexpr int RM = G::RM, RN = G::RN, VB = G::VB, HN = G::HN, ST = G::ST;
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
     const int n = g.n;
     if (PATH) {
-        for (int64_t x = threadIdx.x; x < (int64_t)n * n; x += NT) g.P[x] = -1;
+        for (int x = threadIdx.x; x < n * n; x += NT) g.P[x] = -1;
     }
     __syncthreads();
     const int R = (n + TB - 1) / TB;
-    T d[RM][RM];
-    uint32_t p[RM][RM];
+    T d[RM][RN];
+    uint32_t p[RM][RN];
     for (int r = 0; r < R; ++r) {
         const int k0 = r * TB;
         // Phase 1: close the diagonal block in LDS.  Row k and column k do not
         // change at step k (D[k][k] = 0: their candidates equal the current
         // value with a label that is not smaller), so updating in place while
         // others read them is safe; one barrier per k orders the steps.
-        g.stage(sa, spa, k0, k0);
+        g.stage(sa, la, k0, k0);
         __syncthreads();
-        g.load_regs(d, p, k0, k0, tx, ty);
+        G::load_lds(d, p, sa, la, tx, ty);
         for (int k = 0; k < TB; ++k) {
-            T a[RM], b[RM];
-            uint32_t pa[RM], pb[RM];
+            T a[RM];
+            uint32_t pa[RM];
 #pragma unroll
             for (int ii = 0; ii < RM; ++ii) {
-                a[ii] = sa[(ty + TS * ii) * ST + k];
-                if (PATH) pa[ii] = spa[(ty + TS * ii) * ST + k];
+                a[ii] = sa[G::row(ty, ii) * ST + k];
+                if (PATH) pa[ii] = max((uint32_t)la[G::row(ty, ii) * ST + k], (uint32_t)(k0 + k + 1));
             }
 #pragma unroll
-            for (int jj = 0; jj < RM; ++jj) {
-                b[jj] = sa[k * ST + tx + TS * jj];
-                if (PATH) pb[jj] = spa[k * ST + tx + TS * jj];
-            }
+            for (int h = 0; h < HN; ++h) {
+                const typename G::vecB b = *(const typename G::vecB *)(sa + k * ST + G::col(tx, h));
+                typename G::lvB pb;
+                if (PATH) pb = *(const typename G::lvB *)(la + k * ST + G::col(tx, h));
 #pragma unroll
-            for (int ii = 0; ii < RM; ++ii)
+                for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
-                for (int jj = 0; jj < RM; ++jj) {
-                    const T s = a[ii] + b[jj];
-                    const uint32_t m = PATH ? max(max(pa[ii], pb[jj]), (uint32_t)(k0 + k + 1)) : 0u;
-                    const T d0 = d[ii][jj];
-                    const uint32_t p0 = p[ii][jj];
-                    take<T, PATH>(d[ii][jj], p[ii][jj], s, m);
-                    if (d[ii][jj] != d0 || (PATH && p[ii][jj] != p0)) {
-                        sa[(ty + TS * ii) * ST + tx + TS * jj] = d[ii][jj];
-                        if (PATH) spa[(ty + TS * ii) * ST + tx + TS * jj] = p[ii][jj];
+                    for (int e = 0; e < VB; ++e) {
+                        T &x = d[ii][h * VB + e];
+                        uint32_t &y = p[ii][h * VB + e];
+                        const T s = a[ii] + b[e];
+                        const int at = G::row(ty, ii) * ST + G::col(tx, h) + e;
+                        if (PATH) {
+                            const T x0 = x;
+                            const uint32_t y0 = y;
+                            lex_take_u(x, y, s, max(pa[ii], (uint32_t)pb[e]));
+                            if (x != x0 || y != y0) {
+                                sa[at] = x;
+                                la[at] = (uint16_t)y;
+                            }
+                        } else if (s < x) {
+                            x = s;
+                            sa[at] = s;
+                        }
                     }
-                }
+            }
             __syncthreads();
         }
-        g.store_regs(d, p, k0, k0, tx, ty);
-        // The closed diagonal block stays in sa/spa for the panels.
-        __syncthreads();
-        // Phases 2 and 3: each panel tile is one product with the closed block.
+        g.store(d, p, k0, k0, tx, ty);
+        // The closed diagonal block stays in sa / la for the panels.
+        // Phases 2 and 3: each panel tile is one product with the closed block
+        // (the row panel as its right operand, the column panel as its left).
         for (int t = 0; t < 2 * (R - 1); ++t) {
             const bool rowp = t < R - 1;
             const int o0 = rowp ? t : t - (R - 1);
             const int o = o0 < r ? o0 : o0 + 1;
             const int I0 = rowp ? k0 : o * TB, J0 = rowp ? o * TB : k0;
-            // the old panel tile goes to sb (it is the B operand of a row panel
-            // and the A operand of a column panel)
-            g.stage(sb, spb, I0, J0);
-            g.load_regs(d, p, I0, J0, tx, ty);
+            g.stage(sb, lb, I0, J0);  // the old panel tile
             __syncthreads();
-            const T *A = rowp ? sa : sb;
-            const T *B = rowp ? sb : sa;
-            const uint32_t *PA = rowp ? spa : spb;
-            const uint32_t *PB = rowp ? spb : spa;
-            for (int k = 0; k < TB; ++k) {
-                T a[RM], b[RM];
-                uint32_t pa[RM], pb[RM];
-#pragma unroll
-                for (int ii = 0; ii < RM; ++ii) {
-                    a[ii] = A[(ty + TS * ii) * ST + k];
-                    if (PATH) pa[ii] = max(PA[(ty + TS * ii) * ST + k], (uint32_t)(k0 + k + 1));
-                }
-#pragma unroll
-                for (int jj = 0; jj < RM; ++jj) {
-                    b[jj] = B[k * ST + tx + TS * jj];
-                    if (PATH) pb[jj] = PB[k * ST + tx + TS * jj];
-                }
-#pragma unroll
-                for (int ii = 0; ii < RM; ++ii)
-#pragma unroll
-                    for (int jj = 0; jj < RM; ++jj)
-                        take<T, PATH>(d[ii][jj], p[ii][jj], a[ii] + b[jj], PATH ? max(pa[ii], pb[jj]) : 0u);
-            }
-            g.store_regs(d, p, I0, J0, tx, ty);
+            G::load_lds(d, p, sb, lb, tx, ty);
+            G::product(d, p, rowp ? sa : sb, rowp ? la : lb, rowp ? sb : sa, rowp ? lb : la, k0, tx, ty);
+            g.store(d, p, I0, J0, tx, ty);
             __syncthreads();
         }
-        // Phase 4: every other tile, product of its final column-panel and
-        // row-panel tiles (staged per tile; the panels are not written here).
+        // Phase 4: every other tile, product of its final column-panel tile
+        // (staged once per tile row) and row-panel tile.
         for (int t = 0; t < (R - 1) * (R - 1); ++t) {
             const int bi0 = t / (R - 1), bj0 = t % (R - 1);
             const int bi = bi0 < r ? bi0 : bi0 + 1, bj = bj0 < r ? bj0 : bj0 + 1;
             const int I0 = bi * TB, J0 = bj * TB;
-            g.stage(sa, spa, I0, k0);
-            g.stage(sb, spb, k0, J0);
-            g.load_regs(d, p, I0, J0, tx, ty);
+            if (bj0 == 0) g.stage(sa, la, I0, k0);
+            g.stage(sb, lb, k0, J0);
+            g.load(d, p, I0, J0, tx, ty);
             __syncthreads();
-            for (int k = 0; k < TB; ++k) {
-                T a[RM], b[RM];
-                uint32_t pa[RM], pb[RM];
-#pragma unroll
-                for (int ii = 0; ii < RM; ++ii) {
-                    a[ii] = sa[(ty + TS * ii) * ST + k];
-                    if (PATH) pa[ii] = max(spa[(ty + TS * ii) * ST + k], (uint32_t)(k0 + k + 1));
-                }
-#pragma unroll
-                for (int jj = 0; jj < RM; ++jj) {
-                    b[jj] = sb[k * ST + tx + TS * jj];
-                    if (PATH) pb[jj] = spb[k * ST + tx + TS * jj];
-                }
-#pragma unroll
-                for (int ii = 0; ii < RM; ++ii)
-#pragma unroll
-                    for (int jj = 0; jj < RM; ++jj)
-                        take<T, PATH>(d[ii][jj], p[ii][jj], a[ii] + b[jj], PATH ? max(pa[ii], pb[jj]) : 0u);
-            }
-            g.store_regs(d, p, I0, J0, tx, ty);
+            G::product(d, p, sa, la, sb, lb, k0, tx, ty);
+            g.store(d, p, I0, J0, tx, ty);
             __syncthreads();
         }
     }
+}
+
+// Workgroups per CU that the LDS of k_batched admits (160 KB per CU): the
+// register budget is sized to match.
+template <typename T, bool PATH>
+constexpr int batched_wgs_per_cu() {
+    constexpr int st = 64 + 16 / (int)sizeof(T);
+    constexpr int bytes = 2 * 64 * st * ((int)sizeof(T) + (PATH ? 2 : 0));
+    constexpr int w = 160 * 1024 / (bytes + 64);
+    return w < 1 ? 1 : (w > 4 ? 4 : w);
 }
 
 // Persistent batched kernel.  jobs[0] holds the queue counter (set to 0 by the
@@ -222,13 +298,13 @@ __device__ void solve_graph(GraphTiles<T, TB, PATH> g, T *sa, T *sb, uint32_t *s
 // (n mod 64 = 0 or > 32); otherwise 32 x 32 tiles.  Both share the LDS arrays,
 // sized for 64.
 template <typename T, bool PATH>
-__global__ void __launch_bounds__(NT) k_batched(T *__restrict__ dist, int32_t *__restrict__ path,
+__global__ void __launch_bounds__(NT, (batched_wgs_per_cu<T, PATH>())) k_batched(T *__restrict__ dist, int32_t *__restrict__ path,
                                                int64_t *__restrict__ jobs, int njobs, int small_max_n) {
-    constexpr int ST = 64 + 1;
-    __shared__ T sa[64 * ST];
-    __shared__ T sb[64 * ST];
-    __shared__ uint32_t spa[PATH ? 64 * ST : 1];  // labels + 1
-    __shared__ uint32_t spb[PATH ? 64 * ST : 1];
+    constexpr int ST = Graph<T, 64, PATH>::ST;
+    __shared__ __attribute__((aligned(16))) T sa[64 * ST];
+    __shared__ __attribute__((aligned(16))) T sb[64 * ST];
+    __shared__ __attribute__((aligned(16))) uint16_t la[PATH ? 64 * ST : 8];  // labels + 1
+    __shared__ __attribute__((aligned(16))) uint16_t lb[PATH ? 64 * ST : 8];
     __shared__ int s_job;
     unsigned long long *counter = (unsigned long long *)jobs;
     for (;;) {
@@ -241,11 +317,11 @@ __global__ void __launch_bounds__(NT) k_batched(T *__restrict__ dist, int32_t *_
         const int n = (int)jobs[2 + 2 * q];
         const bool small = (n <= small_max_n) || (((n + 63) & ~63) != ((n + 31) & ~31));
         if (small) {
-            GraphTiles<T, 32, PATH> g{dist + off, PATH ? path + off : nullptr, n};
-            solve_graph<T, 32, PATH>(g, sa, sb, spa, spb);
+            Graph<T, 32, PATH> g{dist + off, PATH ? path + off : nullptr, n};
+            solve_graph<T, 32, PATH>(g, sa, sb, la, lb);
         } else {
-            GraphTiles<T, 64, PATH> g{dist + off, PATH ? path + off : nullptr, n};
-            solve_graph<T, 64, PATH>(g, sa, sb, spa, spb);
+            Graph<T, 64, PATH> g{dist + off, PATH ? path + off : nullptr, n};
+            solve_graph<T, 64, PATH>(g, sa, sb, la, lb);
         }
     }
 }
