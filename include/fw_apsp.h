@@ -93,17 +93,22 @@ fw_status_t fw_apsp(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, void *s
  *            library, concurrently with the rest of round r's last phase on
  *            the caller's stream, which waits for them before round r + 1.
  *            The call stays stream-ordered on the caller's stream.
- *            FW_SCHED_PAIRS (LDS-panel tiles exactly one block square; otherwise
- *            serial, which includes every FW_F16 configuration): rounds in pairs on the caller's stream; the last phase of
- *            both rounds of a pair is applied to every tile outside their two
- *            blocks in one pass, so those tiles move through memory once per
- *            two rounds.
+ *            FW_SCHED_PAIRS (LDS-panel tiles exactly one block square;
+ *            otherwise serial, which includes every FW_F16 configuration):
+ *            rounds in pairs on the caller's stream; the last phase of both
+ *            rounds of a pair is applied to every tile outside their two blocks
+ *            in one pass, so those tiles move through memory once per two
+ *            rounds.  FW_SCHED_PAIRS_LOOKAHEAD (same tiles, at least 3 rounds;
+ *            otherwise serial): the same pairs, with phases 1-3 of the next
+ *            pair, the tiles they read and the cross launches on an auxiliary
+ *            stream of the library while the caller's stream runs the bulk of
+ *            the current pair; stream-ordered on the caller's stream.
  * Fields set to 0 keep the tuned choice (a table of timings on gfx950 per
  * element type, path mode and size range).  The resulting combination must be
  * one the library compiles (fw_apsp_config returns FW_EUNSUPPORTED otherwise).
  */
 enum { FW_P4_PANELS = 1, FW_P4_WAVEROWS = 2 };
-enum { FW_SCHED_SERIAL = 1, FW_SCHED_LOOKAHEAD = 2, FW_SCHED_PAIRS = 3 };
+enum { FW_SCHED_SERIAL = 1, FW_SCHED_LOOKAHEAD = 2, FW_SCHED_PAIRS = 3, FW_SCHED_PAIRS_LOOKAHEAD = 4 };
 typedef struct {
     int32_t block;
     int32_t tile_m;

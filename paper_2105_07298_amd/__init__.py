@@ -9,11 +9,11 @@ PyTorch provides device memory and streams only; no step of the method runs in i
 from __future__ import annotations
 
 from ._lib import (FW_EHIP, FW_EINVAL, FW_ENOMEM, FW_EUNSUPPORTED, FW_F16, FW_F32, FW_F64, FW_OK,  # noqa: F401
-                   FW_P4_PANELS, FW_P4_WAVEROWS, FW_SCHED_LOOKAHEAD, FW_SCHED_PAIRS, FW_SCHED_SERIAL, FwError, fw_apsp, fw_apsp_backward, fw_apsp_batched,
+                   FW_P4_PANELS, FW_P4_WAVEROWS, FW_SCHED_LOOKAHEAD, FW_SCHED_PAIRS, FW_SCHED_PAIRS_LOOKAHEAD, FW_SCHED_SERIAL, FwError, fw_apsp, fw_apsp_backward, fw_apsp_batched,
                    fw_apsp_batched_config, fw_apsp_config, fw_apsp_ooc, fw_last_error, fw_list_configs, fw_ooc_superblock,
                    fw_prof_enable,
                    fw_prof_read, fw_query_config, fw_status_string, fw_version, lib, lookahead_applies,
-                   pairs_applies)
+                   pairs_applies, pairs_lookahead_applies)
 
 
 def _dtype_code(t):
@@ -43,7 +43,7 @@ def apsp_(D, P=None, block: int = 0, tile_m: int = 0, tile_n: int = 0, variant: 
     Runs on the current stream of D's device.  block / tile_m / tile_n / variant /
     schedule override the tuned configuration (0 = tuned; variant FW_P4_PANELS or
     FW_P4_WAVEROWS picks the last-phase kernel, schedule FW_SCHED_SERIAL,
-    FW_SCHED_LOOKAHEAD or FW_SCHED_PAIRS the round schedule).
+    FW_SCHED_LOOKAHEAD, FW_SCHED_PAIRS or FW_SCHED_PAIRS_LOOKAHEAD the round schedule).
     """
     import torch
     if not (D.is_cuda and D.dim() == 2 and D.shape[0] == D.shape[1] and D.is_contiguous()):

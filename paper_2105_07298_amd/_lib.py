@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libfwapsp.so")
 FW_F32, FW_F64, FW_F16 = 0, 1, 2
 FW_OK, FW_EINVAL, FW_ENOMEM, FW_EHIP, FW_EUNSUPPORTED = 0, -1, -2, -3, -4
 FW_P4_PANELS, FW_P4_WAVEROWS = 1, 2
-FW_SCHED_SERIAL, FW_SCHED_LOOKAHEAD, FW_SCHED_PAIRS = 1, 2, 3
+FW_SCHED_SERIAL, FW_SCHED_LOOKAHEAD, FW_SCHED_PAIRS, FW_SCHED_PAIRS_LOOKAHEAD = 1, 2, 3, 4
 
 EXPORTS = ("fw_apsp", "fw_apsp_config", "fw_query_config", "fw_list_configs", "fw_apsp_ooc", "fw_ooc_superblock",
            "fw_apsp_batched", "fw_apsp_batched_config",
@@ -178,3 +178,11 @@ def pairs_applies(block: int, tile_m: int, tile_n: int, variant: int, n: int) ->
     unit = max(block, tile_m, tile_n)
     npad = -(-n // unit) * unit
     return variant == FW_P4_PANELS and tile_m == block and tile_n == block and npad // block >= 2
+
+
+def pairs_lookahead_applies(block: int, tile_m: int, tile_n: int, variant: int, n: int) -> bool:
+    """Whether FW_SCHED_PAIRS_LOOKAHEAD changes anything (else it runs serially): the
+    pairs tiles and at least 3 rounds after padding."""
+    unit = max(block, tile_m, tile_n)
+    npad = -(-n // unit) * unit
+    return pairs_applies(block, tile_m, tile_n, variant, n) and npad // block >= 3

@@ -3,16 +3,20 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fw_tiles.h"
+
 namespace fw {
 
 // Last-phase kernels: both operand panels in LDS, or one column-panel row per
 // wave in scalar registers and the row panel in LDS.
 constexpr int FW_VARIANT_PANELS = 1;
 constexpr int FW_VARIANT_WAVEROWS = 2;
-// Round schedules: one stream, or lookahead on an auxiliary stream.
+// Round schedules: one stream, lookahead on an auxiliary stream, rounds in
+// pairs, or rounds in pairs with lookahead (fw_plan.h).
 constexpr int FW_SCHEDULE_SERIAL = 1;
 constexpr int FW_SCHEDULE_LOOKAHEAD = 2;
 constexpr int FW_SCHEDULE_PAIRS = 3;
+constexpr int FW_SCHEDULE_PAIRS_LOOKAHEAD = 4;
 
 // Round depth (the paper's TB), last-phase output tile (rows x columns),
 // last-phase kernel and round schedule.
@@ -34,18 +38,10 @@ struct TileCfg {
 template <typename T>
 hipError_t launch_phase123(T *D, int32_t *P, uint16_t *L, int64_t ld, int r, int block, hipStream_t s);
 
-// Phase 4 of round r over a selection of its tiles:
-//   all        every tile outside block row and column r;
-//   cross      the tiles of block row and column r + 1 (outside block row and
-//              column r): what phases 1-3 of round r + 1 read and write;
-//   rest       every tile outside block rows and columns r and r + 1;
-//   crossprev  the tiles of block row and column r - 1 outside block row and
-//              column r (round r applied to the block before it);
-//   pair       rounds r and r + 1 in one pass over the rest tiles (both
-//              rounds' panels final; pairs_supported(cfg)).
+// Phase 4 of round r over a selection of its tiles (P4Mode, in fw_tiles.h).
 // cross, rest, crossprev and pair need lookahead_supported(cfg) and a next
-// round (crossprev: r >= 1).
-enum class P4Mode { all, cross, rest, crossprev, pair };
+// round (crossprev: r >= 1); the pair and *_band / *_rest modes need
+// pairs_supported(cfg).
 template <typename T>
 hipError_t launch_phase4(T *D, uint16_t *L, bool path, int64_t ld, int r, TileCfg cfg, P4Mode mode, hipStream_t s);
 

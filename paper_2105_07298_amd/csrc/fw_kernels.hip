@@ -31,9 +31,10 @@
 //
 // All arithmetic is on the vector ALU: the min-plus product is not a ring
 // contraction, so matrix cores do not apply.
-#include "fw_internal.h"
+// The tile selections run on the device too (defined before fw_internal.h
+// includes them).
 #define FW_TILE_FN __host__ __device__ __forceinline__
-#include "fw_tiles.h"
+#include "fw_internal.h"
 #include "fw_lex.h"
 
 #include <limits.h>
@@ -292,7 +293,7 @@ constexpr int p4_kchunk(int TB, int BM, int BN) {
 // marked pending (L = r + 1) and resolved by k_resolve.  Each such mark is
 // written on its own (a 2-byte store under the entry's own condition), so this
 // phase never reads L.
-template <typename T, int TB, int BM, int BN, bool PATH, bool CROSS, bool FUSE = false>
+template <typename T, int TB, int BM, int BN, bool PATH, bool BAND, bool FUSE = false>
 __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__restrict__ L, int64_t ld, int r,
                                               TileSel sel) {
     constexpr int RM = BM / 16, RN = BN / 16;  // 16 x 16 threads
@@ -316,7 +317,7 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
     __shared__ __attribute__((aligned(16))) T Bs[KC * BN];
 
     int bi, bj;
-    if (!select_tile<CROSS>(sel, blockIdx.x, bi, bj)) return;
+    if (!select_tile<BAND>(sel, blockIdx.x, bi, bj)) return;
     const int64_t I0 = (int64_t)bi * BM, J0 = (int64_t)bj * BN, k0 = (int64_t)r * TB;
 
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
@@ -497,7 +498,7 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
 // it, 4 / RM bytes of LDS traffic per update for float (k_phase4's 4 x 4
 // register tiles need 2 bytes, which is all the LDS delivers at the VALU's
 // update rate).
-template <typename T, int TB, int RM, int RN, bool PATH, bool CROSS>
+template <typename T, int TB, int RM, int RN, bool PATH, bool BAND>
 __global__ void __launch_bounds__(NT) k_phase4w(T *__restrict__ D, uint16_t *__restrict__ L, int64_t ld, int r,
                                                TileSel sel) {
     constexpr int BM = (NT / 64) * RM, BN = 64 * RN;
@@ -510,7 +511,7 @@ __global__ void __launch_bounds__(NT) k_phase4w(T *__restrict__ D, uint16_t *__r
     __shared__ __attribute__((aligned(16))) T Bs[TB * BN];
 
     int bi, bj;
-    if (!select_tile<CROSS>(sel, blockIdx.x, bi, bj)) return;
+    if (!select_tile<BAND>(sel, blockIdx.x, bi, bj)) return;
     const int64_t I0 = (int64_t)bi * BM, J0 = (int64_t)bj * BN, k0 = (int64_t)r * TB;
     const bool mask_cols = sel.nsc == 0 && (J0 <= k0) && (k0 < J0 + BN);
 
@@ -894,66 +895,64 @@ void launch_p123(T *D, int32_t *P, uint16_t *L, int64_t ld, int r, hipStream_t s
         hipLaunchKernelGGL((k_phase23<T, TB, false>), dim3(2 * (nb - 1)), dim3(NT), 0, s, D, P, L, ld, r, nb);
 }
 
-// One last-phase launch (mode all / cross / rest / crossprev / pair, see
+// One last-phase launch (any P4Mode, see
 // P4Mode) with the LDS-panel kernel (WAVE = false) or the wave-row kernel
 // (BM = 4 * RM).  r is the round applied (the first of the two for a pair).
 template <typename T, int TB, int BM, int BN, bool WAVE>
 hipError_t p4_impl(T *D, uint16_t *L, bool path, int64_t ld, int r, P4Mode mode, hipStream_t s) {
     const int rb = BM <= TB ? TB / BM : 0;  // tile rows per block; 0: the block row is masked
     const int cb = BN == TB ? 1 : 0;        // likewise for columns
-    int sel_mode = 0, sel_r = r;
-    switch (mode) {
-    case P4Mode::all: sel_mode = 0; break;
-    case P4Mode::cross: sel_mode = 1; break;
-    case P4Mode::rest: sel_mode = 2; break;
-    case P4Mode::crossprev: sel_mode = 3; sel_r = r - 1; break;  // block r - 1, skipping block r
-    case P4Mode::pair: sel_mode = 2; break;                      // the rest of rounds r and r + 1
-    }
-    if (sel_r < 0) return hipErrorInvalidValue;
-    if (mode == P4Mode::pair && (WAVE || r + 2 > (int)(ld / TB))) return hipErrorInvalidValue;
+    const int nb = (int)(ld / TB);
     TileSel sel;
-    if (!make_tile_sel((int)(ld / BM), (int)(ld / BN), rb, cb, sel_r, (int)(ld / TB), sel_mode, sel))
-        return hipErrorInvalidValue;
+    bool band = false, fuse = false;
+    if (!p4_select((int)(ld / BM), (int)(ld / BN), rb, cb, r, nb, mode, sel, band, fuse)) return hipErrorInvalidValue;
+    if (fuse && (WAVE || BM != TB || BN != TB)) return hipErrorInvalidValue;
     if (sel.ntiles == 0) return hipSuccess;
-    const bool cross = mode == P4Mode::cross || mode == P4Mode::crossprev;
-    int64_t upd = 0;  // algorithmic min-plus updates of the bulk launches (timed)
+    // Algorithmic min-plus updates of the bulk launches (timed by the profiling
+    // hooks): every tile outside the skipped blocks, times the rounds applied.
+    int64_t upd = 0;
     if (mode == P4Mode::all) upd = (ld - TB) * (ld - TB) * TB;
     if (mode == P4Mode::rest) upd = (ld - 2 * TB) * (ld - 2 * TB) * TB;
     if (mode == P4Mode::pair) upd = 2 * (ld - 2 * TB) * (ld - 2 * TB) * TB;
+    if (mode == P4Mode::pair_rest) {
+        const int64_t w = nb - r < 4 ? nb - r : 4;
+        upd = 2 * (ld - w * TB) * (ld - w * TB) * TB;
+    }
     const dim3 grid(8 * sel.per_xcd);
     constexpr int RM = BM / (NT / 64), RN = BN / 64;
-#define FW_P4_LAUNCH(PATHV, CROSSV, FUSEV)                                                                          \
+#define FW_P4_LAUNCH(PATHV, BANDV, FUSEV)                                                                           \
     do {                                                                                                         \
         if constexpr (WAVE) {                                                                                    \
             if constexpr (!FUSEV)                                                                                \
-                hipLaunchKernelGGL((k_phase4w<T, TB, RM, RN, PATHV, CROSSV>), grid, dim3(NT), 0, s, D, L, ld, r,   \
+                hipLaunchKernelGGL((k_phase4w<T, TB, RM, RN, PATHV, BANDV>), grid, dim3(NT), 0, s, D, L, ld, r,    \
                                    sel);                                                                         \
-        } else {                                                                                                 \
-            hipLaunchKernelGGL((k_phase4<T, TB, BM, BN, PATHV, CROSSV, FUSEV>), grid, dim3(NT), 0, s, D, L, ld, r, \
+        } else if constexpr (!FUSEV || (BM == TB && BN == TB)) {                                                 \
+            hipLaunchKernelGGL((k_phase4<T, TB, BM, BN, PATHV, BANDV, FUSEV>), grid, dim3(NT), 0, s, D, L, ld, r,  \
                                sel);                                                                             \
         }                                                                                                        \
     } while (0)
-    if (cross) {
-        if (path)
+    const bool timed = upd > 0;
+    if (timed) prof_begin_p4(s);
+    if (path) {
+        if (band && fuse)
+            FW_P4_LAUNCH(true, true, true);
+        else if (band)
             FW_P4_LAUNCH(true, true, false);
+        else if (fuse)
+            FW_P4_LAUNCH(true, false, true);
         else
-            FW_P4_LAUNCH(false, true, false);
-    } else {
-        prof_begin_p4(s);
-        if (mode == P4Mode::pair) {
-            if constexpr (!WAVE && BM == TB && BN == TB) {
-                if (path)
-                    FW_P4_LAUNCH(true, false, true);
-                else
-                    FW_P4_LAUNCH(false, false, true);
-            }
-        } else if (path) {
             FW_P4_LAUNCH(true, false, false);
-        } else {
+    } else {
+        if (band && fuse)
+            FW_P4_LAUNCH(false, true, true);
+        else if (band)
+            FW_P4_LAUNCH(false, true, false);
+        else if (fuse)
+            FW_P4_LAUNCH(false, false, true);
+        else
             FW_P4_LAUNCH(false, false, false);
-        }
-        prof_end_p4(s, upd);
     }
+    if (timed) prof_end_p4(s, upd);
 #undef FW_P4_LAUNCH
     return hipGetLastError();
 }

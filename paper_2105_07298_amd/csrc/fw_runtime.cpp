@@ -14,6 +14,7 @@
 
 #include "../../include/fw_apsp.h"
 #include "fw_internal.h"
+#include "fw_plan.h"
 
 static_assert(fw::FW_VARIANT_PANELS == FW_P4_PANELS && fw::FW_VARIANT_WAVEROWS == FW_P4_WAVEROWS,
               "variant codes of the C ABI");
@@ -98,7 +99,9 @@ bool supported_for(fw_dtype_t dt, fw::TileCfg c) {
 struct Aux {
     int dev;
     hipStream_t st;
-    hipEvent_t rest_done[2], p23_done[2], start;
+    // The lookahead schedule uses ev[0..1] (rest done), ev[2..3] (phases 2+3
+    // done) and ev[6] (start); the pairs-with-lookahead plan all seven (fw_plan.h).
+    hipEvent_t ev[fw::kPlanEvents];
     bool busy;
 };
 std::mutex g_aux_mu;
@@ -111,13 +114,12 @@ Aux *acquire_aux(int dev) {
             a->busy = true;
             return a;
         }
-    Aux *a = new Aux{dev, nullptr, {nullptr, nullptr}, {nullptr, nullptr}, nullptr, true};
+    Aux *a = new Aux{dev, nullptr, {}, true};
     bool ok = hipStreamCreateWithFlags(&a->st, hipStreamNonBlocking) == hipSuccess;
-    hipEvent_t *evs[5] = {&a->rest_done[0], &a->rest_done[1], &a->p23_done[0], &a->p23_done[1], &a->start};
-    for (hipEvent_t *e : evs) ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+    for (hipEvent_t &e : a->ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
-        for (hipEvent_t *e : evs)
-            if (*e) (void)hipEventDestroy(*e);
+        for (hipEvent_t &e : a->ev)
+            if (e) (void)hipEventDestroy(e);
         if (a->st) (void)hipStreamDestroy(a->st);
         delete a;
         return nullptr;
@@ -157,6 +159,23 @@ hipError_t run_rounds(T *D, int32_t *P, uint16_t *L, int64_t ld, fw::TileCfg cfg
         }
         return hipSuccess;
     }
+    if (cfg.schedule == fw::FW_SCHEDULE_PAIRS_LOOKAHEAD && R >= kLookaheadMinRounds && fw::pairs_supported(cfg) &&
+        hipGetDevice(&dev) == hipSuccess && (aux = acquire_aux(dev)) != nullptr) {
+        // The plan of fw_plan.h, enqueued op by op (stream 1 = the auxiliary stream).
+        hipError_t err = hipSuccess;
+        fw::plan_pairs_lookahead(R, [&](const fw::PlanOp &op) {
+            if (err != hipSuccess) return;
+            hipStream_t st = op.stream ? aux->st : s;
+            switch (op.kind) {
+            case fw::PlanKind::p123: err = fw::launch_phase123<T>(D, P, L, ld, op.r, cfg.block, st); break;
+            case fw::PlanKind::p4: err = fw::launch_phase4<T>(D, L, path, ld, op.r, cfg, op.mode, st); break;
+            case fw::PlanKind::record: err = hipEventRecord(aux->ev[op.ev], st); break;
+            case fw::PlanKind::wait: err = hipStreamWaitEvent(st, aux->ev[op.ev], 0); break;
+            }
+        });
+        release_aux(aux);
+        return err;
+    }
     if (cfg.schedule == fw::FW_SCHEDULE_LOOKAHEAD && R >= kLookaheadMinRounds && fw::lookahead_supported(cfg) &&
         hipGetDevice(&dev) == hipSuccess)
         aux = acquire_aux(dev);
@@ -170,23 +189,23 @@ hipError_t run_rounds(T *D, int32_t *P, uint16_t *L, int64_t ld, fw::TileCfg cfg
     hipStream_t a = aux->st;
     auto body = [&]() -> hipError_t {
         hipError_t e;
-        if ((e = hipEventRecord(aux->start, s)) != hipSuccess) return e;  // after the caller's earlier work
-        if ((e = hipStreamWaitEvent(a, aux->start, 0)) != hipSuccess) return e;
+        if ((e = hipEventRecord(aux->ev[fw::kEvStart], s)) != hipSuccess) return e;  // after the caller's earlier work
+        if ((e = hipStreamWaitEvent(a, aux->ev[fw::kEvStart], 0)) != hipSuccess) return e;
         if ((e = fw::launch_phase123<T>(D, P, L, ld, 0, cfg.block, a)) != hipSuccess) return e;
-        if ((e = hipEventRecord(aux->p23_done[0], a)) != hipSuccess) return e;
+        if ((e = hipEventRecord(aux->ev[2], a)) != hipSuccess) return e;
         for (int r = 0; r + 1 < R; ++r) {
             // main stream: the bulk of round r
-            if ((e = hipStreamWaitEvent(s, aux->p23_done[r & 1], 0)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(s, aux->ev[2 + (r & 1)], 0)) != hipSuccess) return e;
             if ((e = fw::launch_phase4<T>(D, L, path, ld, r, cfg, P4Mode::rest, s)) != hipSuccess) return e;
-            if ((e = hipEventRecord(aux->rest_done[r & 1], s)) != hipSuccess) return e;
+            if ((e = hipEventRecord(aux->ev[r & 1], s)) != hipSuccess) return e;
             // auxiliary stream: block row / column r + 1, then phases 1-3 of round r + 1
-            if (r > 0 && (e = hipStreamWaitEvent(a, aux->rest_done[(r - 1) & 1], 0)) != hipSuccess) return e;
+            if (r > 0 && (e = hipStreamWaitEvent(a, aux->ev[(r - 1) & 1], 0)) != hipSuccess) return e;
             if ((e = fw::launch_phase4<T>(D, L, path, ld, r, cfg, P4Mode::cross, a)) != hipSuccess) return e;
             if ((e = fw::launch_phase123<T>(D, P, L, ld, r + 1, cfg.block, a)) != hipSuccess) return e;
-            if ((e = hipEventRecord(aux->p23_done[(r + 1) & 1], a)) != hipSuccess) return e;
+            if ((e = hipEventRecord(aux->ev[2 + ((r + 1) & 1)], a)) != hipSuccess) return e;
         }
         // last round: one launch on the main stream, after everything on the auxiliary one
-        if ((e = hipStreamWaitEvent(s, aux->p23_done[(R - 1) & 1], 0)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(s, aux->ev[2 + ((R - 1) & 1)], 0)) != hipSuccess) return e;
         return fw::launch_phase4<T>(D, L, path, ld, R - 1, cfg, P4Mode::all, s);
     };
     e = body();
@@ -301,9 +320,9 @@ fw_status_t fw_apsp_config(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, 
     fw::TileCfg tc = default_cfg(dt, n, path != nullptr);
     if (cfg) {
         if (cfg->block < 0 || cfg->tile_m < 0 || cfg->tile_n < 0 || cfg->variant < 0 ||
-            cfg->variant > FW_P4_WAVEROWS || cfg->schedule < 0 || cfg->schedule > FW_SCHED_PAIRS)
+            cfg->variant > FW_P4_WAVEROWS || cfg->schedule < 0 || cfg->schedule > FW_SCHED_PAIRS_LOOKAHEAD)
             return fail(FW_EINVAL, "config fields must be 0 (tuned) or positive, variant at most %d, schedule at most %d",
-                        FW_P4_WAVEROWS, FW_SCHED_PAIRS);
+                        FW_P4_WAVEROWS, FW_SCHED_PAIRS_LOOKAHEAD);
         if (cfg->block) tc.block = cfg->block;
         if (cfg->tile_m) tc.tile_m = cfg->tile_m;
         if (cfg->tile_n) tc.tile_n = cfg->tile_n;

@@ -60,9 +60,10 @@ def tune_apsp(fw, torch, log, dtypes=("f32", "f64", "f16")):
                 P = torch.empty((n, n), dtype=torch.int32, device=W.device) if path else None
                 best = None
                 cands = [(b, tm, tn, var, sch) for b, tm, tn, var in fw.fw_list_configs(codes[dt])
-                    for sch in (fw.FW_SCHED_SERIAL, fw.FW_SCHED_LOOKAHEAD, fw.FW_SCHED_PAIRS)
+                    for sch in (fw.FW_SCHED_SERIAL, fw.FW_SCHED_LOOKAHEAD, fw.FW_SCHED_PAIRS, fw.FW_SCHED_PAIRS_LOOKAHEAD)
                     if sch == fw.FW_SCHED_SERIAL or (sch == fw.FW_SCHED_LOOKAHEAD and fw.lookahead_applies(b, tm, tn, n))
-                    or (sch == fw.FW_SCHED_PAIRS and fw.pairs_applies(b, tm, tn, var, n))]
+                    or (sch == fw.FW_SCHED_PAIRS and fw.pairs_applies(b, tm, tn, var, n))
+                    or (sch == fw.FW_SCHED_PAIRS_LOOKAHEAD and fw.pairs_lookahead_applies(b, tm, tn, var, n))]
                 for block, tm, tn, var, sch in cands:
                     def run():
                         D.copy_(W)

@@ -67,7 +67,7 @@ def test_invalid_config(fw):
         cfg = fw._lib.FwConfig(*bad)
         assert L.fw_apsp_config(0, 128, 4096, None, ctypes.byref(cfg), None) == fw.FW_EUNSUPPORTED, bad
         assert "not compiled in" in fw.fw_last_error()
-    for bad in ((64, 64, 64, 3), (-1, 64, 64, 1), (64, 64, -64, 0), (64, 64, 64, 1, 4), (64, 64, 64, 1, -1)):
+    for bad in ((64, 64, 64, 3), (-1, 64, 64, 1), (64, 64, -64, 0), (64, 64, 64, 1, 5), (64, 64, 64, 1, -1)):
         cfg = fw._lib.FwConfig(*bad)
         assert L.fw_apsp_config(0, 128, 4096, None, ctypes.byref(cfg), None) == fw.FW_EINVAL, bad
 
@@ -123,7 +123,8 @@ def test_query_config(fw):
         for n in (1, 100, 1000, 5000, 16384, 65536):
             for path in (False, True):
                 q = fw.fw_query_config(dt, n, path)
-                assert q[:4] in compiled and q[4] in (fw.FW_SCHED_SERIAL, fw.FW_SCHED_LOOKAHEAD, fw.FW_SCHED_PAIRS)
+                assert q[:4] in compiled and q[4] in (fw.FW_SCHED_SERIAL, fw.FW_SCHED_LOOKAHEAD, fw.FW_SCHED_PAIRS,
+                                                                    fw.FW_SCHED_PAIRS_LOOKAHEAD)
 
 
 @pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="a GPU is present: would launch on a bogus pointer")

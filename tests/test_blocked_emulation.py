@@ -136,7 +136,7 @@ def test_model_real_weights_tolerance():
     oracle.check_invariants(W, Dm, Pm, exact=False, rtol=1e-12)
 
 
-def blocked_model_deferred(W, TB, schedule="serial"):
+def blocked_model_deferred(W, TB, schedule="serial", ops=None):
     """The GPU's path-mode schedule: phases 1-3 apply the lexicographic rule to P
     (which holds an older label while an entry is pending) and clear the entry's
     mark L when they change it; the last phase only marks strict improvements
@@ -149,7 +149,10 @@ def blocked_model_deferred(W, TB, schedule="serial"):
     r + 1, then both rounds' last phase in one pass over the tiles outside blocks
     r and r + 1 (round r's minimum kept apart, the mark naming the last round in
     which the entry decreased), and only then round r + 1's last phase on block
-    row / column r."""
+    row / column r.
+
+    schedule "ops" runs an explicit operation list instead, in order: ("p123", r),
+    ("p4", r, fused, tiles) with tiles a list of (block row, block column)."""
     n = W.shape[0]
     npad = -(-n // TB) * TB
     D = np.full((npad, npad), np.inf)
@@ -208,7 +211,15 @@ def blocked_model_deferred(W, TB, schedule="serial"):
     def outside(*bs):
         return [(bi, bj) for bi in range(R) for bj in range(R) if bi not in bs and bj not in bs]
 
-    if schedule == "serial":
+    if schedule == "ops":
+        for op in ops:
+            if op[0] == "p123":
+                phases123(op[1])
+            elif op[2]:
+                fused_pair(op[1], op[3])
+            else:
+                last_phase(op[1], op[3])
+    elif schedule == "serial":
         for r in range(R):
             phases123(r)
             last_phase(r, outside(r))

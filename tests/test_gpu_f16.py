@@ -34,6 +34,8 @@ def f16_configs(n):
             out.append((b, tm, tn, var, fw.FW_SCHED_LOOKAHEAD))
         if fw.pairs_applies(b, tm, tn, var, n):
             out.append((b, tm, tn, var, fw.FW_SCHED_PAIRS))
+        if fw.pairs_lookahead_applies(b, tm, tn, var, n):
+            out.append((b, tm, tn, var, fw.FW_SCHED_PAIRS_LOOKAHEAD))
     return out
 
 

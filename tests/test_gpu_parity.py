@@ -27,6 +27,8 @@ def compiled_configs(dtype, n):
             out.append((b, tm, tn, var, fw.FW_SCHED_LOOKAHEAD))
         if fw.pairs_applies(b, tm, tn, var, n):
             out.append((b, tm, tn, var, fw.FW_SCHED_PAIRS))
+        if fw.pairs_lookahead_applies(b, tm, tn, var, n):
+            out.append((b, tm, tn, var, fw.FW_SCHED_PAIRS_LOOKAHEAD))
     return out
 
 
@@ -229,17 +231,17 @@ def test_c2_16384_dijkstra_rows(dev, dtype, tol):
 
 def test_lookahead_16384_matches_serial(dev):
     """n = 16384 float32 with the path matrix, 64 x 64 tiles: the lookahead (two
-    streams) and pairs (two rounds fused) schedules give bit for bit the serial
-    schedule's D and P, and the sampled rows match the float64 Dijkstra oracle
-    within the float32 tolerance."""
+    streams), pairs (two rounds fused) and pairs-with-lookahead schedules give bit
+    for bit the serial schedule's D and P, and the sampled rows match the float64
+    Dijkstra oracle within the float32 tolerance."""
     import paper_2105_07298_amd as fw
     n = 16384
     W = workloads.unit_complete(n, dtype=np.float32, seed=2)
     res = {}
-    for sch in (fw.FW_SCHED_SERIAL, fw.FW_SCHED_LOOKAHEAD, fw.FW_SCHED_PAIRS):
+    for sch in (fw.FW_SCHED_SERIAL, fw.FW_SCHED_LOOKAHEAD, fw.FW_SCHED_PAIRS, fw.FW_SCHED_PAIRS_LOOKAHEAD):
         res[sch] = run_gpu(W, dev, block=64, tile=(64, 64), variant=fw.FW_P4_PANELS, schedule=sch,
                            case="schedules")
-    for sch in (2, 3):
+    for sch in (2, 3, 4):
         np.testing.assert_array_equal(res[1][0], res[sch][0])
         np.testing.assert_array_equal(res[1][1], res[sch][1])
     srcs = workloads.sample_sources(n, 16)

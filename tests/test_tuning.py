@@ -35,7 +35,8 @@ def test_apsp_table_covers_every_size_once():
                 assert a[3] == b[2], "size ranges must tile [0, inf)"
             for r in rs:
                 assert (r[4], r[5], r[6], r[7]) in supported[dt], r
-                assert r[8] in (fw.FW_SCHED_SERIAL, fw.FW_SCHED_LOOKAHEAD, fw.FW_SCHED_PAIRS), r
+                assert r[8] in (fw.FW_SCHED_SERIAL, fw.FW_SCHED_LOOKAHEAD, fw.FW_SCHED_PAIRS,
+                                fw.FW_SCHED_PAIRS_LOOKAHEAD), r
 
 
 def test_batched_table_complete():
