@@ -70,13 +70,6 @@ __device__ __forceinline__ float vmin(float a, float b) { return __builtin_fminf
 __device__ __forceinline__ double vmin(double a, double b) { return __builtin_fmin(a, b); }
 __device__ __forceinline__ _Float16 vmin(_Float16 a, _Float16 b) { return __builtin_elementwise_min(a, b); }
 
-// Lexicographic label update: take (s, m) when it is smaller than (d, p).
-template <typename T>
-__device__ __forceinline__ void lex_take(T &d, int32_t &p, T s, int32_t m) {
-    const bool take = (s < d) || (s == d && m < p);
-    d = take ? s : d;
-    p = take ? m : p;
-}
 
 
 // ---------------------------------------------------------------------------
@@ -680,41 +673,41 @@ __global__ void __launch_bounds__(NT) k_minplus_lex(T *__restrict__ C, int32_t *
                                                    int64_t K, int32_t kbase, TileSel sel) {
     constexpr int TS = 16, RM = 4, BM = 64, BN = 64, STA = KT + 1, STB = BN + 1;
     __shared__ T sa[BM * STA];
-    __shared__ int32_t spa[BM * STA];
+    __shared__ uint32_t spa[BM * STA];  // labels + 1, as in phases 1-3
     __shared__ T sb[KT * STB];
-    __shared__ int32_t spb[KT * STB];
+    __shared__ uint32_t spb[KT * STB];
     int bi, bj;
     if (!select_tile<false>(sel, blockIdx.x, bi, bj)) return;
     const int64_t I0 = (int64_t)bi * BM, J0 = (int64_t)bj * BN;
     const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
     T d[RM][RM], d0[RM][RM];
-    int32_t p[RM][RM], p0[RM][RM];
+    uint32_t p[RM][RM], p0[RM][RM];
 #pragma unroll
     for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
         for (int jj = 0; jj < RM; ++jj) {
             const int64_t g = (I0 + ty + TS * ii) * ldc + J0 + tx + TS * jj;
-            d[ii][jj] = d0[ii][jj] = C[g];
-            p[ii][jj] = p0[ii][jj] = PC[g];
+            d[ii][jj] = d0[ii][jj] = canon(C[g]);
+            p[ii][jj] = p0[ii][jj] = (uint32_t)(PC[g] + 1);
         }
     for (int64_t k0 = 0; k0 < K; k0 += KT) {
         __syncthreads();  // the previous chunk is consumed
         for (int q = threadIdx.x; q < BM * KT; q += NT) {
             const int row = q / KT, kk = q % KT;
             const int64_t g = (I0 + row) * lda + k0 + kk;
-            sa[row * STA + kk] = A[g];
-            spa[row * STA + kk] = PA[g];
+            sa[row * STA + kk] = canon(A[g]);
+            spa[row * STA + kk] = (uint32_t)(PA[g] + 1);
         }
         for (int q = threadIdx.x; q < KT * BN; q += NT) {
             const int kr = q / BN, c = q % BN;
             const int64_t g = (k0 + kr) * ldb + J0 + c;
-            sb[kr * STB + c] = B[g];
-            spb[kr * STB + c] = PB[g];
+            sb[kr * STB + c] = canon(B[g]);
+            spb[kr * STB + c] = (uint32_t)(PB[g] + 1);
         }
         __syncthreads();
         for (int kk = 0; kk < KT; ++kk) {
             T a[RM], b[RM];
-            int32_t pa[RM], pb[RM];
+            uint32_t pa[RM], pb[RM];
 #pragma unroll
             for (int ii = 0; ii < RM; ++ii) {
                 a[ii] = sa[(ty + TS * ii) * STA + kk];
@@ -725,12 +718,13 @@ __global__ void __launch_bounds__(NT) k_minplus_lex(T *__restrict__ C, int32_t *
                 b[jj] = sb[kk * STB + tx + TS * jj];
                 pb[jj] = spb[kk * STB + tx + TS * jj];
             }
-            const int32_t kg = kbase + (int32_t)(k0 + kk);
+            const uint32_t kg1 = (uint32_t)(kbase + k0 + kk + 1);
 #pragma unroll
-            for (int ii = 0; ii < RM; ++ii)
+            for (int ii = 0; ii < RM; ++ii) {
+                const uint32_t mi = max(pa[ii], kg1);
 #pragma unroll
-                for (int jj = 0; jj < RM; ++jj)
-                    lex_take(d[ii][jj], p[ii][jj], a[ii] + b[jj], max(max(pa[ii], pb[jj]), kg));
+                for (int jj = 0; jj < RM; ++jj) lex_take_u(d[ii][jj], p[ii][jj], a[ii] + b[jj], max(mi, pb[jj]));
+            }
         }
     }
 #pragma unroll
@@ -740,7 +734,7 @@ __global__ void __launch_bounds__(NT) k_minplus_lex(T *__restrict__ C, int32_t *
             if (d[ii][jj] == d0[ii][jj] && p[ii][jj] == p0[ii][jj]) continue;
             const int64_t g = (I0 + ty + TS * ii) * ldc + J0 + tx + TS * jj;
             C[g] = d[ii][jj];
-            PC[g] = p[ii][jj];
+            PC[g] = (int32_t)p[ii][jj] - 1;
         }
 }
 
