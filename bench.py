@@ -308,8 +308,9 @@ def roofline(n, dtype, stats, path=True):
             "frac": round(achieved / peak, 4), "traffic": traffic,
             "kernel": ("k_phase4w (wave-row min-plus tile update)" if stats["variant"] == 2
                        else "k_phase4 (LDS-panel min-plus tile update"
-                       + (", fused pair of rounds)" if stats["schedule"] == 3 else ")")),
-            "schedule": {1: "serial", 2: "lookahead", 3: "pairs"}.get(stats["schedule"], stats["schedule"]),
+                       + (", fused pair of rounds)" if stats["schedule"] in (3, 4) else ")")),
+            "schedule": {1: "serial", 2: "lookahead", 3: "pairs", 4: "pairs with lookahead"}.get(stats["schedule"],
+                                                                                              stats["schedule"]),
             "tile": stats["tile"], "block": block, "launches": stats["launches"],
             "mean_launch_ms": round(stats["mean_ms"], 4), "flops_per_launch": 2 * upd}
 
