@@ -19,8 +19,10 @@
 static_assert(fw::FW_VARIANT_PANELS == FW_P4_PANELS && fw::FW_VARIANT_WAVEROWS == FW_P4_WAVEROWS,
               "variant codes of the C ABI");
 static_assert(fw::FW_SCHEDULE_SERIAL == FW_SCHED_SERIAL && fw::FW_SCHEDULE_LOOKAHEAD == FW_SCHED_LOOKAHEAD &&
-                  fw::FW_SCHEDULE_PAIRS == FW_SCHED_PAIRS,
+                  fw::FW_SCHEDULE_PAIRS == FW_SCHED_PAIRS &&
+                  fw::FW_SCHEDULE_PAIRS_LOOKAHEAD == FW_SCHED_PAIRS_LOOKAHEAD,
               "schedule codes of the C ABI");
+static_assert(FW_F32 == 0 && FW_F64 == 1 && FW_F16 == 2, "dtype codes of the tuning table");
 
 namespace {
 
@@ -39,8 +41,10 @@ fw_status_t hip_fail(hipError_t e, const char *what) {
 }
 
 // ---- last-phase timing hooks ------------------------------------------------
-// When enabled, each last-phase launch is bracketed by two events on its
-// stream; fw_prof_read() synchronizes them and returns the count and summed time.
+// When enabled, each bulk last-phase launch (every tile outside the round's
+// block, or the caller-stream part of a pair of rounds) is bracketed by two
+// events on its stream; fw_prof_read() synchronizes them and returns the count,
+// the summed time and the summed algorithmic updates.
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<hipEvent_t> g_ev_pool;
