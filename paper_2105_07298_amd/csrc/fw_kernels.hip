@@ -173,11 +173,15 @@ __global__ void __launch_bounds__(P1_TS *P1_TS) k_phase1(T *__restrict__ D, int3
 template <typename T, int TB, bool PATH>
 __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__restrict__ P, uint16_t *__restrict__ L,
                                                int64_t ld, int r, int nb) {
-    constexpr int TS = 16, RM = TB / TS, ST = TB + 1;
-    __shared__ T sa[TB * ST];
-    __shared__ T sb[TB * ST];
-    __shared__ uint32_t spa[PATH ? TB * ST : 1];  // labels + 1
-    __shared__ uint32_t spb[PATH ? TB * ST : 1];
+    // The operands are staged KC = 32 values of k at a time (33.5 KB of LDS with
+    // labels for TB = 64 instead of 66.6 KB), so that a workgroup of this kernel
+    // fits on a CU beside three of the last phase's when the two run
+    // concurrently (pairs-with-lookahead schedule).
+    constexpr int TS = 16, RM = TB / TS, KC = TB < 32 ? TB : 32, SA = KC + 1, SB = TB + 1;
+    __shared__ T sa[TB * SA];  // A chunk: rows x KC
+    __shared__ T sb[KC * SB];  // B chunk: KC x columns
+    __shared__ uint32_t spa[PATH ? TB * SA : 1];  // labels + 1
+    __shared__ uint32_t spb[PATH ? KC * SB : 1];
     const int w = blockIdx.x;
     const bool rowp = w < nb - 1;
     const int t = rowp ? w : w - (nb - 1);
@@ -185,17 +189,8 @@ __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__re
     const int64_t k0 = (int64_t)r * TB;
     const int64_t I0 = rowp ? k0 : (int64_t)o * TB;
     const int64_t J0 = rowp ? (int64_t)o * TB : k0;
-    for (int q = threadIdx.x; q < TB * TB; q += NT) {
-        const int rr = q / TB, cc = q % TB;
-        const int64_t ga = (I0 + rr) * ld + k0 + cc;  // A = D[I0.., K]
-        const int64_t gb = (k0 + rr) * ld + J0 + cc;  // B = D[K, J0..]
-        sa[rr * ST + cc] = PATH ? canon(D[ga]) : D[ga];
-        sb[rr * ST + cc] = PATH ? canon(D[gb]) : D[gb];
-        if (PATH) {
-            spa[rr * ST + cc] = (uint32_t)(P[ga] + 1);
-            spb[rr * ST + cc] = (uint32_t)(P[gb] + 1);
-        }
-    }
+    // A = D[I0.., K] and B = D[K, J0..]: for a row panel A is the closed diagonal
+    // block and B the old tile, for a column panel the other way round.
     const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
     T d[RM][RM], d0[RM][RM];
     uint32_t p[RM][RM], p0[RM][RM];
@@ -207,31 +202,46 @@ __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__re
             d[ii][jj] = d0[ii][jj] = PATH ? canon(D[g]) : D[g];
             if (PATH) p[ii][jj] = p0[ii][jj] = (uint32_t)(P[g] + 1);
         }
-    __syncthreads();
-    for (int k = 0; k < TB; ++k) {
-        T a[RM], b[RM];
-        uint32_t pa[RM], pb[RM];
-#pragma unroll
-        for (int ii = 0; ii < RM; ++ii) {
-            a[ii] = sa[(ty + TS * ii) * ST + k];
-            if (PATH) pa[ii] = spa[(ty + TS * ii) * ST + k];
+    for (int kc = 0; kc < TB; kc += KC) {
+        if (kc) __syncthreads();  // every thread is done with the previous chunk
+        for (int q = threadIdx.x; q < TB * KC; q += NT) {
+            const int rr = q / KC, cc = q % KC;
+            const int64_t g = (I0 + rr) * ld + k0 + kc + cc;
+            sa[rr * SA + cc] = PATH ? canon(D[g]) : D[g];
+            if (PATH) spa[rr * SA + cc] = (uint32_t)(P[g] + 1);
         }
-#pragma unroll
-        for (int jj = 0; jj < RM; ++jj) {
-            b[jj] = sb[k * ST + tx + TS * jj];
-            if (PATH) pb[jj] = spb[k * ST + tx + TS * jj];
+        for (int q = threadIdx.x; q < KC * TB; q += NT) {
+            const int rr = q / TB, cc = q % TB;
+            const int64_t g = (k0 + kc + rr) * ld + J0 + cc;
+            sb[rr * SB + cc] = PATH ? canon(D[g]) : D[g];
+            if (PATH) spb[rr * SB + cc] = (uint32_t)(P[g] + 1);
         }
-        const uint32_t kg1 = (uint32_t)(k0 + k + 1);
+        __syncthreads();
+        for (int k = 0; k < KC; ++k) {
+            T a[RM], b[RM];
+            uint32_t pa[RM], pb[RM];
 #pragma unroll
-        for (int ii = 0; ii < RM; ++ii)
+            for (int ii = 0; ii < RM; ++ii) {
+                a[ii] = sa[(ty + TS * ii) * SA + k];
+                if (PATH) pa[ii] = spa[(ty + TS * ii) * SA + k];
+            }
 #pragma unroll
             for (int jj = 0; jj < RM; ++jj) {
-                const T s = a[ii] + b[jj];
-                if (PATH)
-                    lex_take_u(d[ii][jj], p[ii][jj], s, max(max(pa[ii], pb[jj]), kg1));
-                else
-                    d[ii][jj] = vmin(d[ii][jj], s);
+                b[jj] = sb[k * SB + tx + TS * jj];
+                if (PATH) pb[jj] = spb[k * SB + tx + TS * jj];
             }
+            const uint32_t kg1 = (uint32_t)(k0 + kc + k + 1);
+#pragma unroll
+            for (int ii = 0; ii < RM; ++ii)
+#pragma unroll
+                for (int jj = 0; jj < RM; ++jj) {
+                    const T s = a[ii] + b[jj];
+                    if (PATH)
+                        lex_take_u(d[ii][jj], p[ii][jj], s, max(max(pa[ii], pb[jj]), kg1));
+                    else
+                        d[ii][jj] = vmin(d[ii][jj], s);
+                }
+        }
     }
 #pragma unroll
     for (int ii = 0; ii < RM; ++ii)
