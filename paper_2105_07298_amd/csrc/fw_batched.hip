@@ -69,20 +69,41 @@ struct Graph {
     __device__ static int col(int tx, int h) { return h * CS + tx * VB; }
 
     // Lengths pass through canon() in path mode (lex_take_u's key needs +0.0);
-    // labels are read as label + 1.
-    // (Indices within one graph are below 4096^2, so 32-bit offsets from the
-    // graph's base pointer suffice.)
-    __device__ T ld_d(int i, int j) const {
-        if (i < n && j < n) return PATH ? canon(D[i * n + j]) : D[i * n + j];
-        return i == j ? (T)0 : inf_b<T>();
+    // labels are read as label + 1.  A guarded load reads the entry clamped into
+    // the graph and then substitutes the padding value, so it has no branch and
+    // all loads of a tile are in flight before the first wait.  (Indices within
+    // one graph are below 4096^2; byte offsets are formed in 32 bits so that the
+    // accesses take the scalar-base + 32-bit vector-offset form.)
+    template <typename U> __device__ static U &elem(U *base, uint32_t idx) {
+        return *(U *)((char *)base + idx * (uint32_t)sizeof(U));
     }
-    __device__ uint32_t ld_p(int i, int j) const { return (i < n && j < n) ? (uint32_t)(P[i * n + j] + 1) : 0u; }
-    // Tile (I0, J0) into LDS, row-major with stride ST (labels likewise).
+    __device__ uint32_t at(int i, int j) const { return (uint32_t)(min(i, n - 1) * n + min(j, n - 1)); }
+    __device__ T ld_d(int i, int j) const {
+        const T v = elem(D, at(i, j));
+        const T pad = i == j ? (T)0 : inf_b<T>();
+        return (i < n && j < n) ? (PATH ? canon(v) : v) : pad;
+    }
+    __device__ uint32_t ld_p(int i, int j) const {
+        const uint32_t v = (uint32_t)(elem(P, at(i, j)) + 1);
+        return (i < n && j < n) ? v : 0u;
+    }
+    // Tile (I0, J0) into LDS, row-major with stride ST (labels likewise): all
+    // global loads first, then the LDS writes.
     __device__ void stage(T *s, uint16_t *l, int I0, int J0) const {
-        for (int q = threadIdx.x; q < TB * TB; q += NT) {
-            const int rr = q / TB, cc = q % TB;
-            s[rr * ST + cc] = ld_d(I0 + rr, J0 + cc);
-            if (PATH) l[rr * ST + cc] = (uint16_t)ld_p(I0 + rr, J0 + cc);
+        constexpr int IT = TB * TB / NT;
+        T v[IT];
+        uint32_t w[PATH ? IT : 1];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int q = (int)threadIdx.x + it * NT, rr = q / TB, cc = q % TB;
+            v[it] = ld_d(I0 + rr, J0 + cc);
+            if (PATH) w[it] = ld_p(I0 + rr, J0 + cc);
+        }
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int q = (int)threadIdx.x + it * NT, rr = q / TB, cc = q % TB;
+            s[rr * ST + cc] = v[it];
+            if (PATH) l[rr * ST + cc] = (uint16_t)w[it];
         }
     }
     // The thread's entries of tile (I0, J0): from global memory ...
@@ -121,8 +142,8 @@ struct Graph {
                 for (int e = 0; e < VB; ++e) {
                     const int i = I0 + row(ty, ii), j = J0 + col(tx, h) + e;
                     if (i < n && j < n) {
-                        D[i * n + j] = d[ii][h * VB + e];
-                        if (PATH) P[i * n + j] = (int32_t)p[ii][h * VB + e] - 1;
+                        elem(D, (uint32_t)(i * n + j)) = d[ii][h * VB + e];
+                        if (PATH) elem(P, (uint32_t)(i * n + j)) = (int32_t)p[ii][h * VB + e] - 1;
                     }
                 }
     }
@@ -310,11 +331,13 @@ __global__ void __launch_bounds__(NT, (batched_wgs_per_cu<T, PATH>())) k_batched
     for (;;) {
         if (threadIdx.x == 0) s_job = (int)atomicAdd(counter, 1ull);
         __syncthreads();
-        const int q = s_job;
+        const int q = __builtin_amdgcn_readfirstlane(s_job);  // uniform: graph bases in scalar registers
         __syncthreads();
         if (q >= njobs) return;
-        const int64_t off = jobs[1 + 2 * q];
-        const int n = (int)jobs[2 + 2 * q];
+        const int64_t off0 = jobs[1 + 2 * q];
+        const int64_t off = ((int64_t)__builtin_amdgcn_readfirstlane((int)(off0 >> 32)) << 32) |
+                            (uint32_t)__builtin_amdgcn_readfirstlane((int)off0);
+        const int n = __builtin_amdgcn_readfirstlane((int)jobs[2 + 2 * q]);
         const bool small = (n <= small_max_n) || (((n + 63) & ~63) != ((n + 31) & ~31));
         if (small) {
             Graph<T, 32, PATH> g{dist + off, PATH ? path + off : nullptr, n};
