@@ -119,6 +119,21 @@ struct Graph {
                     if (PATH) p[ii][h * VB + e] = ld_p(i, j);
                 }
     }
+    // ... lengths only, with label + 1 = 0 (last phase in path mode: every
+    // candidate's label + 1 is above k0 >= 0, so an old label, whatever it is,
+    // wins every tie with the old length exactly as 0 does, and an entry whose
+    // word is still 0 after the product has not changed) ...
+    __device__ void load_d0(T (&d)[RM][RN], uint32_t (&p)[RM][RN], int I0, int J0, int tx, int ty) const {
+#pragma unroll
+        for (int ii = 0; ii < RM; ++ii)
+#pragma unroll
+            for (int h = 0; h < HN; ++h)
+#pragma unroll
+                for (int e = 0; e < VB; ++e) {
+                    d[ii][h * VB + e] = ld_d(I0 + row(ty, ii), J0 + col(tx, h) + e);
+                    p[ii][h * VB + e] = 0u;
+                }
+    }
     // ... or from a staged copy.
     __device__ static void load_lds(T (&d)[RM][RN], uint32_t (&p)[RM][RN], const T *s, const uint16_t *l, int tx,
                                     int ty) {
@@ -144,6 +159,23 @@ struct Graph {
                     if (i < n && j < n) {
                         elem(D, (uint32_t)(i * n + j)) = d[ii][h * VB + e];
                         if (PATH) elem(P, (uint32_t)(i * n + j)) = (int32_t)p[ii][h * VB + e] - 1;
+                    }
+                }
+    }
+
+    // The entries that a last-phase product (from load_d0) decreased.
+    __device__ void store_changed(const T (&d)[RM][RN], const uint32_t (&p)[RM][RN], int I0, int J0, int tx,
+                                  int ty) const {
+#pragma unroll
+        for (int ii = 0; ii < RM; ++ii)
+#pragma unroll
+            for (int h = 0; h < HN; ++h)
+#pragma unroll
+                for (int e = 0; e < VB; ++e) {
+                    const int i = I0 + row(ty, ii), j = J0 + col(tx, h) + e;
+                    if (i < n && j < n && p[ii][h * VB + e] != 0u) {
+                        elem(D, (uint32_t)(i * n + j)) = d[ii][h * VB + e];
+                        elem(P, (uint32_t)(i * n + j)) = (int32_t)p[ii][h * VB + e] - 1;
                     }
                 }
     }
@@ -286,17 +318,24 @@ __device__ void solve_graph(Graph<T, TB, PATH> g, T *sa, T *sb, uint16_t *la, ui
             __syncthreads();
         }
         // Phase 4: every other tile, product of its final column-panel tile
-        // (staged once per tile row) and row-panel tile.
+        // (staged once per tile row) and row-panel tile; with labels, only the
+        // entries that decrease are read back and written.
         for (int t = 0; t < (R - 1) * (R - 1); ++t) {
             const int bi0 = t / (R - 1), bj0 = t % (R - 1);
             const int bi = bi0 < r ? bi0 : bi0 + 1, bj = bj0 < r ? bj0 : bj0 + 1;
             const int I0 = bi * TB, J0 = bj * TB;
             if (bj0 == 0) g.stage(sa, la, I0, k0);
             g.stage(sb, lb, k0, J0);
-            g.load(d, p, I0, J0, tx, ty);
+            if (PATH)
+                g.load_d0(d, p, I0, J0, tx, ty);
+            else
+                g.load(d, p, I0, J0, tx, ty);
             __syncthreads();
             G::product(d, p, sa, la, sb, lb, k0, tx, ty);
-            g.store(d, p, I0, J0, tx, ty);
+            if (PATH)
+                g.store_changed(d, p, I0, J0, tx, ty);
+            else
+                g.store(d, p, I0, J0, tx, ty);
             __syncthreads();
         }
     }
