@@ -25,8 +25,10 @@
 // elements, so a thread reads V consecutive k of a row, or VB consecutive
 // columns of a k row, with one vector load; without labels two k are folded per
 // three-way minimum.  In the last phase the column-panel tile of a block row
-// stays staged while the row's tiles are swept.  Labels are held in LDS as
-// 16-bit label + 1 (n <= 4096).
+// stays staged while the row's tiles are swept.  Labels are held as 16-bit
+// label + 1 (n <= 4096), in LDS and, while a graph is solved, in global
+// memory too: the first n*n*2 bytes of the graph's P hold them, and a last pass
+// widens them in place to the 32-bit labels.
 #include "fw_internal.h"
 #include "fw_lex.h"
 
@@ -84,7 +86,7 @@ struct Graph {
         return (i < n && j < n) ? (PATH ? canon(v) : v) : pad;
     }
     __device__ uint32_t ld_p(int i, int j) const {
-        const uint32_t v = (uint32_t)(elem(P, at(i, j)) + 1);
+        const uint32_t v = elem((uint16_t *)P, at(i, j));
         return (i < n && j < n) ? v : 0u;
     }
     // Tile (I0, J0) into LDS, row-major with stride ST (labels likewise): all
@@ -158,7 +160,7 @@ struct Graph {
                     const int i = I0 + row(ty, ii), j = J0 + col(tx, h) + e;
                     if (i < n && j < n) {
                         elem(D, (uint32_t)(i * n + j)) = d[ii][h * VB + e];
-                        if (PATH) elem(P, (uint32_t)(i * n + j)) = (int32_t)p[ii][h * VB + e] - 1;
+                        if (PATH) elem((uint16_t *)P, (uint32_t)(i * n + j)) = (uint16_t)p[ii][h * VB + e];
                     }
                 }
     }
@@ -175,7 +177,7 @@ struct Graph {
                     const int i = I0 + row(ty, ii), j = J0 + col(tx, h) + e;
                     if (i < n && j < n && p[ii][h * VB + e] != 0u) {
                         elem(D, (uint32_t)(i * n + j)) = d[ii][h * VB + e];
-                        elem(P, (uint32_t)(i * n + j)) = (int32_t)p[ii][h * VB + e] - 1;
+                        elem((uint16_t *)P, (uint32_t)(i * n + j)) = (uint16_t)p[ii][h * VB + e];
                     }
                 }
     }
@@ -249,7 +251,7 @@ __device__ void solve_graph(Graph<T, TB, PATH> g, T *sa, T *sb, uint16_t *la, ui
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
     const int n = g.n;
     if (PATH) {
-        for (int x = threadIdx.x; x < n * n; x += NT) g.P[x] = -1;
+        for (uint32_t x = threadIdx.x; x < (uint32_t)(n * n); x += NT) G::elem((uint16_t *)g.P, x) = 0;  // no label
     }
     __syncthreads();
     const int R = (n + TB - 1) / TB;
@@ -338,6 +340,31 @@ __device__ void solve_graph(Graph<T, TB, PATH> g, T *sa, T *sb, uint16_t *la, ui
                 g.store(d, p, I0, J0, tx, ty);
             __syncthreads();
         }
+    }
+    if (PATH) {
+        // Widen the 16-bit labels + 1 to 32-bit labels in place, last chunk
+        // first.  Chunk [a, a + CH) reads bytes [2a, 2a + 2CH) and writes
+        // [4a, 4a + 4CH): the words of lower chunks, not yet read, lie below
+        // 2a, and only chunk 0 writes over words of its own, after the barrier
+        // that follows its reads.
+        constexpr int PER = 8, CH = PER * NT;
+        const uint32_t nn = (uint32_t)(n * n);
+        for (int c = (int)((nn + CH - 1) / CH) - 1; c >= 0; --c) {
+            const uint32_t a = (uint32_t)c * CH;
+            uint32_t v[PER];
+#pragma unroll
+            for (int it = 0; it < PER; ++it) {
+                const uint32_t x = a + it * NT + threadIdx.x;
+                v[it] = x < nn ? G::elem((uint16_t *)g.P, x) : 0u;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int it = 0; it < PER; ++it) {
+                const uint32_t x = a + it * NT + threadIdx.x;
+                if (x < nn) G::elem(g.P, x) = (int32_t)v[it] - 1;
+            }
+        }
+        __syncthreads();
     }
 }
 
