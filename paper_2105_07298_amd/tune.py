@@ -174,7 +174,9 @@ def main():
         apsp_table.sort(key=lambda t: (t["dtype"], t["n_lo"], t["path"]))
         if args.skip_batched:
             batched_table = old["batched"]
-        log = [t for t in old["timings"] if not (t["kind"] == "apsp" and codes[t["dtype"]] in timed)] + log
+        log = [t for t in old["timings"]
+               if not ((t["kind"] == "apsp" and codes[t["dtype"]] in timed)
+                       or (t["kind"] == "batched" and not args.skip_batched))] + log
     with open(os.path.join(args.out, "tune_table.json"), "w") as f:
         json.dump({"arch": arch, "apsp": apsp_table, "batched": batched_table, "timings": log}, f, indent=1)
     write_inc(os.path.join(args.out, "tune_table.inc"), apsp_table, batched_table, arch)
