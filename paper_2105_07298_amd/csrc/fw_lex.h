@@ -12,17 +12,15 @@ namespace fw {
 // The same rule on labels kept offset by one (label + 1: "no interior vertex"
 // is 0, and labels compare as unsigned numbers).  For float the pair is one
 // 64-bit unsigned key, length bits above label: non-negative floats (+0 to
-// +inf) order like their bit patterns, so one compare and two selects replace
-// the three compares and two mask operations of the two-key test (binary16
-// likewise, its 16 bits above the label).  Lengths must not be -0.0 (see
-// canon()).
-// float: the 64-bit key read as an IEEE double orders like the key itself
-// (non-negative, and never NaN: a NaN double would need a float bit pattern
-// above +inf), subnormal doubles included, which these kernels keep (their
-// float mode preserves double subnormals).  So one double minimum takes the
-// lexicographic minimum, with no compare and selects.  It is written as the
-// instruction itself: the library minimum would first canonicalise both
-// operands against signalling NaNs.
+// +inf) order like their bit patterns, so the lexicographic minimum is the
+// minimum of the keys.  Lengths must not be -0.0 (see canon()).
+// The key read as an IEEE double orders like the key itself: it is
+// non-negative and never NaN (a NaN double would need a float bit pattern
+// above +inf), and non-negative doubles order like their bit patterns,
+// subnormals included, which these kernels keep (their float mode preserves
+// double subnormals).  So one double minimum takes it, with no compare and
+// selects.  It is written as the instruction itself: the library minimum would
+// first canonicalise both operands against signalling NaNs.
 __device__ __forceinline__ void lex_take_u(float &d, uint32_t &p, float s, uint32_t m) {
     const double ks = __builtin_bit_cast(double, ((uint64_t)__float_as_uint(s) << 32) | m);
     const double kd = __builtin_bit_cast(double, ((uint64_t)__float_as_uint(d) << 32) | p);
@@ -32,12 +30,16 @@ __device__ __forceinline__ void lex_take_u(float &d, uint32_t &p, float s, uint3
     d = __uint_as_float((uint32_t)(u >> 32));
     p = (uint32_t)u;
 }
+// binary16 likewise: its 16 bits above the label make every key a subnormal
+// double.
 __device__ __forceinline__ void lex_take_u(_Float16 &d, uint32_t &p, _Float16 s, uint32_t m) {
-    const uint64_t ks = ((uint64_t)__builtin_bit_cast(uint16_t, s) << 32) | m;
-    const uint64_t kd = ((uint64_t)__builtin_bit_cast(uint16_t, d) << 32) | p;
-    const bool take = ks < kd;
-    d = take ? s : d;
-    p = take ? m : p;
+    const double ks = __builtin_bit_cast(double, ((uint64_t)__builtin_bit_cast(uint16_t, s) << 32) | m);
+    const double kd = __builtin_bit_cast(double, ((uint64_t)__builtin_bit_cast(uint16_t, d) << 32) | p);
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(kd), "v"(ks));
+    const uint64_t u = __builtin_bit_cast(uint64_t, r);
+    d = __builtin_bit_cast(_Float16, (uint16_t)(u >> 32));
+    p = (uint32_t)u;
 }
 __device__ __forceinline__ void lex_take_u(double &d, uint32_t &p, double s, uint32_t m) {
     const bool take = (s < d) || (s == d && m < p);
