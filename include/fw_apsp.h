@@ -165,21 +165,31 @@ int64_t fw_ooc_superblock(fw_dtype_t dt, int64_t n, int32_t path, size_t device_
  *              (graph b occupies n_b*n_b elements from there, row-major).
  *   dist, path device, ragged concatenation; path may be NULL.
  * Same per-graph semantics and results as fw_apsp on each graph.  Allocates a
- * small stream-ordered job table.
+ * small stream-ordered job table.  In the launch one workgroup solves one
+ * graph, so a graph that alone holds much more than its share of the batch's
+ * work would finish long after the rest: a graph with n >= 256 whose n^3 is
+ * above 4 times the batch's sum of n^3 per resident workgroup is solved by
+ * fw_apsp instead, on the same stream, before the launch (see the route field
+ * of fw_batched_config_t).
  */
 fw_status_t fw_apsp_batched(fw_dtype_t dt, int32_t batch, const int32_t *n_host,
                             const int64_t *off_host, void *dist, int32_t *path, void *stream);
 
 /*
- * Tile choice of fw_apsp_batched, for tuning and for the tests that show results
- * do not depend on it: a graph is processed in 64 x 64 tiles when
- * n > small_max_n and 64-tiles pad it to no more vertices than 32-tiles would
- * (n mod 64 = 0 or > 32), otherwise in 32 x 32 tiles.  small_max_n = -1 keeps
- * the tuned choice; reserved fields must be 0.
+ * Choices of fw_apsp_batched, for tuning and for the tests that show results
+ * do not depend on them.
+ *   small_max_n  tile choice: a graph is processed in 64 x 64 tiles when
+ *                n > small_max_n and 64-tiles pad it to no more vertices than
+ *                32-tiles would (n mod 64 = 0 or > 32), otherwise in 32 x 32
+ *                tiles; -1 keeps the tuned choice.
+ *   route        which graphs fw_apsp solves instead of the persistent launch:
+ *                0 the rule given at fw_apsp_batched, -1 none, k > 0 every
+ *                graph with n >= k.
+ * Reserved fields must be 0.
  */
-typedef struct { int32_t small_max_n; int32_t reserved0; int32_t reserved1; int32_t reserved2; } fw_batched_config_t;
+typedef struct { int32_t small_max_n; int32_t route; int32_t reserved1; int32_t reserved2; } fw_batched_config_t;
 
-/* fw_apsp_batched with an explicit tile choice (cfg may be NULL = tuned choice). */
+/* fw_apsp_batched with explicit choices (cfg may be NULL = tuned tiles, route 0). */
 fw_status_t fw_apsp_batched_config(fw_dtype_t dt, int32_t batch, const int32_t *n_host,
                                    const int64_t *off_host, void *dist, int32_t *path,
                                    const fw_batched_config_t *cfg, void *stream);

@@ -88,7 +88,7 @@ def apsp_ooc_(W, P=None, device_bytes: int = 0):
     return W, P
 
 
-def apsp_batched_(Dcat, ns, offsets, Pcat=None, small_max_n: int = -1):
+def apsp_batched_(Dcat, ns, offsets, Pcat=None, small_max_n: int = -1, route: int = 0):
     """In-place APSP of many graphs in one persistent launch.
 
     Dcat: 1-D contiguous device tensor (float32/float64) holding every graph's
@@ -96,6 +96,9 @@ def apsp_batched_(Dcat, ns, offsets, Pcat=None, small_max_n: int = -1):
     with distances.  ns (int32) and offsets (int64) are host sequences of length
     batch.  Pcat (int32, same length as Dcat) receives the path matrices.
     small_max_n: graphs with n <= small_max_n use 32 x 32 tiles (-1 = tuned).
+    route: graphs solved by fw_apsp instead of the persistent launch (0 = those
+    that would hold far more than their share of the batch's work, -1 = none,
+    k > 0 = every graph with n >= k).
     """
     import numpy as np
     import torch
@@ -113,16 +116,16 @@ def apsp_batched_(Dcat, ns, offsets, Pcat=None, small_max_n: int = -1):
             raise ValueError("Pcat must be a contiguous int32 device tensor shaped like Dcat")
         pp = Pcat.data_ptr()
     fw_apsp_batched_config(_dtype_code(Dcat), int(ns.size), ns.ctypes.data, offs.ctypes.data, Dcat.data_ptr(), pp,
-                           small_max_n, _stream_ptr(Dcat.device))
+                           small_max_n, _stream_ptr(Dcat.device), route)
     return Dcat, Pcat
 
 
-def apsp_batched(Wcat, ns, offsets, path: bool = True, small_max_n: int = -1):
+def apsp_batched(Wcat, ns, offsets, path: bool = True, small_max_n: int = -1, route: int = 0):
     """(Dcat, Pcat) for a ragged batch of weight matrices (Wcat is not modified)."""
     import torch
     D = Wcat.contiguous().clone()
     P = torch.empty(D.shape, dtype=torch.int32, device=D.device) if path else None
-    return apsp_batched_(D, ns, offsets, P, small_max_n)
+    return apsp_batched_(D, ns, offsets, P, small_max_n, route)
 
 
 def apsp_backward(D, P, G):

@@ -28,7 +28,7 @@ class FwConfig(ctypes.Structure):
 
 
 class FwBatchedConfig(ctypes.Structure):
-    _fields_ = [("small_max_n", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+    _fields_ = [("small_max_n", ctypes.c_int32), ("route", ctypes.c_int32),
                 ("reserved1", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
@@ -128,8 +128,8 @@ def fw_apsp_batched(dt, batch, n_host, off_host, dist, path, stream=None):
     _check(lib().fw_apsp_batched(dt, batch, n_host, off_host, dist, path, stream), "fw_apsp_batched")
 
 
-def fw_apsp_batched_config(dt, batch, n_host, off_host, dist, path, small_max_n=-1, stream=None):
-    cfg = FwBatchedConfig(small_max_n, 0, 0, 0)
+def fw_apsp_batched_config(dt, batch, n_host, off_host, dist, path, small_max_n=-1, stream=None, route=0):
+    cfg = FwBatchedConfig(small_max_n, route, 0, 0)
     _check(lib().fw_apsp_batched_config(dt, batch, n_host, off_host, dist, path, ctypes.byref(cfg), stream),
            "fw_apsp_batched_config")
 

@@ -68,6 +68,10 @@ hipEvent_t take_event() {
 
 constexpr int64_t kMaxN = int64_t(1) << 20;
 constexpr int32_t kMaxBatchedN = 4096;
+// fw_apsp_batched routes a graph to fw_apsp when n >= kRouteMinN and n^3 is
+// above kRouteFactor times the batch's sum of n^3 per resident workgroup.
+constexpr int32_t kRouteMinN = 256;
+constexpr double kRouteFactor = 4.0;
 constexpr int32_t kMaxBackwardN = 4096;
 
 // Pinned staging for the batched job table.
@@ -412,7 +416,8 @@ fw_status_t fw_apsp(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, void *s
 fw_status_t fw_apsp_batched_config(fw_dtype_t dt, int32_t batch, const int32_t *n_host, const int64_t *off_host,
                                    void *dist, int32_t *path, const fw_batched_config_t *cfg, void *stream) {
     g_err[0] = 0;
-    if (cfg && (cfg->reserved0 || cfg->reserved1 || cfg->reserved2)) return fail(FW_EINVAL, "reserved config fields must be 0");
+    if (cfg && (cfg->reserved1 || cfg->reserved2)) return fail(FW_EINVAL, "reserved config fields must be 0");
+    if (cfg && cfg->route < -1) return fail(FW_EINVAL, "route = %d < -1", cfg->route);
     if (fw_status_t st = check_dtype(dt, true); st != FW_OK) return st;
     if (batch < 1) return fail(FW_EINVAL, "batch = %d < 1", batch);
     if (!n_host || !off_host || !dist) return fail(FW_EINVAL, "NULL argument");
@@ -427,11 +432,44 @@ fw_status_t fw_apsp_batched_config(fw_dtype_t dt, int32_t batch, const int32_t *
     hipStream_t s = (hipStream_t)stream;
     const int small_max_n = (cfg && cfg->small_max_n >= 0) ? cfg->small_max_n
                                                           : fw::tuned_batched_small_max_n(dt == FW_F64, path != nullptr);
+    int cus = 0;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return hip_fail(e, "CU count");
+    const bool p = path != nullptr;
+    const int occ = dt == FW_F32 ? fw::batched_occupancy<float>(p) : fw::batched_occupancy<double>(p);
+    // Routing: one workgroup solves one graph in the launch, so a graph that
+    // alone holds much more than the batch's work per resident workgroup would
+    // finish long after the rest.  Such graphs go to fw_apsp (the whole GPU
+    // per graph), one after another on the same stream, before the launch.
+    const int route = cfg ? cfg->route : 0;
+    double work = 0.0;
+    for (int32_t b = 0; b < batch; ++b) work += (double)n_host[b] * n_host[b] * n_host[b];
+    const double share = work / ((double)cus * occ);
+    auto routed = [&](int32_t b) {
+        const double nb = n_host[b];
+        if (route == -1) return false;
+        if (route > 0) return n_host[b] >= route;
+        return n_host[b] >= kRouteMinN && nb * nb * nb > kRouteFactor * share;
+    };
+    const size_t esize = dt == FW_F32 ? sizeof(float) : sizeof(double);
+    std::vector<int32_t> order;
+    order.reserve((size_t)batch);
+    for (int32_t b = 0; b < batch; ++b) {
+        if (!routed(b)) {
+            order.push_back(b);
+            continue;
+        }
+        if (fw_status_t st = fw_apsp_config(dt, n_host[b], (char *)dist + off_host[b] * esize,
+                                            path ? path + off_host[b] : nullptr, nullptr, stream);
+            st != FW_OK)
+            return st;
+    }
+    g_err[0] = 0;
+    if (order.empty()) return FW_OK;
+    const int32_t njobs = (int32_t)order.size();
     // Queue in order of decreasing n (longest job first); counter slot first.
-    std::vector<int32_t> order((size_t)batch);
-    for (int32_t b = 0; b < batch; ++b) order[(size_t)b] = b;
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return n_host[x] > n_host[y]; });
-    const size_t words = 1 + 2 * (size_t)batch, bytes = words * sizeof(int64_t);
+    const size_t words = 1 + 2 * (size_t)njobs, bytes = words * sizeof(int64_t);
     void *djobs = nullptr;
     e = hipMallocAsync(&djobs, bytes, s);
     if (e != hipSuccess) return fail(FW_ENOMEM, "job table of %zu bytes: %s", bytes, hipGetErrorString(e));
@@ -448,7 +486,7 @@ fw_status_t fw_apsp_batched_config(fw_dtype_t dt, int32_t batch, const int32_t *
         }
         int64_t *tab = (int64_t *)g_stage;
         tab[0] = 0;
-        for (int32_t q = 0; q < batch; ++q) {
+        for (int32_t q = 0; q < njobs; ++q) {
             tab[1 + 2 * q] = off_host[order[(size_t)q]];
             tab[2 + 2 * q] = n_host[order[(size_t)q]];
         }
@@ -457,15 +495,10 @@ fw_status_t fw_apsp_batched_config(fw_dtype_t dt, int32_t batch, const int32_t *
             return hip_fail(e, "event");
         if ((e = hipEventRecord(g_stage_ev, s)) != hipSuccess) return hip_fail(e, "event record");
     }
-    int cus = 0;
-    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
-        return hip_fail(e, "CU count");
-    const bool p = path != nullptr;
-    const int occ = dt == FW_F32 ? fw::batched_occupancy<float>(p) : fw::batched_occupancy<double>(p);
     int grid = cus * occ;
-    if (grid > batch) grid = batch;
-    e = dt == FW_F32 ? fw::launch_batched<float>((float *)dist, path, (int64_t *)djobs, batch, small_max_n, grid, s)
-                     : fw::launch_batched<double>((double *)dist, path, (int64_t *)djobs, batch, small_max_n, grid, s);
+    if (grid > njobs) grid = njobs;
+    e = dt == FW_F32 ? fw::launch_batched<float>((float *)dist, path, (int64_t *)djobs, njobs, small_max_n, grid, s)
+                     : fw::launch_batched<double>((double *)dist, path, (int64_t *)djobs, njobs, small_max_n, grid, s);
     hipError_t e2 = hipFreeAsync(djobs, s);
     if (e != hipSuccess) return hip_fail(e, "batched launch");
     if (e2 != hipSuccess) return hip_fail(e2, "job table free");

@@ -26,26 +26,29 @@ def ragged(graphs, dtype):
     return ns, off, W
 
 
-def run_batched(ns, off, W, dev, path=True, case=""):
+def run_batched(ns, off, W, dev, path=True, case="", route=0):
     import torch
     import paper_2105_07298_amd as fw
-    print(f"[gpu] fw_apsp_batched {case} batch={ns.size} dtype={W.dtype} path={path}", flush=True)
-    D, P = fw.apsp_batched(torch.from_numpy(W).to(dev), ns, off[:-1], path=path)
+    print(f"[gpu] fw_apsp_batched {case} batch={ns.size} dtype={W.dtype} path={path} route={route}", flush=True)
+    D, P = fw.apsp_batched(torch.from_numpy(W).to(dev), ns, off[:-1], path=path, route=route)
     torch.cuda.synchronize()
     return D.cpu().numpy(), (P.cpu().numpy() if P is not None else None)
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 @pytest.mark.parametrize("path", [True, False])
-def test_batched_integer_exact(dev, dtype, path):
+@pytest.mark.parametrize("route", [0, -1])
+def test_batched_integer_exact(dev, dtype, path, route):
     """Uneven sizes (1 .. 300, including non-multiples of the tile), tie-heavy integer
-    weights: every graph's D and P equal the oracle bit for bit."""
+    weights: every graph's D and P equal the oracle bit for bit, with the largest
+    graphs routed to fw_apsp (route 0: the n = 300 graph holds far more than its share)
+    and with every graph in the persistent launch (route -1)."""
     rng = np.random.default_rng(5)
     sizes = [1, 2, 5, 17, 63, 64, 65, 100, 128, 129, 200, 300] + list(rng.integers(1, 260, 28))
     graphs = [workloads.int_graph(n=int(n), p=float(rng.uniform(0.02, 0.5)), wmax=3, seed=300 + i)
               for i, n in enumerate(sizes)]
     ns, off, W = ragged(graphs, dtype)
-    D, P = run_batched(ns, off, W, dev, path=path, case="integer")
+    D, P = run_batched(ns, off, W, dev, path=path, case="integer", route=route)
     for b, g in enumerate(graphs):
         n = g.shape[0]
         Do, Po = oracle.fw(g)
@@ -123,8 +126,28 @@ def test_batched_c4_full(dev):
     assert worst <= 1e-5
 
 
+@pytest.mark.parametrize("route", [0, -1, 100])
+def test_batched_routing(dev, route):
+    """One graph of n = 700 among small ones: routed to fw_apsp by the automatic rule
+    (route 0) or by size (route 100, which also routes the n = 130 graph), or kept in
+    the persistent launch (route -1); D and P equal the oracle's in every case."""
+    rng = np.random.default_rng(10)
+    sizes = [700, 130, 65, 33, 7] + list(rng.integers(2, 60, 11))
+    graphs = [workloads.int_graph(n=int(n), p=0.05 if n > 300 else 0.2, wmax=4, seed=700 + i)
+              for i, n in enumerate(sizes)]
+    ns, off, W = ragged(graphs, np.float32)
+    D, P = run_batched(ns, off, W, dev, case="routing", route=route)
+    for b, g in enumerate(graphs):
+        n = g.shape[0]
+        Do, Po = oracle.fw(g)
+        np.testing.assert_array_equal(D[off[b]:off[b + 1]].reshape(n, n).astype(np.float64), Do)
+        np.testing.assert_array_equal(P[off[b]:off[b + 1]].reshape(n, n), Po)
+
+
 def test_batched_rejects_bad_arguments(dev):
+    import ctypes
     import paper_2105_07298_amd as fw
+    from paper_2105_07298_amd._lib import FwBatchedConfig
     L = fw.lib()
     ns = np.array([4, 0], dtype=np.int32)
     offs = np.array([0, 16], dtype=np.int64)
@@ -133,6 +156,10 @@ def test_batched_rejects_bad_arguments(dev):
     ns = np.array([4097], dtype=np.int32)
     st = L.fw_apsp_batched(0, 1, ns.ctypes.data, offs.ctypes.data, 4096, None, None)
     assert st == fw.FW_EINVAL
+    ns = np.array([4], dtype=np.int32)
+    for bad in (FwBatchedConfig(-1, -2, 0, 0), FwBatchedConfig(-1, 0, 1, 0), FwBatchedConfig(-1, 0, 0, 1)):
+        st = L.fw_apsp_batched_config(0, 1, ns.ctypes.data, offs.ctypes.data, 4096, None, ctypes.byref(bad), None)
+        assert st == fw.FW_EINVAL
 
 
 @pytest.mark.parametrize("small_max_n", [0, 96, 1 << 20])
