@@ -822,6 +822,73 @@ __device__ __forceinline__ void resolve_one(const T *__restrict__ D, const T *__
     P[ij] = (M == INT_MAX) ? (int32_t)(k0 + kbest) : M;
 }
 
+// The same with each entry's label + 1 and mark packed in one word
+// (W = mark << 16 | label + 1, ld <= 65535), so that a candidate k costs one
+// gathered word of (k, j) instead of a label and a mark.  A word read here is
+// either still pending (its mark and the label it had when marked) or already
+// resolved (mark 0, final label): the argument above gives the same minimum
+// either way, the skipped k being those whose word still carries a later mark.
+// Resolved words are label + 1 with no mark.
+template <typename T, int TB>
+__device__ __forceinline__ void resolve_one_packed(const T *__restrict__ D, const T *__restrict__ DT,
+                                                   uint32_t *__restrict__ W, int64_t ld, int64_t i, int64_t j) {
+    using vec = typename V16<T>::type;
+    constexpr int V = V16<T>::n;
+    const int64_t ij = i * ld + j;
+    const uint32_t lv = W[ij] >> 16;
+    if (lv == 0) return;
+    const int64_t k0 = (int64_t)(lv - 1) * TB;
+    const T d = D[ij];
+    const T *arow = D + i * ld + k0;
+    const T *brow = DT + j * ld + k0;
+    uint64_t hits = 0;
+    T best = inf_v<T>();
+    int kbest = 0;
+#pragma unroll 4
+    for (int kv = 0; kv < TB / V; ++kv) {
+        const vec a = *(const vec *)(arow + kv * V);
+        const vec b = *(const vec *)(brow + kv * V);
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const T s = a[e] + b[e];
+            const int k = kv * V + e;
+            hits |= (s == d) ? (1ull << k) : 0ull;
+            kbest = (s < best) ? k : kbest;
+            best = vmin(best, s);
+        }
+    }
+    uint32_t M = 0xffffffffu;
+    while (hits) {
+        const int k = __builtin_ctzll(hits);
+        hits &= hits - 1;
+        const int64_t kg = k0 + k;
+        const uint32_t wik = W[i * ld + kg], wkj = W[kg * ld + j];
+        if ((wik >> 16) > lv || (wkj >> 16) > lv) continue;  // decreased after round lv - 1
+        M = min(M, max(max(wik & 0xffffu, wkj & 0xffffu), (uint32_t)(kg + 1)));
+    }
+    W[ij] = (M == 0xffffffffu) ? (uint32_t)(k0 + kbest + 1) : M;
+}
+
+template <typename T, int TB>
+__global__ void __launch_bounds__(NT) k_resolve_packed(const T *__restrict__ D, const T *__restrict__ DT,
+                                                      uint32_t *__restrict__ W, int64_t ld) {
+    const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (j >= ld) return;
+    for (int64_t i = blockIdx.y; i < ld; i += gridDim.y) resolve_one_packed<T, TB>(D, DT, W, ld, i, j);
+}
+
+// P (labels, -1 = none) and L (marks) -> W = mark << 16 | label + 1, in P's
+// storage; and back to labels after the resolve.
+__global__ void __launch_bounds__(NT) k_pack_marks(int32_t *__restrict__ P, const uint16_t *__restrict__ L,
+                                                   int64_t count) {
+    for (int64_t x = (int64_t)blockIdx.x * NT + threadIdx.x; x < count; x += (int64_t)gridDim.x * NT)
+        P[x] = (int32_t)(((uint32_t)L[x] << 16) | (uint32_t)(P[x] + 1));
+}
+__global__ void __launch_bounds__(NT) k_unpack_labels(int32_t *__restrict__ P, int64_t count) {
+    for (int64_t x = (int64_t)blockIdx.x * NT + threadIdx.x; x < count; x += (int64_t)gridDim.x * NT)
+        P[x] = (int32_t)((uint32_t)P[x] & 0xffffu) - 1;
+}
+
 template <typename T, int TB>
 __global__ void __launch_bounds__(NT) k_resolve(const T *__restrict__ D, const T *__restrict__ DT,
                                                const uint16_t *__restrict__ L, int32_t *__restrict__ P,
@@ -1095,12 +1162,21 @@ template <typename T>
 hipError_t launch_resolve(const T *D, T *DT, const uint16_t *L, int32_t *P, int64_t ld, int block, hipStream_t s) {
     hipLaunchKernelGGL((k_transpose<T>), dim3((unsigned)(ld / 64), (unsigned)(ld / 64)), dim3(NT), 0, s, D, DT, ld);
     const dim3 grid((unsigned)((ld + NT - 1) / NT), (unsigned)(ld < 65535 ? ld : 65535));
+    if (block != 64 && block != 32) return hipErrorInvalidValue;
+    if (ld <= 65535) {  // label + 1 and the mark fit one word
+        uint32_t *W = (uint32_t *)P;
+        hipLaunchKernelGGL(k_pack_marks, dim3(grid_for(ld * ld)), dim3(NT), 0, s, P, L, ld * ld);
+        if (block == 64)
+            hipLaunchKernelGGL((k_resolve_packed<T, 64>), grid, dim3(NT), 0, s, D, DT, W, ld);
+        else
+            hipLaunchKernelGGL((k_resolve_packed<T, 32>), grid, dim3(NT), 0, s, D, DT, W, ld);
+        hipLaunchKernelGGL(k_unpack_labels, dim3(grid_for(ld * ld)), dim3(NT), 0, s, P, ld * ld);
+        return hipGetLastError();
+    }
     if (block == 64)
         hipLaunchKernelGGL((k_resolve<T, 64>), grid, dim3(NT), 0, s, D, DT, L, P, ld);
-    else if (block == 32)
-        hipLaunchKernelGGL((k_resolve<T, 32>), grid, dim3(NT), 0, s, D, DT, L, P, ld);
     else
-        return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_resolve<T, 32>), grid, dim3(NT), 0, s, D, DT, L, P, ld);
     return hipGetLastError();
 }
 
