@@ -41,10 +41,16 @@ __device__ __forceinline__ void lex_take_u(_Float16 &d, uint32_t &p, _Float16 s,
     d = __builtin_bit_cast(_Float16, (uint16_t)(u >> 32));
     p = (uint32_t)u;
 }
+// double: the key would need 96 bits, so the rule stays two-keyed, written
+// without short-circuit logic (which compiles to a branch around every
+// update): a tie keeps the smaller label, a shorter candidate takes its own,
+// and the length is the double minimum (the same instruction as above).
 __device__ __forceinline__ void lex_take_u(double &d, uint32_t &p, double s, uint32_t m) {
-    const bool take = (s < d) || (s == d && m < p);
-    d = take ? s : d;
-    p = take ? m : p;
+    const uint32_t q = (s == d) ? min(p, m) : p;
+    p = (s < d) ? m : q;
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(d), "v"(s));
+    d = r;
 }
 // A length as read from memory, with -0.0 turned into +0.0 (equal as numbers,
 // but its bit pattern would sort above +inf in lex_take_u's key).
