@@ -51,7 +51,18 @@ def product_two_pass(DA, PA, DB, PB, k_ids, Dc, Pc):
     return np.where(improve, S, Dc), Pn
 
 
-def blocked_model(W, TB, two_pass=True):
+def product_sentinel(DA, PA, DB, PB, k_ids, Dc, Pc, sentinel=-1):
+    """The batched kernel's last phase: the tile starts with its old lengths and the
+    label `sentinel` (-1, "no interior vertex": below every candidate's label, which
+    is at least k >= the round's first vertex), takes the lexicographic product, and
+    writes back only the entries whose label left the sentinel (those that
+    decreased); the others keep their old length and label."""
+    Dn, Pn = product_lex(DA, PA, DB, PB, k_ids, Dc, np.full(Pc.shape, sentinel, dtype=np.int64))
+    changed = Pn != sentinel
+    return np.where(changed, Dn, Dc), np.where(changed, Pn, Pc)
+
+
+def blocked_model(W, TB, two_pass=True, phase4=None):
     n = W.shape[0]
     npad = -(-n // TB) * TB
     D = np.full((npad, npad), np.inf)
@@ -80,7 +91,7 @@ def blocked_model(W, TB, two_pass=True):
         for bi in others:
             for bj in others:
                 is_, js = slice(bi * TB, (bi + 1) * TB), slice(bj * TB, (bj + 1) * TB)
-                f = product_two_pass if two_pass else product_lex
+                f = phase4 or (product_two_pass if two_pass else product_lex)
                 D[is_, js], P[is_, js] = f(D[is_, ks], P[is_, ks], D[ks, js], P[ks, js], K,
                                            D[is_, js], P[is_, js])
     return D[:n, :n], P[:n, :n].astype(np.int32)
@@ -105,6 +116,31 @@ def test_model_c1_like(two_pass):
     Dm, Pm = blocked_model(W.astype(np.float64), 16, two_pass=two_pass)
     np.testing.assert_array_equal(Dm, D)
     np.testing.assert_array_equal(Pm, P)
+
+
+@pytest.mark.parametrize("TB", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("seed", range(4))
+def test_sentinel_last_phase_equals_classic(TB, seed):
+    """The batched kernel's last phase (old labels not read, only decreased entries
+    written) gives the classic loop's D and P on tie-heavy graphs."""
+    rng = np.random.default_rng(seed + 20)
+    n = int(rng.integers(5, 40))
+    W = workloads.int_graph(n=n, p=float(rng.uniform(0.05, 0.6)), wmax=int(rng.integers(1, 4)), seed=seed + 90)
+    D, P = oracle.fw(W)
+    Dm, Pm = blocked_model(W.astype(np.float64), TB, phase4=product_sentinel)
+    np.testing.assert_array_equal(Dm, D)
+    np.testing.assert_array_equal(Pm, P)
+
+
+def test_sentinel_must_sort_below_candidates():
+    """Control: a sentinel above every label lets a tie with the old length replace
+    the old label, and P then differs from the classic loop's."""
+    W = workloads.int_graph(n=40, p=0.3, wmax=2, seed=3).astype(np.float64)
+    D, P = oracle.fw(W)
+    high = lambda *a: product_sentinel(*a, sentinel=1 << 40)
+    Dm, Pm = blocked_model(W, 4, phase4=high)
+    np.testing.assert_array_equal(Dm, D)
+    assert not np.array_equal(Pm, P)
 
 
 def test_naive_p_rule_differs():
