@@ -14,6 +14,7 @@
 
 #include "../../include/fw_apsp.h"
 #include "fw_internal.h"
+#include "fw_route.h"
 #include "fw_plan.h"
 
 static_assert(fw::FW_VARIANT_PANELS == FW_P4_PANELS && fw::FW_VARIANT_WAVEROWS == FW_P4_WAVEROWS,
@@ -68,10 +69,6 @@ hipEvent_t take_event() {
 
 constexpr int64_t kMaxN = int64_t(1) << 20;
 constexpr int32_t kMaxBatchedN = 4096;
-// fw_apsp_batched routes a graph to fw_apsp when n >= kRouteMinN and n^3 is
-// above kRouteFactor times the batch's sum of n^3 per resident workgroup.
-constexpr int32_t kRouteMinN = 256;
-constexpr double kRouteFactor = 4.0;
 constexpr int32_t kMaxBackwardN = 4096;
 
 // Pinned staging for the batched job table.
@@ -437,25 +434,15 @@ fw_status_t fw_apsp_batched_config(fw_dtype_t dt, int32_t batch, const int32_t *
         return hip_fail(e, "CU count");
     const bool p = path != nullptr;
     const int occ = dt == FW_F32 ? fw::batched_occupancy<float>(p) : fw::batched_occupancy<double>(p);
-    // Routing: one workgroup solves one graph in the launch, so a graph that
-    // alone holds much more than the batch's work per resident workgroup would
-    // finish long after the rest.  Such graphs go to fw_apsp (the whole GPU
+    // Graphs far above their share of the work go to fw_apsp (the whole GPU
     // per graph), one after another on the same stream, before the launch.
-    const int route = cfg ? cfg->route : 0;
-    double work = 0.0;
-    for (int32_t b = 0; b < batch; ++b) work += (double)n_host[b] * n_host[b] * n_host[b];
-    const double share = work / ((double)cus * occ);
-    auto routed = [&](int32_t b) {
-        const double nb = n_host[b];
-        if (route == -1) return false;
-        if (route > 0) return n_host[b] >= route;
-        return n_host[b] >= kRouteMinN && nb * nb * nb > kRouteFactor * share;
-    };
+    std::vector<uint8_t> routed((size_t)batch);
+    fw::batched_route(n_host, batch, (int64_t)cus * occ, cfg ? cfg->route : 0, routed.data());
     const size_t esize = dt == FW_F32 ? sizeof(float) : sizeof(double);
     std::vector<int32_t> order;
     order.reserve((size_t)batch);
     for (int32_t b = 0; b < batch; ++b) {
-        if (!routed(b)) {
+        if (!routed[(size_t)b]) {
             order.push_back(b);
             continue;
         }
