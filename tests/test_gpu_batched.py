@@ -144,6 +144,24 @@ def test_batched_routing(dev, route):
         np.testing.assert_array_equal(P[off[b]:off[b + 1]].reshape(n, n), Po)
 
 
+def test_batched_large_graph_in_launch(dev):
+    """n = 2048 (32 rounds of 64-tiles, labels up to 2047 in the 16-bit in-solve
+    form) kept in the persistent launch, beside small graphs: D and P equal
+    fw_apsp's on the same graph bit for bit (tie-heavy integer weights)."""
+    import torch
+    import paper_2105_07298_amd as fw
+    graphs = [workloads.int_graph(n=2048, p=0.01, wmax=3, seed=800)] + \
+             [workloads.int_graph(n=int(n), p=0.2, wmax=3, seed=801 + i) for i, n in enumerate([5, 63, 130])]
+    ns, off, W = ragged(graphs, np.float32)
+    D, P = run_batched(ns, off, W, dev, case="large in launch", route=-1)
+    for b, g in enumerate(graphs):
+        n = g.shape[0]
+        print(f"[gpu] fw_apsp n={n} (reference for the batched result)", flush=True)
+        Ds, Ps = fw.apsp(torch.from_numpy(g).to(dev))
+        np.testing.assert_array_equal(D[off[b]:off[b + 1]].reshape(n, n), Ds.cpu().numpy())
+        np.testing.assert_array_equal(P[off[b]:off[b + 1]].reshape(n, n), Ps.cpu().numpy())
+
+
 def test_batched_rejects_bad_arguments(dev):
     import ctypes
     import paper_2105_07298_amd as fw
