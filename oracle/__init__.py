@@ -17,9 +17,12 @@ Contents
                         of (D, P) written out.
   backward_pathwalk     dL/dW from dL/dD by walking each pair's shortest path.
   reconstruct(P, i, j)  vertex list of the path P encodes.
+  path_sums(W, P)       every pair's encoded path walked and summed (the checker's
+                        all-pairs pass).
   check_invariants      D[i][i] = 0, D <= W, triangle inequality, P never names
-                        an endpoint, and every encoded path exists, sums to D and
-                        is canonical.
+                        an endpoint, and on every pair the encoded path exists,
+                        splits at P[i][j] and sums to D (exactly and canonically
+                        for integer weights, within rtol for real weights).
 
 Parity status of each function and the pins that fix it are listed in the design doc.
 """
@@ -69,6 +72,9 @@ def load(path: str = _LIB):
     lib.oracle_reconstruct.argtypes = [i64, vp, i64, i64, vp, i64]
     lib.oracle_reconstruct.restype = i64
     lib.oracle_max_threads.restype = ctypes.c_int
+    lib.oracle_path_sums_rows_f64.argtypes = [i64, vp, vp, i64, vp, vp, vp, ctypes.c_int]
+    lib.oracle_triangle_violations_rows.argtypes = [i64, vp, i64, vp, vp, i64, ctypes.c_double, ctypes.c_int]
+    lib.oracle_triangle_violations_rows.restype = i64
     if path == _LIB:
         _lib = lib
     return lib
@@ -267,62 +273,122 @@ def brute_force(W: np.ndarray):
     return D, P
 
 
+def path_sums(W: np.ndarray, P: np.ndarray, rows=None, threads: int = 0):
+    """Walk the encoded paths of the given source rows (default: all): (S, H) with
+    S[q][j] the sum of W along the path of (rows[q], j) (float64, path order) and
+    H[q][j] its edge count, H = -1 where P encodes no path (endpoint or
+    out-of-range label, cycle, more than n - 1 edges)."""
+    lib = load()
+    n = W.shape[0]
+    Wd = np.ascontiguousarray(W, dtype=np.float64)
+    Pc = np.ascontiguousarray(P, dtype=np.int32)
+    rows = np.arange(n, dtype=np.int64) if rows is None else np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+    S = np.empty((rows.size, n), dtype=np.float64)
+    H = np.empty((rows.size, n), dtype=np.int64)
+    lib.oracle_path_sums_rows_f64(n, _ptr(Wd), _ptr(Pc), rows.size, _ptr(rows), _ptr(S), _ptr(H), threads)
+    return S, H
+
+
+def triangle_violations(D: np.ndarray, ks, rtol: float = 0.0, rows=None, threads: int = 0) -> int:
+    """Number of (i, j, k), i in rows (default all), k in ks, with
+    D[i][j] > (D[i][k] + D[k][j]) (1 + rtol)."""
+    lib = load()
+    Dd = np.ascontiguousarray(D, dtype=np.float64)
+    n = Dd.shape[0]
+    ks = np.ascontiguousarray(np.asarray(ks, dtype=np.int64))
+    rows = np.arange(n, dtype=np.int64) if rows is None else np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+    return int(lib.oracle_triangle_violations_rows(n, _ptr(Dd), rows.size, _ptr(rows), _ptr(ks), ks.size,
+                                                   float(rtol), threads))
+
+
 def check_invariants(W, D, P, exact: bool, sample=None, rtol: float = 0.0, nsample: int = 2000,
-                     seed: int = 0):
+                     seed: int = 0, rows=None):
     """Assert the properties every correct (D, P) has; raises AssertionError on the first failure.
 
-    Always: D[i][i] = 0, P[i][i] = -1, D <= W, the triangle inequality
-    D[i][j] <= D[i][k] + D[k][j] (every k for n <= 1024, else 64 sampled k),
-    P in [-1, n), P[i][j] never i or j, P = -1 on unreachable pairs.
+    What (D, P) must be follows from Sect. 2.2 (Algorithm 1): D[i][j] the length
+    of a shortest i->j path, P[i][j] an intermediate vertex of one, -1 for the
+    direct edge or no path (readings R1-R2).
 
-    exact (integer weights): for every pair, P[i][j] = -1 means D[i][j] = W[i][j]
-    (the direct edge is shortest), and P[i][j] = k >= 0 means
-    D[i][j] = D[i][k] + D[k][j] with P[i][k] < k and P[k][j] < k.  By induction on
-    k these make every encoded path exist, end at j, sum exactly to D[i][j], and
-    have k as its largest interior vertex -- i.e. P is the canonical path matrix.
+    Checked on every pair (i, j) with i in `rows` (default: every row): D[i][i] =
+    0, P[i][i] = -1, D <= W, the triangle inequality D[i][j] <= D[i][k] + D[k][j]
+    (every k for n <= 2048, else 64 sampled k), P in [-1, n), P[i][j] never i or j,
+    P = -1 on unreachable pairs, and the path P encodes for (i, j) exists (no
+    cycle, at most n - 1 edges, only existing edges) and its weights add up to
+    D[i][j].
 
-    Both: sampled pairs are reconstructed explicitly and summed (within rtol for
-    real weights).
+    exact (integer weights): that sum equals D[i][j] exactly; P[i][j] = -1 means
+    D[i][j] = W[i][j], and P[i][j] = k >= 0 means D[i][j] = D[i][k] + D[k][j] with
+    P[i][k] < k and P[k][j] < k.  By induction on k these make P the canonical
+    path matrix (its k is the largest interior vertex of the encoded path).
+
+    real weights (exact=False): the same relations within rtol: |D - W| <= rtol D
+    where P = -1, |D[i][k] + D[k][j] - D[i][j]| <= rtol D[i][j] at k = P[i][j] >= 0
+    (finite pairs), and |sum - D[i][j]| <= rtol D[i][j] h for an encoded path of
+    h edges.
+
+    Both: sampled pairs are also reconstructed vertex by vertex (no repeated
+    vertex; with exact weights the largest interior vertex is P[i][j]).
     """
-    W = np.asarray(W, dtype=np.float64)
-    D = np.asarray(D, dtype=np.float64)
+    W = np.asarray(W)
+    D = np.asarray(D)
     P = np.asarray(P)
     n = W.shape[0]
-    assert np.all(np.diagonal(D) == 0), "D[i][i] != 0"
-    assert np.all(np.diagonal(P) == -1), "P[i][i] != -1"
-    assert np.all(D <= W), "D exceeds W"
-    finD = np.isfinite(D)
-    ks = range(n) if n <= 1024 else np.random.default_rng(seed).choice(n, 64, replace=False)
-    for k in ks:
-        via = D[:, k:k + 1] + D[k:k + 1, :]
-        tol = rtol * np.where(np.isfinite(via), via, 0)
-        assert np.all(D <= via + tol), f"triangle inequality broken through k={k}"
-    assert np.all((P >= -1) & (P < n)), "P out of range"
-    idx = np.arange(n)
-    off = ~np.eye(n, dtype=bool)
-    assert not np.any((P == idx[:, None]) & off), "P[i][j] == i"
-    assert not np.any((P == idx[None, :]) & off), "P[i][j] == j"
-    assert np.all(P[~finD] == -1), "P set on an unreachable pair"
-    direct = (P == -1) & finD & off
+    assert D.shape == (n, n) and P.shape == (n, n), "shape"
+    rows = np.arange(n, dtype=np.int64) if rows is None else np.asarray(rows, dtype=np.int64)
+    Wr = W[rows].astype(np.float64)
+    Dr = D[rows].astype(np.float64)
+    Pr = P[rows]
+    R = np.arange(rows.size)
+    assert not np.isnan(Dr).any(), "D holds NaN"
+    assert np.all(Dr[R, rows] == 0), "D[i][i] != 0"
+    assert np.all(Pr[R, rows] == -1), "P[i][i] != -1"
+    assert np.all(Dr <= Wr), "D exceeds W"
+    finD = np.isfinite(Dr)
+    ks = np.arange(n) if n <= 2048 else np.random.default_rng(seed).choice(n, 64, replace=False)
+    assert triangle_violations(D, ks, rtol, rows=rows) == 0, "triangle inequality broken"
+    assert np.all((Pr >= -1) & (Pr < n)), "P out of range"
+    off = rows[:, None] != np.arange(n)[None, :]
+    assert not np.any((Pr == rows[:, None]) & off), "P[i][j] == i"
+    assert not np.any((Pr == np.arange(n)[None, :]) & off), "P[i][j] == j"
+    assert np.all(Pr[~finD] == -1), "P set on an unreachable pair"
+    direct = (Pr == -1) & finD & off
+
+    def dval(a, b):  # D[a][b] as float64, elementwise
+        return np.asarray(D[a, b], dtype=np.float64)
+
     if exact:
-        assert np.all(D[direct] == W[direct]), "P = -1 but D differs from the direct edge"
-        I, J = np.nonzero(P >= 0)
-        K = P[I, J].astype(np.int64)
-        assert np.all(D[I, K] + D[K, J] == D[I, J]), "D[i][j] != D[i][k] + D[k][j] for k = P[i][j]"
+        assert np.all(Dr[direct] == Wr[direct]), "P = -1 but D differs from the direct edge"
+        Q, J = np.nonzero(Pr >= 0)
+        I, K = rows[Q], Pr[Q, J].astype(np.int64)
+        assert np.all(dval(I, K) + dval(K, J) == Dr[Q, J]), "D[i][j] != D[i][k] + D[k][j] for k = P[i][j]"
         assert np.all(P[I, K] < K), "P[i][P[i][j]] >= P[i][j] (not canonical)"
         assert np.all(P[K, J] < K), "P[P[i][j]][j] >= P[i][j] (not canonical)"
     else:
-        dd = D[direct]
-        assert np.all(np.abs(dd - W[direct]) <= rtol * dd), "P = -1 but D differs from the direct edge"
+        dd = Dr[direct]
+        assert np.all(np.abs(dd - Wr[direct]) <= rtol * dd), "P = -1 but D differs from the direct edge"
+        Q, J = np.nonzero((Pr >= 0) & finD)
+        I, K = rows[Q], Pr[Q, J].astype(np.int64)
+        dij = Dr[Q, J]
+        assert np.all(np.abs(dval(I, K) + dval(K, J) - dij) <= rtol * dij), \
+            "D[i][k] + D[k][j] differs from D[i][j] at k = P[i][j]"
+    S, H = path_sums(W, P, rows=rows)
+    assert np.all(H[finD] >= 0), "P encodes no path (cycle, endpoint label or too long) for some pair"
+    if exact:
+        assert np.array_equal(S[finD], Dr[finD]), "an encoded path does not sum to D"
+    else:
+        df = Dr[finD]
+        assert np.all(np.abs(S[finD] - df) <= rtol * df * np.maximum(H[finD], 1)), \
+            "an encoded path does not sum to D within rtol"
     if sample is None:
         rng = np.random.default_rng(seed)
-        I, J = np.nonzero(finD & off)
-        if I.size > nsample:
-            pick = rng.choice(I.size, nsample, replace=False)
-            I, J = I[pick], J[pick]
-        sample = list(zip(I.tolist(), J.tolist()))
+        Q, J = np.nonzero(finD & off)
+        if Q.size > nsample:
+            pick = rng.choice(Q.size, nsample, replace=False)
+            Q, J = Q[pick], J[pick]
+        sample = list(zip(rows[Q].tolist(), J.tolist()))
     for (i, j) in sample:
-        if not finD[i, j]:
+        dij = float(D[i, j])
+        if not np.isfinite(dij):
             continue
         path = reconstruct(P, i, j)
         assert path is not None, f"invalid path encoding at ({i},{j})"
@@ -330,12 +396,13 @@ def check_invariants(W, D, P, exact: bool, sample=None, rtol: float = 0.0, nsamp
         assert len(set(path)) == len(path), f"path for ({i},{j}) repeats a vertex"
         s = 0.0
         for a, b in zip(path[:-1], path[1:]):
-            assert np.isfinite(W[a, b]), f"path ({i},{j}) uses a missing edge {a}->{b}"
-            s += W[a, b]
+            w = float(W[a, b])
+            assert np.isfinite(w), f"path ({i},{j}) uses a missing edge {a}->{b}"
+            s += w
         if exact:
-            assert s == D[i, j], f"path ({i},{j}) sums to {s} != D {D[i, j]}"
+            assert s == dij, f"path ({i},{j}) sums to {s} != D {dij}"
             if len(path) > 2:
                 assert max(path[1:-1]) == P[i, j], "P is not the largest interior vertex"
         else:
-            assert abs(s - D[i, j]) <= rtol * max(abs(D[i, j]), 1e-30) * len(path), \
-                f"path ({i},{j}) sums to {s} vs D {D[i, j]}"
+            assert abs(s - dij) <= rtol * max(abs(dij), 1e-30) * len(path), \
+                f"path ({i},{j}) sums to {s} vs D {dij}"

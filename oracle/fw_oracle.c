@@ -364,4 +364,81 @@ int64_t oracle_reconstruct(int64_t n, const int32_t *P, int64_t i, int64_t j, in
     return len;
 }
 
+/*
+ * Walk the encoded paths of rows rows[0..nrows) of P and add up their weights
+ * (the checker of a path matrix; what P must encode follows from Sect. 2.2,
+ * Algorithm 1: P[i][j] = k names an intermediate vertex, so the path of (i, j) is
+ * the path of (i, k) followed by the path of (k, j), and -1 means the edge i->j
+ * itself).
+ *
+ * For source i = rows[q] and every j != i: S[q][j] = sum of W over the edges of
+ * the encoded path, summed in path order in double (+inf when it uses a missing
+ * edge), and H[q][j] = its number of edges.  H[q][j] = -1 marks an encoding that
+ * is no path: a label equal to an endpoint or outside [-1, n), a walk that would
+ * need more than n - 1 edges, or a recursion deeper than 2n (a cyclic encoding).
+ * j == i gets S = 0, H = 0.  Parallel over the rows (pairs are independent).
+ */
+void oracle_path_sums_rows_f64(int64_t n, const double *W, const int32_t *P, int64_t nrows, const int64_t *rows,
+                               double *S, int64_t *H, int threads)
+{
+#pragma omp parallel num_threads(pick_threads(threads))
+    {
+        int64_t scap = 2 * n + 4;
+        int64_t *stk = (int64_t *)malloc(sizeof(int64_t) * 2 * (size_t)scap);
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t q = 0; q < nrows; ++q) {
+            const int64_t i = rows[q];
+            for (int64_t j = 0; j < n; ++j) {
+                if (i == j) { S[q * n + j] = 0.0; H[q * n + j] = 0; continue; }
+                double sum = 0.0;
+                int64_t edges = 0, top = 1, bad = 0;
+                stk[0] = i; stk[1] = j;
+                while (top > 0) {
+                    --top;
+                    int64_t a = stk[2 * top], b = stk[2 * top + 1];
+                    int32_t m = P[a * n + b];
+                    if (m == -1) {
+                        if (++edges > n - 1) { bad = 1; break; }
+                        sum += W[a * n + b];
+                        continue;
+                    }
+                    if (m < -1 || m >= n || m == a || m == b || top + 2 > scap) { bad = 1; break; }
+                    stk[2 * top] = m; stk[2 * top + 1] = b; ++top;
+                    stk[2 * top] = a; stk[2 * top + 1] = m; ++top;
+                }
+                S[q * n + j] = bad ? NAN : sum;
+                H[q * n + j] = bad ? -1 : edges;
+            }
+        }
+        free(stk);
+    }
+}
+
+/*
+ * Triangle inequality D[i][j] <= (D[i][k] + D[k][j]) (1 + rtol) for every i in
+ * rows[0..nrows), every j and every k in ks[0..nk) (shortest distances satisfy
+ * it for every k).  Returns the number of violating (i, j, k); +inf sums never
+ * violate.
+ */
+int64_t oracle_triangle_violations_rows(int64_t n, const double *D, int64_t nrows, const int64_t *rows,
+                                        const int64_t *ks, int64_t nk, double rtol, int threads)
+{
+    int64_t bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : bad) num_threads(pick_threads(threads))
+    for (int64_t q = 0; q < nrows; ++q) {
+        const double *rowi = D + rows[q] * n;
+        for (int64_t t = 0; t < nk; ++t) {
+            const int64_t k = ks[t];
+            const double a = rowi[k];
+            if (a == INFINITY) continue;
+            const double *rowk = D + k * n;
+            for (int64_t j = 0; j < n; ++j) {
+                const double via = a + rowk[j];
+                if (via != INFINITY && rowi[j] > via + rtol * via) ++bad;
+            }
+        }
+    }
+    return bad;
+}
+
 int oracle_max_threads(void) { return omp_get_max_threads(); }

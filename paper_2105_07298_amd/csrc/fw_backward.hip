@@ -55,19 +55,20 @@ __global__ void __launch_bounds__(NT) k_backward(const T *__restrict__ D, const 
     constexpr int16_t UNSET = -1, NONE = -2;
 
     // 1. predecessor of every reachable j (the chain has at most n links for a
-    //    valid path matrix; a longer one is treated as unreachable).
+    //    valid path matrix; a longer one, or a label outside [-1, n), is
+    //    treated as unreachable).
     for (int j = threadIdx.x; j < n; j += NT) {
         int16_t pr = -1, dp = NONE;
         double s = 0.0;
         if (j != i && Drow[j] != inf_w<T>()) {
             int a = i, steps = 0;
             int32_t m = Pg[(int64_t)a * n + j];
-            while (m >= 0 && steps < n) {
+            while (m >= 0 && m < n && steps < n) {
                 a = m;
                 m = Pg[(int64_t)a * n + j];
                 ++steps;
             }
-            if (m < 0) {
+            if (m == -1) {
                 pr = (int16_t)a;
                 dp = UNSET;
                 s = (double)Grow[j];

@@ -342,6 +342,10 @@ __device__ void solve_graph(Graph<T, TB, PATH> g, T *sa, T *sb, uint16_t *la, ui
         }
     }
     if (PATH) {
+        // Every thread's last label stores must be visible before any thread
+        // reads them back: with one round (n <= TB) nothing after phase 1's
+        // store has a barrier.
+        __syncthreads();
         // Widen the 16-bit labels + 1 to 32-bit labels in place, last chunk
         // first.  Chunk [a, a + CH) reads bytes [2a, 2a + 2CH) and writes
         // [4a, 4a + 4CH): the words of lower chunks, not yet read, lie below

@@ -826,9 +826,10 @@ __device__ __forceinline__ void resolve_one(const T *__restrict__ D, const T *__
 // (W = mark << 16 | label + 1, ld <= 65535), so that a candidate k costs one
 // gathered word of (k, j) instead of a label and a mark.  A word read here is
 // either still pending (its mark and the label it had when marked) or already
-// resolved (mark 0, final label): the argument above gives the same minimum
-// either way, the skipped k being those whose word still carries a later mark.
-// Resolved words are label + 1 with no mark.
+// resolved (its mark and its final label): the argument above gives the same
+// minimum either way.  A resolved word keeps its mark, so whether a neighbour
+// entry counts as decreased after round r never depends on whether another
+// thread has resolved it yet, and the result does not depend on timing.
 template <typename T, int TB>
 __device__ __forceinline__ void resolve_one_packed(const T *__restrict__ D, const T *__restrict__ DT,
                                                    uint32_t *__restrict__ W, int64_t ld, int64_t i, int64_t j) {
@@ -866,7 +867,7 @@ __device__ __forceinline__ void resolve_one_packed(const T *__restrict__ D, cons
         if ((wik >> 16) > lv || (wkj >> 16) > lv) continue;  // decreased after round lv - 1
         M = min(M, max(max(wik & 0xffffu, wkj & 0xffffu), (uint32_t)(kg + 1)));
     }
-    W[ij] = (M == 0xffffffffu) ? (uint32_t)(k0 + kbest + 1) : M;
+    W[ij] = (lv << 16) | ((M == 0xffffffffu) ? (uint32_t)(k0 + kbest + 1) : M);
 }
 
 template <typename T, int TB>

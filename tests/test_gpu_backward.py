@@ -125,6 +125,29 @@ def test_batched_forward_backward(dev):
         np.testing.assert_allclose(gW[b], ref, rtol=1e-5, atol=1e-5 * np.abs(ref).max())
 
 
+def test_batched_real_weights_vs_path_walk(dev):
+    """A batch of 64 graphs at n = 128, float32 weights in [1, 2) at density 0.1
+    (multi-hop paths, real weights): each graph's GPU (D, P) passes the checker, and
+    its gradient equals the oracle path walk over the GPU's own (D, P) -- the
+    subgradient along the paths that P encodes, whichever of two near-equal paths
+    rounding made the GPU pick."""
+    B, n = 64, 128
+    Ws = np.stack([workloads.graph(71, n, 0.1, workloads.W_ONE_TWO, 0, np.float32, g=b) for b in range(B)])
+    G = np.random.default_rng(7).standard_normal(Ws.shape).astype(np.float32)
+    D, P, gW = gpu_forward_backward(Ws, G, dev, "batch-real")
+    hops = 0
+    for b in range(B):
+        Do, _ = oracle.fw(Ws[b], exact=False)
+        fin = np.isfinite(Do)
+        assert np.array_equal(np.isfinite(D[b]), fin)
+        assert np.max(np.abs(D[b][fin] - Do[fin]) / np.maximum(Do[fin], 1e-30)) <= 1e-5
+        oracle.check_invariants(Ws[b], D[b], P[b], exact=False, rtol=1e-5, nsample=50, seed=b)
+        hops += int((P[b] >= 0).sum())
+        ref = oracle.backward_pathwalk(D[b].astype(np.float64), P[b], G[b].astype(np.float64))
+        np.testing.assert_allclose(gW[b], ref, rtol=1e-5, atol=1e-5 * np.abs(ref).max())
+    assert hops > B * n * 10  # multi-hop paths throughout
+
+
 def test_c5_batch_closed_form(dev):
     """The 256 x 128 complete-graph batch with weights in [1, 2): D = W and dL/dW = G
     off the diagonal for every graph."""

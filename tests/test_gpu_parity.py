@@ -208,25 +208,24 @@ def test_configs_real_weights(dev, dtype, tol):
             np.testing.assert_array_equal(Pg, first[block][1])
 
 
+@pytest.mark.timeout(600)
 @pytest.mark.parametrize("dtype,tol", [(np.float32, 1e-5), (np.float64, 1e-12)])
-def test_c2_16384_dijkstra_rows(dev, dtype, tol):
-    """n = 16384 (the benchmark size): 64 seeded source rows vs Dijkstra in float64."""
-    n = 16384
+@pytest.mark.parametrize("n", [8192, 16384])
+def test_c2_large_dijkstra_rows(dev, n, dtype, tol):
+    """n = 8192 and 16384 (the benchmark size; the tuned schedule changes at 8192):
+    64 seeded source rows vs float64 Dijkstra, and the path matrix on those rows
+    through the checker (every encoded path exists, splits at its label and sums to
+    D within the tolerance)."""
     W = workloads.unit_complete(n, dtype=dtype, seed=2)
-    Dg, Pg = run_gpu(W, dev, case="C2-16384")
+    Dg, Pg = run_gpu(W, dev, case=f"C2-{n}")
     srcs = workloads.sample_sources(n, 64)
     print("[cpu] dijkstra 64 rows", flush=True)
     Dr, _ = oracle.dijkstra_rows(W, srcs, exact=False)
     err = rel_err(Dg[srcs], Dr)
     print(f"max relative error {err:.3e}", flush=True)
     assert err <= tol
-    # path matrix on the sampled rows: encoded paths exist and sum to D
-    pairs = [(int(i), int(j)) for i in srcs[:8] for j in range(0, n, 97) if i != j]
-    for (i, j) in pairs:
-        pth = oracle.reconstruct(Pg, i, j)
-        assert pth is not None and pth[0] == i and pth[-1] == j
-        s = sum(float(W[a, b]) for a, b in zip(pth[:-1], pth[1:]))
-        assert abs(s - float(Dg[i, j])) <= 1e-5 * float(Dg[i, j]) * len(pth)
+    print("[cpu] checker on the 64 rows", flush=True)
+    oracle.check_invariants(W, Dg, Pg, exact=False, rtol=max(tol, 1e-7), nsample=200, rows=srcs)
 
 
 def test_lookahead_16384_matches_serial(dev):

@@ -5,6 +5,7 @@ import os
 import shutil
 import subprocess
 import tempfile
+import types
 
 import numpy as np
 import pytest
@@ -12,6 +13,7 @@ import pytest
 import oracle
 import workloads
 from conftest import load_golden
+from test_checker_pins import escaped
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "fw_oracle.c")
 
@@ -102,7 +104,11 @@ def run_pins():
     pin("golden", golden)
     pin("dijkstra", dijkstra)
     pin("backward", backward)
+    def checker():
+        assert escaped(oracle.check_invariants) == []
+
     pin("invariants", invariants)
+    pin("checker", checker)
     return failed
 
 
@@ -138,3 +144,43 @@ def test_mutant_is_caught(workdir, monkeypatch, name):
     monkeypatch.setattr(oracle, "_lib", lib)
     failed = run_pins()
     assert failed, f"no pin rejects mutant {name}"
+
+
+# Mutants of the checker itself (oracle.check_invariants, Python): each must let
+# at least one corrupted (D, P) of test_checker_pins through, i.e. the checker's
+# pins notice when the checker is weakened.
+ORACLE_PY = os.path.join(os.path.dirname(oracle.__file__), "__init__.py")
+CHECKER_MUTANTS = {
+    "accept_all": [('    assert D.shape == (n, n) and P.shape == (n, n), "shape"', "    return")],
+    # the sampled reconstruction emptied, and the all-pairs walk and split check dropped
+    "pair_checks_emptied": [("        sample = list(zip(rows[Q].tolist(), J.tolist()))", "        sample = []"),
+                            ("    S, H = path_sums(W, P, rows=rows)", "    S, H = Dr.copy(), np.ones(Dr.shape, dtype=np.int64)"),
+                            ("        assert np.all(np.abs(dval(I, K) + dval(K, J) - dij) <= rtol * dij), \\",
+                             "        assert True, \\")],
+    "canonical_dropped": [('        assert np.all(P[I, K] < K), "P[i][P[i][j]] >= P[i][j] (not canonical)"', ""),
+                          ('        assert np.all(P[K, J] < K), "P[P[i][j]][j] >= P[i][j] (not canonical)"', ""),
+                          ("                assert max(path[1:-1]) == P[i, j], \"P is not the largest interior vertex\"",
+                           "                pass")],
+    "unreachable_label_allowed": [('    assert np.all(Pr[~finD] == -1), "P set on an unreachable pair"', "")],
+}
+
+
+def mutated_oracle(edits):
+    src = open(ORACLE_PY).read()
+    for old, new in edits:
+        assert old in src, f"mutation anchor missing: {old!r}"
+        src = src.replace(old, new)
+    mod = types.ModuleType("oracle_checker_mutant")
+    mod.__file__ = ORACLE_PY
+    exec(compile(src, ORACLE_PY, "exec"), mod.__dict__)
+    return mod
+
+
+def test_checker_unmodified_copy_passes():
+    assert escaped(mutated_oracle([]).check_invariants) == []
+
+
+@pytest.mark.parametrize("name", sorted(CHECKER_MUTANTS))
+def test_checker_mutant_is_caught(name):
+    got = escaped(mutated_oracle(CHECKER_MUTANTS[name]).check_invariants)
+    assert got, f"no corruption gets past checker mutant {name}"
