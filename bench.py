@@ -145,9 +145,34 @@ class EnergyMeter:
         return out
 
 
+def run_stats(step_ms):
+    """mean / min / median of the per-step times (ms) of the timed runs."""
+    import numpy as np
+    a = np.asarray(step_ms, dtype=np.float64)
+    return {"runs": int(a.size), "mean_ms": round(float(a.mean()), 4), "min_ms": round(float(a.min()), 4),
+            "median_ms": round(float(np.median(a)), 4)}
+
+
+def timed_steps(torch, step, steps, warmup):
+    """W untimed warm-ups, then K steps between device synchronizations, each
+    bracketed by events on the current stream.  Returns (seconds for all K, per-step ms)."""
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for i in range(steps):
+        step()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    return ev[0].elapsed_time(ev[steps]) / 1e3, per
+
+
 def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False, config=None, energy=None):
-    """Mean seconds per fw_apsp step (D <- W, P <- -1, all rounds) and last-phase stats.
-    config: (block, tile_m, tile_n, variant, schedule), default the tuned choice."""
+    """Mean seconds per fw_apsp step (D <- W, P <- -1, all rounds), the per-step
+    times and last-phase stats.  config: (block, tile_m, tile_n, variant, schedule),
+    default the tuned choice."""
     import numpy as np
     import workloads
     block, tm, tn, var, sch = config or fw.fw_query_config(DT_CODE[dtype], n, path)
@@ -169,18 +194,12 @@ def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False, config=None,
     if prof:
         fw.fw_prof_read(reset=True)
         fw.fw_prof_enable(True)
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     if energy is not None:
         energy.start()
-    t0.record()
-    for _ in range(steps):
-        step()
-    t1.record()
-    torch.cuda.synchronize()
+    total, per = timed_steps(torch, step, steps, 0)
     if energy is not None:
         energy.result = energy.stop(steps, 2.0 * n ** 3)
-    sec = t0.elapsed_time(t1) / 1e3 / steps
+    sec = total / steps
     stats = None
     if prof:
         fw.fw_prof_enable(False)
@@ -189,10 +208,10 @@ def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False, config=None,
                  "variant": var, "schedule": sch, "updates_per_launch": upd / max(cnt, 1)}
     del Wd, D, P
     torch.cuda.empty_cache()
-    return sec, stats
+    return sec, stats, per
 
 
-def time_batched(fw, torch, steps=3, warmup=1):
+def time_batched(fw, torch, steps=15, warmup=2):
     """The batched workload: 10,000 graphs, n uniform in [16, 512], density uniform in
     [0.1, 1.0), float32 weights in [1, 10], path matrices, one persistent launch."""
     import numpy as np
@@ -207,25 +226,19 @@ def time_batched(fw, torch, steps=3, warmup=1):
         D.copy_(Wd)
         fw.apsp_batched_(D, ns, offs, P)
 
-    for _ in range(warmup):
-        step()
-    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record()
-    for _ in range(steps):
-        step()
-    t1.record()
-    torch.cuda.synchronize()
-    sec = t0.elapsed_time(t1) / 1e3 / steps
+    total, per = timed_steps(torch, step, steps, warmup)
+    sec = total / steps
     flops = 2.0 * float(np.sum(ns.astype(np.float64) ** 3))
     return {"graphs_per_s": round(ns.size / sec, 1), "ms_per_batch": round(sec * 1e3, 3),
-            "gflops": round(flops / sec / 1e9, 2), "batch": int(ns.size), "n_range": [16, 512]}
+            "gflops": round(flops / sec / 1e9, 2), "batch": int(ns.size), "n_range": [16, 512],
+            "timing": run_stats(per)}
 
 
-def time_ooc(fw, torch, n=32768, S=8192, path=False):
+def time_ooc(fw, torch, n=32768, S=8192, path=False, runs=15):
     """Out of core: an n x n float32 complete graph (weights in (0,1)) in pinned host
     memory, through a device budget that holds super-blocks of edge S (n / S
-    super-rounds).  One timed call, transfers included."""
+    super-rounds).  Each timed call (transfers included) starts from the same
+    weights, regenerated into the pinned buffer before it, outside the timing."""
     import numpy as np
     import workloads
     nb = -(-n // S)
@@ -235,19 +248,23 @@ def time_ooc(fw, torch, n=32768, S=8192, path=False):
     H = torch.empty((n, n), dtype=torch.float32, pin_memory=True)
     HP = torch.empty((n, n), dtype=torch.int32, pin_memory=True) if path else None
     Hn = H.numpy()
-    for i0 in range(0, n, 4096):  # the generator writes straight into the pinned rows
-        i1 = min(n, i0 + 4096)
-        workloads.rows(2, n, i0, i1, 1.0, workloads.W_UNIT_OPEN, 0, np.float32, 0, Hn[i0:i1])
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    fw.apsp_ooc_(H, HP, budget)
-    sec = time.perf_counter() - t
+    times = []
+    for _ in range(runs):
+        for i0 in range(0, n, 4096):  # the generator writes straight into the pinned rows
+            i1 = min(n, i0 + 4096)
+            workloads.rows(2, n, i0, i1, 1.0, workloads.W_UNIT_OPEN, 0, np.float32, 0, Hn[i0:i1])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fw.apsp_ooc_(H, HP, budget)
+        times.append(time.perf_counter() - t)
+    sec = sum(times) / len(times)
     return {"n": n, "superblock": S, "device_bytes": budget, "seconds": round(sec, 3),
             "gflops": round(gflops(n, sec), 2), "dtype": "f32", "path": path,
+            "timing": run_stats([t * 1e3 for t in times]),
             "note": "matrix in pinned host memory; host-to-device and device-to-host transfers included"}
 
 
-def time_fwd_bwd(fw, torch, steps=5, warmup=2):
+def time_fwd_bwd(fw, torch, steps=15, warmup=2):
     """Forward (D and P) and forward + backward (dL/dW for G ~ N(0,1)): n = 2048 complete
     graph with float32 weights in [1, 2), and a batch of 256 such graphs at n = 128."""
     import numpy as np
@@ -271,16 +288,9 @@ def time_fwd_bwd(fw, torch, steps=5, warmup=2):
 
         res = {}
         for name, fn in (("fwd", fwd), ("fwd_bwd", fwd_bwd), ("bwd", bwd)):
-            for _ in range(warmup):
-                fn()
-            t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            t0.record()
-            for _ in range(steps):
-                fn()
-            t1.record()
-            torch.cuda.synchronize()
-            res[name + "_ms"] = round(t0.elapsed_time(t1) / steps, 3)
+            total, per = timed_steps(torch, fn, steps, warmup)
+            res[name + "_ms"] = round(total * 1e3 / steps, 3)
+            res[name + "_timing"] = run_stats(per)
         res["ratio"] = round(res["fwd_bwd_ms"] / res["fwd_ms"], 3)
         return res
 
@@ -349,11 +359,143 @@ def cpu_baseline(n, budget_s=15.0):
             "extrapolated_full_run_s": round(dt / total_k * n, 1)}
 
 
+def host_cpu():
+    """CPU model and logical CPU count of the host the oracle runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(), "sched_affinity": len(os.sched_getaffinity(0))}
+
+
+class BackgroundOracle:
+    """A single-thread oracle run in a Python thread (the C call releases the GIL),
+    so that it overlaps GPU timing that needs only the launching thread."""
+
+    def __init__(self, fn):
+        import threading
+        self.result = None
+        self.t = threading.Thread(target=self._run, args=(fn,), daemon=True)
+        self.t.start()
+
+    def _run(self, fn):
+        t = time.perf_counter()
+        fn()
+        self.result = time.perf_counter() - t
+
+    def join(self):
+        self.t.join()
+        return self.result
+
+
+def oracle_c2_4096_single():
+    import numpy as np
+    import oracle
+    import workloads
+    W = workloads.unit_complete(4096, dtype=np.float32, seed=2)
+    return lambda: oracle.fw(W, exact=False, threads=1)
+
+
+def oracle_timings(fw, torch, gpu_secondary, single_thread_s=None, runs=15):
+    """The oracle timed fully on the small workloads, all host cores (and one thread
+    where stated), beside the GPU figure for the same input:
+      C1  n = 512, edge probability 0.5, integer weights in [1, 1000] (int64 loop);
+      C2  n = 4096 complete graph, weights in (0, 1) (float64 loop);
+      C4  the 10,000-graph batch (float64 loop per graph, graphs spread over the
+          cores, one thread each);
+      C5  n = 2048 complete graph, weights in [1, 2): forward (float64 loop) and the
+          path-walk backward (serial), and the 256 x 128 batch likewise."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    import workloads
+    cores = oracle.max_threads()
+    out = {"cores": cores}
+
+    def gpu_ms(W, path=True):
+        Wd = torch.from_numpy(W).cuda()
+        D = torch.empty_like(Wd)
+        P = torch.empty(W.shape, dtype=torch.int32, device="cuda") if path else None
+
+        def step():
+            D.copy_(Wd)
+            fw.apsp_(D, P)
+        total, per = timed_steps(torch, step, runs, 2)
+        return run_stats(per)
+
+    W1 = workloads.int_graph(n=512, p=0.5, wmax=1000, seed=1)
+    g1 = gpu_ms(W1)
+    t = time.perf_counter()
+    oracle.fw(W1)
+    a = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.fw(W1, threads=1)
+    b = time.perf_counter() - t
+    out["C1_n512"] = {"oracle_s_all_cores": round(a, 4), "oracle_s_1_thread": round(b, 4), "gpu": g1,
+                      "speedup_vs_all_cores": round(a * 1e3 / g1["mean_ms"], 1)}
+
+    W2 = workloads.unit_complete(4096, dtype=np.float32, seed=2)
+    g2 = gpu_ms(W2)
+    t = time.perf_counter()
+    oracle.fw(W2, exact=False)
+    a = time.perf_counter() - t
+    out["C2_n4096"] = {"oracle_s_all_cores": round(a, 3), "oracle_gflops_all_cores": round(gflops(4096, a), 2),
+                       "oracle_s_1_thread": round(single_thread_s, 3) if single_thread_s else None,
+                       "oracle_gflops_1_thread": round(gflops(4096, single_thread_s), 3) if single_thread_s else None,
+                       "gpu": g2, "gpu_gflops": round(gflops(4096, g2["mean_ms"] / 1e3), 1),
+                       "speedup_vs_all_cores": round(a * 1e3 / g2["mean_ms"], 1)}
+
+    ns, off, W4 = workloads.batch_graphs(batch=10000, seed=4)
+    graphs = [W4[off[b]:off[b + 1]].reshape(int(ns[b]), int(ns[b])) for b in range(ns.size)]
+    order = np.argsort(-ns)  # largest first, as the GPU queue
+    t = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(lambda b: oracle.fw(graphs[b], exact=False, threads=1), order))
+    a = time.perf_counter() - t
+    gb = (gpu_secondary or {}).get("batched", {})
+    out["C4_batch10000"] = {"oracle_s_all_cores": round(a, 2), "oracle_graphs_per_s": round(ns.size / a, 1),
+                            "gpu_ms": gb.get("ms_per_batch"), "gpu_graphs_per_s": gb.get("graphs_per_s"),
+                            "speedup_vs_all_cores": round(a * 1e3 / gb["ms_per_batch"], 1) if gb else None}
+
+    W5, G5 = workloads.grad_graph(n=2048, seed=5)
+    t = time.perf_counter()
+    D5, P5 = oracle.fw(W5, exact=False)
+    a = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.backward_pathwalk(D5, P5, G5.astype(np.float64))
+    b = time.perf_counter() - t
+    Ws = [workloads.grad_graph(n=128, seed=5, g=g) for g in range(256)]
+    t = time.perf_counter()
+    res = [oracle.fw(w, exact=False) for w, _ in Ws]
+    c = time.perf_counter() - t
+    t = time.perf_counter()
+    for (D, P), (_, G) in zip(res, Ws):
+        oracle.backward_pathwalk(D, P, G.astype(np.float64))
+    d = time.perf_counter() - t
+    fb = (gpu_secondary or {}).get("fwd_bwd", {})
+    out["C5"] = {"n2048": {"oracle_fwd_s": round(a, 3), "oracle_bwd_s": round(b, 3),
+                           "gpu_fwd_ms": fb.get("n2048", {}).get("fwd_ms"),
+                           "gpu_fwd_bwd_ms": fb.get("n2048", {}).get("fwd_bwd_ms")},
+                 "batch256_n128": {"oracle_fwd_s": round(c, 3), "oracle_bwd_s": round(d, 3),
+                                   "gpu_fwd_ms": fb.get("batch256_n128", {}).get("fwd_ms"),
+                                   "gpu_fwd_bwd_ms": fb.get("batch256_n128", {}).get("fwd_bwd_ms")},
+                 "note": "oracle forward on all cores, path-walk backward serial"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=15)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--sec-steps", type=int, default=15, help="timed runs of every secondary figure")
+    ap.add_argument("--no-oracle-timings", action="store_true",
+                    help="skip the full oracle runs on the small workloads")
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--dtype", choices=["f32", "f64", "f16"], default="f32")
     ap.add_argument("--no-path", action="store_true", help="distances only (P = NULL)")
@@ -406,8 +548,8 @@ def main():
           file=sys.stderr, flush=True)
     config = tuple(int(x) for x in args.config.split(",")) if args.config else None
     meter = None if args.no_energy else EnergyMeter(torch)
-    sec, stats = time_apsp(fw, torch, args.n, args.dtype, path, args.steps, args.warmup, prof=True, config=config,
-                           energy=meter)
+    sec, stats, per = time_apsp(fw, torch, args.n, args.dtype, path, args.steps, args.warmup, prof=True,
+                                config=config, energy=meter)
     value = gflops(args.n, sec)
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GFLOPS", "n_gpus": 1,
@@ -420,37 +562,60 @@ def main():
                                + ("distances + path matrix" if path else "distances only"),
                    "n": args.n, "path": path, "block": stats["block"], "tile": stats["tile"],
                    "parallelism": "single GPU"},
+        "timing": run_stats(per),
         "roofline": roofline(args.n, args.dtype, stats, path),
         "energy": meter.result if meter is not None else None,
     }
     calib_copy(out)
+    single = None
+    if not args.no_cpu_baseline and not args.no_oracle_timings:
+        print("[bench] oracle n=4096 on one thread, in the background", file=sys.stderr, flush=True)
+        single = BackgroundOracle(oracle_c2_4096_single())
+    sec_out = None
     if not args.no_secondary:
         sec_out = {}
+        K, Wu = args.sec_steps, args.warmup
         for dt_, pth in (("f64", True), ("f32", False), ("f64", False), ("f16", True), ("f16", False)):
             if dt_ == args.dtype and pth == path:
                 continue
             print(f"[bench] secondary n={args.n} {dt_} path={pth}", file=sys.stderr, flush=True)
-            s, st = time_apsp(fw, torch, args.n, dt_, pth, 2, 1, prof=True)
+            m2 = EnergyMeter(torch) if (dt_ == "f64" and pth and not args.no_energy) else None
+            s, st, p2 = time_apsp(fw, torch, args.n, dt_, pth, K, Wu, prof=True, energy=m2)
             key = f"{dt_}_{'path' if pth else 'dist'}"
             sec_out[key] = {"gflops": round(gflops(args.n, s), 2), "ms_per_step": round(s * 1e3, 2),
-                            "roofline_frac": roofline(args.n, dt_, st, pth)["frac"]}
+                            "timing": run_stats(p2), "roofline_frac": roofline(args.n, dt_, st, pth)["frac"]}
+            if m2 is not None:
+                sec_out[key]["energy"] = dict(m2.result, dtype="f64")
             if dt_ == "f16":
                 sec_out[key]["workload"] = "complete graph, integer weights in [1, 1000] (exact in binary16)"
+        for n2 in (4096, 8192):
+            for dt_ in ("f32", "f64"):
+                print(f"[bench] secondary n={n2} {dt_} path=True", file=sys.stderr, flush=True)
+                s, st, p2 = time_apsp(fw, torch, n2, dt_, True, K, Wu, prof=True)
+                sec_out[f"{dt_}_path_n{n2}"] = {"gflops": round(gflops(n2, s), 2), "ms_per_step": round(s * 1e3, 3),
+                                                "timing": run_stats(p2),
+                                                "roofline_frac": roofline(n2, dt_, st, True)["frac"]}
         print("[bench] secondary out of core n=32768", file=sys.stderr, flush=True)
-        sec_out["ooc_f32_dist"] = time_ooc(fw, torch)
+        sec_out["ooc_f32_dist"] = time_ooc(fw, torch, runs=K)
         print("[bench] secondary out of core n=16384 with the path matrix", file=sys.stderr, flush=True)
-        sec_out["ooc_f32_path"] = time_ooc(fw, torch, n=16384, S=4096, path=True)
+        sec_out["ooc_f32_path"] = time_ooc(fw, torch, n=16384, S=4096, path=True, runs=K)
         print("[bench] secondary batched 10,000 graphs", file=sys.stderr, flush=True)
-        sec_out["batched"] = time_batched(fw, torch)
+        sec_out["batched"] = time_batched(fw, torch, steps=K, warmup=Wu)
         print("[bench] secondary forward + backward", file=sys.stderr, flush=True)
-        sec_out["fwd_bwd"] = time_fwd_bwd(fw, torch)
+        sec_out["fwd_bwd"] = time_fwd_bwd(fw, torch, steps=K, warmup=Wu)
         out["secondary"] = sec_out
     out["paper_context"] = {"note": "best measured GFLOPS over N in {4096..65536}, other hardware",
                             "f32": {"Xeon Phi KNL 7230": 1037, "Titan X (Pascal)": 972},
                             "f64": {"Xeon Phi KNL 7230": 501, "Titan X (Pascal)": 90}}
     if not args.no_cpu_baseline:
+        t1 = single.join() if single is not None else None  # before the all-core runs
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(args.n)
+        out["cpu_baseline"]["host"] = host_cpu()
+        if not args.no_oracle_timings:
+            print("[bench] oracle timings on the small workloads", file=sys.stderr, flush=True)
+            out["cpu_baseline"]["oracle_timings"] = oracle_timings(fw, torch, sec_out, single_thread_s=t1,
+                                                                   runs=args.sec_steps)
     print(json.dumps(out), flush=True)
 
 

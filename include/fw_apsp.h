@@ -195,6 +195,39 @@ fw_status_t fw_apsp_batched_config(fw_dtype_t dt, int32_t batch, const int32_t *
                                    const fw_batched_config_t *cfg, void *stream);
 
 /*
+ * fw_apsp_batched with the vertex counts and offsets in DEVICE memory, for
+ * callers whose batch description is produced on the GPU (same per-graph
+ * semantics and results, paper Sect. 2.2 per graph).
+ *   n_dev    device [batch] int32: vertex count of each graph.
+ *   off_dev  device [batch] int64: element offset of each graph in dist / path
+ *            (an array of batch + 1 offsets, whose last entry is the end, may be
+ *            passed as is; only the first batch entries are read).
+ * The device arrays are read by the launches, so they must stay valid until the
+ * stream reaches this point.  Their values are not seen by the host: a graph
+ * whose n is outside [1, 4096] or whose offset is negative is skipped on the
+ * device (left untouched, no error reported).  The queue (ordered by decreasing
+ * n) is built on the device into a stream-ordered job table of 16 (batch + 1)
+ * bytes.  Every graph runs in the persistent launch (no routing of large
+ * graphs to fw_apsp, which needs n on the host).  FW_F32 and FW_F64.
+ */
+fw_status_t fw_apsp_batched_device(fw_dtype_t dt, int32_t batch, const int32_t *n_dev,
+                                   const int64_t *off_dev, void *dist, int32_t *path, void *stream);
+
+/*
+ * fw_apsp_batched_device for callers that cannot allocate memory (code under
+ * HIP graph capture, tight serving loops): the same launches and results, with
+ * the job table in a static device array of the library (one per GPU, 4 MiB,
+ * held until the process ends) instead of stream-ordered scratch.  Calls no
+ * allocation routine.  batch is at most 262144 (FW_EINVAL above).  Every call on
+ * one GPU uses that GPU's one table: calls that overlap on one GPU (different
+ * streams, or host threads, without ordering between them) race and must not
+ * be issued; calls ordered on one stream are safe (the table is rebuilt by the
+ * first launch of each call).
+ */
+fw_status_t fw_apsp_batched_device_noalloc(fw_dtype_t dt, int32_t batch, const int32_t *n_dev,
+                                           const int64_t *off_dev, void *dist, int32_t *path, void *stream);
+
+/*
  * Gradient of a loss L(D) with respect to the weights W, given the forward
  * outputs.  D is piecewise linear in W: dD[i][j]/dW[u][v] = 1 when edge u->v is
  * on the path P encodes for (i, j), else 0 (the subgradient along that path at
@@ -206,8 +239,12 @@ fw_status_t fw_apsp_batched_config(fw_dtype_t dt, int32_t batch, const int32_t *
  *   grad_dist  device, dL/dD (same layout/type as dist).
  *   grad_w     device, output dL/dW (same layout/type), overwritten.
  * Diagonal and unused edges get 0.  Requires positive off-diagonal weights and
- * a path matrix produced by this library for the same dist.  Contributions
- * are accumulated with atomics, so the last bits may vary between runs.
+ * a path matrix produced by this library for the same dist; a label outside
+ * [-1, n) or a chain of labels that does not end within n steps makes the pair
+ * count as unreachable (no contribution).  Each source's contributions are
+ * summed per column in a fixed order, in double, and rounded once: the result
+ * is the same bit for bit on every run.  Allocates stream-ordered scratch of
+ * 10 bytes per (graph, source, column).
  */
 fw_status_t fw_apsp_backward(fw_dtype_t dt, int64_t n, int32_t batch, const void *dist,
                              const int32_t *path, const void *grad_dist, void *grad_w,
@@ -221,6 +258,16 @@ const char *fw_last_error(void);
 
 /* Library version string. */
 const char *fw_version(void);
+
+/*
+ * Test hook for the error paths.  where = 1: the next fw_apsp / fw_apsp_config
+ * call in the process returns FW_EHIP right after allocating its scratch, before
+ * launching anything; where = 2: the same for the next fw_apsp_batched /
+ * fw_apsp_batched_config call after its job table allocation; 0 clears a pending
+ * request.  The call frees its scratch on its stream like any failing call, so
+ * later calls on that stream run normally.  Host only; launches nothing.
+ */
+void fw_debug_fail_next(int where);
 
 /*
  * Timing hooks for benchmarks.  While enabled, every bulk launch of the

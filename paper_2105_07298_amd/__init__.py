@@ -10,7 +10,7 @@ from __future__ import annotations
 
 from ._lib import (FW_EHIP, FW_EINVAL, FW_ENOMEM, FW_EUNSUPPORTED, FW_F16, FW_F32, FW_F64, FW_OK,  # noqa: F401
                    FW_P4_PANELS, FW_P4_WAVEROWS, FW_SCHED_LOOKAHEAD, FW_SCHED_PAIRS, FW_SCHED_PAIRS_LOOKAHEAD, FW_SCHED_SERIAL, FwError, fw_apsp, fw_apsp_backward, fw_apsp_batched,
-                   fw_apsp_batched_config, fw_apsp_config, fw_apsp_ooc, fw_last_error, fw_list_configs, fw_ooc_superblock,
+                   fw_apsp_batched_config, fw_apsp_batched_device, fw_apsp_batched_device_noalloc, fw_apsp_config, fw_apsp_ooc, fw_last_error, fw_list_configs, fw_ooc_superblock,
                    fw_prof_enable,
                    fw_prof_read, fw_query_config, fw_status_string, fw_version, lib, lookahead_applies,
                    pairs_applies, pairs_lookahead_applies)
@@ -126,6 +126,29 @@ def apsp_batched(Wcat, ns, offsets, path: bool = True, small_max_n: int = -1, ro
     D = Wcat.contiguous().clone()
     P = torch.empty(D.shape, dtype=torch.int32, device=D.device) if path else None
     return apsp_batched_(D, ns, offsets, P, small_max_n, route)
+
+
+def apsp_batched_device_(Dcat, n_dev, off_dev, Pcat=None):
+    """apsp_batched_ with the vertex counts (int32) and element offsets (int64) as
+    1-D device tensors of length batch, read by the library on the device; every
+    graph runs in the persistent launch.  Graphs with n outside [1, 4096] or a
+    negative offset are skipped on the device (left untouched)."""
+    import torch
+    if not (n_dev.is_cuda and n_dev.dtype == torch.int32 and n_dev.dim() == 1 and n_dev.is_contiguous()):
+        raise ValueError("n_dev must be a contiguous 1-D int32 device tensor")
+    if not (off_dev.is_cuda and off_dev.dtype == torch.int64 and off_dev.dim() == 1 and off_dev.is_contiguous()
+            and off_dev.numel() >= n_dev.numel()):
+        raise ValueError("off_dev must be a contiguous 1-D int64 device tensor with at least batch entries")
+    if not (Dcat.is_cuda and Dcat.dim() == 1 and Dcat.is_contiguous()):
+        raise ValueError("Dcat must be a contiguous 1-D device tensor")
+    pp = None
+    if Pcat is not None:
+        if not (Pcat.is_cuda and Pcat.dtype == torch.int32 and Pcat.shape == Dcat.shape and Pcat.is_contiguous()):
+            raise ValueError("Pcat must be a contiguous int32 device tensor shaped like Dcat")
+        pp = Pcat.data_ptr()
+    fw_apsp_batched_device(_dtype_code(Dcat), int(n_dev.numel()), n_dev.data_ptr(), off_dev.data_ptr(),
+                           Dcat.data_ptr(), pp, _stream_ptr(Dcat.device))
+    return Dcat, Pcat
 
 
 def apsp_backward(D, P, G):

@@ -17,9 +17,10 @@ FW_P4_PANELS, FW_P4_WAVEROWS = 1, 2
 FW_SCHED_SERIAL, FW_SCHED_LOOKAHEAD, FW_SCHED_PAIRS, FW_SCHED_PAIRS_LOOKAHEAD = 1, 2, 3, 4
 
 EXPORTS = ("fw_apsp", "fw_apsp_config", "fw_query_config", "fw_list_configs", "fw_apsp_ooc", "fw_ooc_superblock",
-           "fw_apsp_batched", "fw_apsp_batched_config",
+           "fw_apsp_batched", "fw_apsp_batched_config", "fw_apsp_batched_device", "fw_apsp_batched_device_noalloc",
            "fw_apsp_backward",
-           "fw_status_string", "fw_last_error", "fw_version", "fw_prof_enable", "fw_prof_read")
+           "fw_status_string", "fw_last_error", "fw_version", "fw_prof_enable", "fw_prof_read",
+           "fw_debug_fail_next")
 
 
 class FwConfig(ctypes.Structure):
@@ -64,7 +65,10 @@ def lib():
     L.fw_apsp_batched.argtypes = [ctypes.c_int, i32, vp, vp, vp, vp, vp]
     L.fw_apsp_batched_config.argtypes = [ctypes.c_int, i32, vp, vp, vp, vp, ctypes.POINTER(FwBatchedConfig), vp]
     L.fw_apsp_backward.argtypes = [ctypes.c_int, i64, i32, vp, vp, vp, vp, vp]
-    for f in ("fw_apsp", "fw_apsp_config", "fw_apsp_batched", "fw_apsp_batched_config", "fw_apsp_backward"):
+    L.fw_apsp_batched_device.argtypes = [ctypes.c_int, i32, vp, vp, vp, vp, vp]
+    L.fw_apsp_batched_device_noalloc.argtypes = [ctypes.c_int, i32, vp, vp, vp, vp, vp]
+    for f in ("fw_apsp", "fw_apsp_config", "fw_apsp_batched", "fw_apsp_batched_config", "fw_apsp_backward",
+              "fw_apsp_batched_device", "fw_apsp_batched_device_noalloc"):
         getattr(L, f).restype = ctypes.c_int
     L.fw_status_string.argtypes = [ctypes.c_int]
     L.fw_status_string.restype = ctypes.c_char_p
@@ -73,6 +77,8 @@ def lib():
     L.fw_prof_enable.argtypes = [ctypes.c_int]
     L.fw_prof_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), ctypes.c_int]
     L.fw_prof_read.restype = ctypes.c_int
+    L.fw_debug_fail_next.argtypes = [ctypes.c_int]
+    L.fw_debug_fail_next.restype = None
     _lib = L
     return L
 
@@ -132,6 +138,17 @@ def fw_apsp_batched_config(dt, batch, n_host, off_host, dist, path, small_max_n=
     cfg = FwBatchedConfig(small_max_n, route, 0, 0)
     _check(lib().fw_apsp_batched_config(dt, batch, n_host, off_host, dist, path, ctypes.byref(cfg), stream),
            "fw_apsp_batched_config")
+
+
+def fw_apsp_batched_device(dt, batch, n_dev, off_dev, dist, path, stream=None):
+    """n_dev / off_dev: device pointers (int32 counts, int64 offsets)."""
+    _check(lib().fw_apsp_batched_device(dt, batch, n_dev, off_dev, dist, path, stream), "fw_apsp_batched_device")
+
+
+def fw_apsp_batched_device_noalloc(dt, batch, n_dev, off_dev, dist, path, stream=None):
+    """As fw_apsp_batched_device, with the library's static job table (no allocation)."""
+    _check(lib().fw_apsp_batched_device_noalloc(dt, batch, n_dev, off_dev, dist, path, stream),
+           "fw_apsp_batched_device_noalloc")
 
 
 def fw_apsp_backward(dt, n, batch, dist, path, grad_dist, grad_w, stream=None):

@@ -9,7 +9,7 @@
 // pred_i(j) -> j.  Hence, with S(j) = G[i][j] + sum of S over j's children,
 // source i contributes S(j) to dL/dW[pred_i(j)][j] for every j it reaches.
 //
-// One workgroup per (graph, source):
+// k_backward_tree, one workgroup per (graph, source i):
 //   1. pred_i(j): the last edge of path(i, j) is the last edge of
 //      path(P[i][j], j), so follow a <- P[a][j] from a = i while it is >= 0; the
 //      vertex reached is pred_i(j).
@@ -17,10 +17,19 @@
 //      level by level.
 //   3. subtree sums, deepest level first: every vertex of a level adds its sum
 //      to its parent's (LDS atomics, double); a level is complete before the
-//      next shallower one starts.
-//   4. scatter S(j) into dL/dW[pred_i(j)][j] with global atomics (sources share
-//      edges).  The order of the additions is not fixed, so the last bits of
-//      the result may differ between runs.
+//      next shallower one starts.  Within one level every vertex is a child of
+//      a vertex one level up, and a parent's sum is read only after its level
+//      is complete, so S(j) is exact up to the order in which a vertex's
+//      children are added.
+//   4. row i of two scratch matrices: U[i][j] = pred_i(j) (-1 where source i
+//      contributes nothing to column j) and S[i][j] = S(j) in double.
+// k_backward_columns, one wave per (graph, column j): dL/dW[u][j] is the sum of
+// S[i][j] over the sources i with U[i][j] = u.  The wave takes the sources 64 at
+// a time; lanes with equal u are summed in lane order by the lowest of them,
+// which then adds the group's sum to an LDS accumulator per u.  Every addition
+// happens in an order fixed by (i, lane), so the gradient is the same bit for
+// bit from run to run (no atomics), and it is accumulated in double before the
+// one rounding to T.
 #include "fw_internal.h"
 
 namespace fw {
@@ -32,16 +41,11 @@ template <typename T> __device__ __forceinline__ T inf_w();
 template <> __device__ __forceinline__ float inf_w<float>() { return __builtin_inff(); }
 template <> __device__ __forceinline__ double inf_w<double>() { return __builtin_inf(); }
 
-template <typename T>
-__global__ void k_zero(T *p, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = (T)0;
-}
-
 // LDS layout (dynamic): S double[n], pred int16[n], depth int16[n].
 template <typename T>
-__global__ void __launch_bounds__(NT) k_backward(const T *__restrict__ D, const int32_t *__restrict__ P,
-                                                const T *__restrict__ G, T *__restrict__ gW, int n) {
+__global__ void __launch_bounds__(NT) k_backward_tree(const T *__restrict__ D, const int32_t *__restrict__ P,
+                                                     const T *__restrict__ G, int16_t *__restrict__ U,
+                                                     double *__restrict__ SV, int n) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     double *S = (double *)lds;
     int16_t *pred = (int16_t *)(S + n);
@@ -107,27 +111,76 @@ __global__ void __launch_bounds__(NT) k_backward(const T *__restrict__ D, const 
             if (depth[j] == lev) atomicAdd(&S[pred[j]], S[j]);
         __syncthreads();
     }
-    // 4. scatter into dL/dW.
-    T *gWb = gW + base;
-    for (int j = threadIdx.x; j < n; j += NT)
-        if (depth[j] >= 1) atomicAdd(&gWb[(int64_t)pred[j] * n + j], (T)S[j]);
+    // 4. this source's row of the (pred, subtree sum) scratch.
+    const int64_t row = base + (int64_t)i * n;
+    for (int j = threadIdx.x; j < n; j += NT) {
+        U[row + j] = depth[j] >= 1 ? pred[j] : (int16_t)-1;
+        SV[row + j] = S[j];
+    }
+}
+
+// One wave per (graph, column j); LDS: acc double[n].  Consecutive workgroups
+// are dispatched round-robin over the 8 XCDs, so workgroup x takes column
+// (x mod 8) * per + x / 8: each XCD walks a contiguous range of columns, whose
+// strided reads of U and S share cache lines in that XCD's L2.
+template <typename T>
+__global__ void __launch_bounds__(64) k_backward_columns(const int16_t *__restrict__ U, const double *__restrict__ SV,
+                                                        T *__restrict__ gW, int n, int per) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    double *acc = (double *)lds;
+    const int x = blockIdx.x;
+    const int j = (x % 8) * per + x / 8;
+    if (j >= n) return;
+    const int lane = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.y * n * n;
+    for (int u = lane; u < n; u += 64) acc[u] = 0.0;
+    __syncthreads();
+    for (int i0 = 0; i0 < n; i0 += 64) {
+        const int i = i0 + lane;
+        int u = -1;
+        double s = 0.0;
+        if (i < n) {
+            u = U[base + (int64_t)i * n + j];
+            s = SV[base + (int64_t)i * n + j];
+        }
+        const uint64_t sb = __builtin_bit_cast(uint64_t, s);
+        const int slo = (int)(uint32_t)sb, shi = (int)(uint32_t)(sb >> 32);
+        double sum = 0.0;
+        bool leader = true;
+#pragma unroll 8
+        for (int l = 0; l < 64; ++l) {
+            const int ul = __builtin_amdgcn_readlane(u, l);
+            const uint64_t bl = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(shi, l) << 32) |
+                                (uint32_t)__builtin_amdgcn_readlane(slo, l);
+            const bool same = ul == u;
+            sum += same ? __builtin_bit_cast(double, bl) : 0.0;
+            leader = leader && !(same && l < lane);
+        }
+        if (leader && u >= 0) acc[u] += sum;  // one leader per u in this group of sources
+        __syncthreads();
+    }
+    for (int u = lane; u < n; u += 64) gW[base + (int64_t)u * n + j] = (T)acc[u];
 }
 
 }  // namespace
 
 template <typename T>
-hipError_t launch_backward(const T *D, const int32_t *P, const T *G, T *gW, int n, int batch, hipStream_t s) {
-    const int64_t total = (int64_t)n * n * batch;
-    int64_t gz = (total + NT - 1) / NT;
-    hipLaunchKernelGGL((k_zero<T>), dim3((unsigned)(gz < 8192 ? gz : 8192)), dim3(NT), 0, s, gW, total);
+hipError_t launch_backward(const T *D, const int32_t *P, const T *G, T *gW, int n, int batch, void *scratch,
+                           hipStream_t s) {
+    int16_t *U = (int16_t *)scratch;
+    double *SV = (double *)((char *)scratch + backward_scratch_split(n, batch));
     const size_t lds = (size_t)n * (sizeof(double) + 2 * sizeof(int16_t));
-    hipLaunchKernelGGL((k_backward<T>), dim3((unsigned)n, (unsigned)batch), dim3(NT), lds, s, D, P, G, gW, n);
+    hipLaunchKernelGGL((k_backward_tree<T>), dim3((unsigned)n, (unsigned)batch), dim3(NT), lds, s, D, P, G, U, SV,
+                       n);
+    const int per = (n + 7) / 8;
+    hipLaunchKernelGGL((k_backward_columns<T>), dim3((unsigned)(8 * per), (unsigned)batch), dim3(64),
+                       (size_t)n * sizeof(double), s, U, SV, gW, n, per);
     return hipGetLastError();
 }
 
-template hipError_t launch_backward<float>(const float *, const int32_t *, const float *, float *, int, int,
+template hipError_t launch_backward<float>(const float *, const int32_t *, const float *, float *, int, int, void *,
                                            hipStream_t);
 template hipError_t launch_backward<double>(const double *, const int32_t *, const double *, double *, int, int,
-                                            hipStream_t);
+                                            void *, hipStream_t);
 
 }  // namespace fw

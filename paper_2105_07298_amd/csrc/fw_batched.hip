@@ -32,6 +32,8 @@
 #include "fw_internal.h"
 #include "fw_lex.h"
 
+#include <mutex>
+
 namespace fw {
 namespace {
 
@@ -382,15 +384,15 @@ constexpr int batched_wgs_per_cu() {
     return w < 1 ? 1 : (w > 4 ? 4 : w);
 }
 
-// Persistent batched kernel.  jobs[0] holds the queue counter (set to 0 by the
-// host copy that uploads the table); jobs[1 + 2q], jobs[2 + 2q] = offset and n
-// of queue slot q.  A graph uses 64 x 64 tiles when n > small_max_n (from the
-// tuning table) and 64-tiles pad it to no more vertices than 32-tiles would
+// Persistent batched kernel.  jobs[0] holds the queue counter (0 when the launch
+// starts), jobs[1] the number of jobs, and jobs[2 + 2q], jobs[3 + 2q] the offset
+// and n of queue slot q.  A graph uses 64 x 64 tiles when n > small_max_n (from
+// the tuning table) and 64-tiles pad it to no more vertices than 32-tiles would
 // (n mod 64 = 0 or > 32); otherwise 32 x 32 tiles.  Both share the LDS arrays,
 // sized for 64.
 template <typename T, bool PATH>
 __global__ void __launch_bounds__(NT, (batched_wgs_per_cu<T, PATH>())) k_batched(T *__restrict__ dist, int32_t *__restrict__ path,
-                                               int64_t *__restrict__ jobs, int njobs, int small_max_n) {
+                                               int64_t *__restrict__ jobs, int small_max_n) {
     constexpr int ST = Graph<T, 64, PATH>::ST;
     __shared__ __attribute__((aligned(16))) T sa[64 * ST];
     __shared__ __attribute__((aligned(16))) T sb[64 * ST];
@@ -398,16 +400,17 @@ __global__ void __launch_bounds__(NT, (batched_wgs_per_cu<T, PATH>())) k_batched
     __shared__ __attribute__((aligned(16))) uint16_t lb[PATH ? 64 * ST : 8];
     __shared__ int s_job;
     unsigned long long *counter = (unsigned long long *)jobs;
+    const int njobs = __builtin_amdgcn_readfirstlane((int)jobs[1]);
     for (;;) {
         if (threadIdx.x == 0) s_job = (int)atomicAdd(counter, 1ull);
         __syncthreads();
         const int q = __builtin_amdgcn_readfirstlane(s_job);  // uniform: graph bases in scalar registers
         __syncthreads();
         if (q >= njobs) return;
-        const int64_t off0 = jobs[1 + 2 * q];
+        const int64_t off0 = jobs[2 + 2 * q];
         const int64_t off = ((int64_t)__builtin_amdgcn_readfirstlane((int)(off0 >> 32)) << 32) |
                             (uint32_t)__builtin_amdgcn_readfirstlane((int)off0);
-        const int n = __builtin_amdgcn_readfirstlane((int)jobs[2 + 2 * q]);
+        const int n = __builtin_amdgcn_readfirstlane((int)jobs[3 + 2 * q]);
         const bool small = (n <= small_max_n) || (((n + 63) & ~63) != ((n + 31) & ~31));
         if (small) {
             Graph<T, 32, PATH> g{dist + off, PATH ? path + off : nullptr, n};
@@ -419,16 +422,104 @@ __global__ void __launch_bounds__(NT, (batched_wgs_per_cu<T, PATH>())) k_batched
     }
 }
 
+// Job table from device arrays of vertex counts nv[batch] and element offsets
+// off[batch], in the layout k_batched reads: [0] the queue counter (set to 0),
+// [1] the number of jobs, then (offset, n) per queue slot in order of
+// decreasing n (longest job first).  A graph whose n is outside [1, BJ_MAXN] or
+// whose offset is negative gets no slot (it is not solved and not touched).
+// One workgroup, a counting sort on n: a histogram in LDS, its exclusive scan
+// from the largest n down, then every graph takes the next slot of its n (the
+// order among graphs of equal n is arbitrary; each is solved independently).
+constexpr int BJ_NT = 1024, BJ_MAXN = 4096, BJ_PER = BJ_MAXN / BJ_NT;
+__global__ void __launch_bounds__(BJ_NT) k_build_jobs(const int32_t *__restrict__ nv, const int64_t *__restrict__ off,
+                                                     int batch, int64_t *__restrict__ jobs) {
+    __shared__ int cnt[BJ_MAXN + 1];
+    __shared__ int part[BJ_NT];
+    const int t = threadIdx.x;
+    for (int x = t; x <= BJ_MAXN; x += BJ_NT) cnt[x] = 0;
+    __syncthreads();
+    for (int b = t; b < batch; b += BJ_NT) {
+        const int n = nv[b];
+        if (n >= 1 && n <= BJ_MAXN && off[b] >= 0) atomicAdd(&cnt[n], 1);
+    }
+    __syncthreads();
+    // Thread t owns bins n = BJ_MAXN - BJ_PER t - q, q < BJ_PER (n = 1 .. BJ_MAXN
+    // from thread BJ_NT - 1 up to thread 0); an inclusive scan of the per-thread
+    // sums (Hillis-Steele in LDS) gives each thread the count of larger n.
+    int local[BJ_PER], sum = 0;
+#pragma unroll
+    for (int q = 0; q < BJ_PER; ++q) {
+        local[q] = cnt[BJ_MAXN - BJ_PER * t - q];
+        sum += local[q];
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int d = 1; d < BJ_NT; d <<= 1) {
+        const int v = t >= d ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - sum;
+#pragma unroll
+    for (int q = 0; q < BJ_PER; ++q) {
+        cnt[BJ_MAXN - BJ_PER * t - q] = run;  // first slot of this n
+        run += local[q];
+    }
+    if (t == BJ_NT - 1) {
+        jobs[0] = 0;
+        jobs[1] = part[t];
+    }
+    __syncthreads();
+    for (int b = t; b < batch; b += BJ_NT) {
+        const int n = nv[b];
+        const int64_t o = off[b];
+        if (n >= 1 && n <= BJ_MAXN && o >= 0) {
+            const int slot = atomicAdd(&cnt[n], 1);
+            jobs[2 + 2 * slot] = o;
+            jobs[3 + 2 * slot] = n;
+        }
+    }
+}
+
+// The job table of fw_apsp_batched_device_noalloc, for callers that cannot
+// allocate: one per GPU, held until the process ends.  Host code never passes
+// the array's name to a kernel: each device's address comes from
+// hipGetSymbolAddress (noalloc_jobs below).
+static __device__ __align__(256) int64_t scratch[2 + 2 * (size_t)kNoAllocMaxBatch];
+
 }  // namespace
 
 template <typename T>
-hipError_t launch_batched(T *dist, int32_t *path, int64_t *jobs, int njobs, int small_max_n, int grid,
-                          hipStream_t s) {
+hipError_t launch_batched(T *dist, int32_t *path, int64_t *jobs, int small_max_n, int grid, hipStream_t s) {
     if (path)
-        hipLaunchKernelGGL((k_batched<T, true>), dim3(grid), dim3(NT), 0, s, dist, path, jobs, njobs, small_max_n);
+        hipLaunchKernelGGL((k_batched<T, true>), dim3(grid), dim3(NT), 0, s, dist, path, jobs, small_max_n);
     else
-        hipLaunchKernelGGL((k_batched<T, false>), dim3(grid), dim3(NT), 0, s, dist, path, jobs, njobs, small_max_n);
+        hipLaunchKernelGGL((k_batched<T, false>), dim3(grid), dim3(NT), 0, s, dist, path, jobs, small_max_n);
     return hipGetLastError();
+}
+
+hipError_t launch_build_jobs(const int32_t *nv, const int64_t *off, int batch, int64_t *jobs, hipStream_t s) {
+    hipLaunchKernelGGL(k_build_jobs, dim3(1), dim3(BJ_NT), 0, s, nv, off, batch, jobs);
+    return hipGetLastError();
+}
+
+// Device address of `scratch` on the current device, looked up once per device
+// (with that device current) and kept; later calls only read the table.
+hipError_t noalloc_jobs(int dev, int64_t **out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static int64_t *addr[kMaxDevices] = {};
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = (int64_t *)p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 template <typename T>
@@ -441,7 +532,7 @@ int batched_occupancy(bool path) {
 
 template int batched_occupancy<float>(bool);
 template int batched_occupancy<double>(bool);
-template hipError_t launch_batched<float>(float *, int32_t *, int64_t *, int, int, int, hipStream_t);
-template hipError_t launch_batched<double>(double *, int32_t *, int64_t *, int, int, int, hipStream_t);
+template hipError_t launch_batched<float>(float *, int32_t *, int64_t *, int, int, hipStream_t);
+template hipError_t launch_batched<double>(double *, int32_t *, int64_t *, int, int, hipStream_t);
 
 }  // namespace fw

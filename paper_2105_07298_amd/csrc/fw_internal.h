@@ -66,13 +66,24 @@ template <typename T>
 hipError_t launch_resolve(const T *D, T *DT, const uint16_t *L, int32_t *P, int64_t ld, int block, hipStream_t s);
 
 // Persistent batched launch (one workgroup per graph at a time).  jobs is a
-// device table of 1 + 2*njobs int64: [0] the queue counter (must be 0), then
-// (element offset, n) per queue slot in processing order.  Graphs with
-// n <= small_max_n, or that 64-tiles would pad further than 32-tiles, use
+// device table of 2 + 2*njobs int64: [0] the queue counter (must be 0), [1]
+// njobs, then (element offset, n) per queue slot in processing order.  Graphs
+// with n <= small_max_n, or that 64-tiles would pad further than 32-tiles, use
 // 32 x 32 tiles; the others 64 x 64.
 template <typename T>
-hipError_t launch_batched(T *dist, int32_t *path, int64_t *jobs, int njobs, int small_max_n, int grid,
-                          hipStream_t s);
+hipError_t launch_batched(T *dist, int32_t *path, int64_t *jobs, int small_max_n, int grid, hipStream_t s);
+
+// The same table built on the device from device arrays nv[batch] (vertex
+// counts) and off[batch] (element offsets), ordered by decreasing n; graphs
+// with n outside [1, 4096] or a negative offset are left out.  jobs holds
+// 2 + 2*batch int64.
+hipError_t launch_build_jobs(const int32_t *nv, const int64_t *off, int batch, int64_t *jobs, hipStream_t s);
+
+// Largest batch of fw_apsp_batched_device_noalloc, whose job table is a static
+// device array (2 + 2*kNoAllocMaxBatch int64 = 4 MiB per GPU), and that array's
+// address on device dev (looked up on the first call with dev current).
+constexpr int kNoAllocMaxBatch = 262144;
+hipError_t noalloc_jobs(int dev, int64_t **out);
 
 // Workgroups of the batched kernel that fit on one CU at once.
 template <typename T>
@@ -83,10 +94,19 @@ int batched_occupancy(bool path);
 TileCfg tuned_config(int dtype, bool path, int64_t n);  // dtype: an fw_dtype_t code
 int tuned_batched_small_max_n(bool f64, bool path);
 
-// Gradient dL/dW (zeroed here) from (D, P) and G = dL/dD for batch graphs of n
-// vertices each (contiguous, stride n*n), n <= 4096.
+// Gradient dL/dW (every entry written) from (D, P) and G = dL/dD for batch
+// graphs of n vertices each (contiguous, stride n*n), n <= 4096.  scratch holds
+// backward_scratch_bytes(n, batch) bytes: per (graph, source, column) the
+// predecessor (int16) and the subtree sum (double).
+inline size_t backward_scratch_split(int n, int batch) {  // bytes of the int16 part, 256-aligned
+    return ((size_t)n * n * batch * sizeof(int16_t) + 255) / 256 * 256;
+}
+inline size_t backward_scratch_bytes(int n, int batch) {
+    return backward_scratch_split(n, batch) + (size_t)n * n * batch * sizeof(double);
+}
 template <typename T>
-hipError_t launch_backward(const T *D, const int32_t *P, const T *G, T *gW, int n, int batch, hipStream_t s);
+hipError_t launch_backward(const T *D, const int32_t *P, const T *G, T *gW, int n, int batch, void *scratch,
+                           hipStream_t s);
 
 // C <- min(C, A (x) B): C is M x N (leading dimension ldc), A is M x K (lda), B
 // is K x N (ldb); M, N, K multiples of 64, pointers and leading dimensions

@@ -79,13 +79,18 @@ __device__ __forceinline__ _Float16 vmin(_Float16 a, _Float16 b) { return __buil
 // candidate for them equals the current value with a label that is not
 // smaller), hence updating in place while other threads read them is safe; one
 // barrier per k orders step k's writes before step k+1's reads.  The k-steps
-// are a dependent chain on one CU, so the block runs with P1_TS x P1_TS = 1024
-// threads (few entries each) to keep every SIMD busy within a step.
-constexpr int P1_TS = 32;
-template <typename T, int TB, bool PATH>
-__global__ void __launch_bounds__(P1_TS *P1_TS) k_phase1(T *__restrict__ D, int32_t *__restrict__ P,
-                                                        uint16_t *__restrict__ L, int64_t ld, int r) {
-    constexpr int TS = P1_TS, RM = TB / TS, ST = TB + 1;
+// are a dependent chain on one CU; the block runs with TS x TS threads: 1024
+// (few entries each, every SIMD busy within a step) or 256 (one wave per SIMD).
+// The 256-thread form is the one that fits on a CU beside the last phase's
+// workgroups when it runs concurrently with them (the lookahead schedules):
+// 1024 threads need four waves on every SIMD of one CU, i.e. a CU from which
+// every last-phase workgroup has left.
+template <typename T> constexpr int p1_ts() { return sizeof(T) == 8 ? 16 : 32; }
+template <typename T, int TB, bool PATH, int TS>
+__global__ void __launch_bounds__(TS *TS) k_phase1(T *__restrict__ D, int32_t *__restrict__ P,
+                                                  uint16_t *__restrict__ L, int64_t ld, int r) {
+    constexpr int RM = TB / TS, ST = TB + 1;
+    static_assert(RM * TS == TB, "phase 1 thread layout");
     __shared__ T sd[TB * ST];
     __shared__ uint32_t sp[PATH ? TB * ST : 1];  // labels + 1
     const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
@@ -956,10 +961,11 @@ template <typename T, int TB>
 void launch_p123(T *D, int32_t *P, uint16_t *L, int64_t ld, int r, hipStream_t s) {
     const int nb = (int)(ld / TB);
     const bool path = P != nullptr;
+    constexpr int TS = TB < p1_ts<T>() ? TB : p1_ts<T>();
     if (path)
-        hipLaunchKernelGGL((k_phase1<T, TB, true>), dim3(1), dim3(P1_TS * P1_TS), 0, s, D, P, L, ld, r);
+        hipLaunchKernelGGL((k_phase1<T, TB, true, TS>), dim3(1), dim3(TS * TS), 0, s, D, P, L, ld, r);
     else
-        hipLaunchKernelGGL((k_phase1<T, TB, false>), dim3(1), dim3(P1_TS * P1_TS), 0, s, D, P, L, ld, r);
+        hipLaunchKernelGGL((k_phase1<T, TB, false, TS>), dim3(1), dim3(TS * TS), 0, s, D, P, L, ld, r);
     if (nb == 1) return;
     if (path)
         hipLaunchKernelGGL((k_phase23<T, TB, true>), dim3(2 * (nb - 1)), dim3(NT), 0, s, D, P, L, ld, r, nb);

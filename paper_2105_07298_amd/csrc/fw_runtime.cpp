@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -218,6 +219,35 @@ hipError_t run_rounds(T *D, int32_t *P, uint16_t *L, int64_t ld, fw::TileCfg cfg
     return e;
 }
 
+// Test hook (fw_debug_fail_next): the next call of the named entry point
+// returns an injected error right after its scratch allocations, through the
+// same clean-up path as a real failure.
+std::atomic<int> g_fail_next{0};
+bool take_injected_failure(int where) {
+    int expect = where;
+    return where != 0 && g_fail_next.compare_exchange_strong(expect, 0);
+}
+
+// Stream-ordered scratch of one call, freed on the caller's stream on every
+// return path (hipFreeAsync is ordered after the launches that use it).
+struct StreamScratch {
+    hipStream_t s;
+    void *p[2] = {nullptr, nullptr};
+    explicit StreamScratch(hipStream_t st) : s(st) {}
+    hipError_t alloc(int slot, size_t bytes) { return hipMallocAsync(&p[slot], bytes, s); }
+    hipError_t release() {
+        hipError_t first = hipSuccess;
+        for (void *&q : p) {
+            if (!q) continue;
+            hipError_t e = hipFreeAsync(q, s);
+            if (first == hipSuccess) first = e;
+            q = nullptr;
+        }
+        return first;
+    }
+    ~StreamScratch() { (void)release(); }
+};
+
 template <typename T>
 fw_status_t run_apsp(int64_t n, T *dist, int32_t *path, fw::TileCfg cfg, hipStream_t s) {
     if (!fw::config_supported<T>(cfg))
@@ -229,40 +259,38 @@ fw_status_t run_apsp(int64_t n, T *dist, int32_t *path, fw::TileCfg cfg, hipStre
     hipError_t e;
     T *D = dist;
     int32_t *P = path;
-    void *scratch = nullptr;
-    if (npad != n || !aligned) {
+    StreamScratch scr(s);  // [0] padded copies, [1] path-mode marks and transpose
+    const bool padded = npad != n || !aligned;
+    if (padded) {
         const size_t dbytes = (size_t)(npad * npad) * sizeof(T);
         const size_t pbytes = path ? (size_t)(npad * npad) * sizeof(int32_t) : 0;
-        e = hipMallocAsync(&scratch, dbytes + pbytes, s);
-        if (e != hipSuccess) return fail(FW_ENOMEM, "scratch of %zu bytes: %s", dbytes + pbytes, hipGetErrorString(e));
-        D = (T *)scratch;
-        P = path ? (int32_t *)((char *)scratch + dbytes) : nullptr;
-        if ((e = fw::launch_pad_in<T>(dist, n, D, npad, s)) != hipSuccess) return hip_fail(e, "pad");
+        if ((e = scr.alloc(0, dbytes + pbytes)) != hipSuccess)
+            return fail(FW_ENOMEM, "scratch of %zu bytes: %s", dbytes + pbytes, hipGetErrorString(e));
+        D = (T *)scr.p[0];
+        P = path ? (int32_t *)((char *)scr.p[0] + dbytes) : nullptr;
     }
-    if (P && (e = fw::launch_fill_i32(P, npad * npad, -1, s)) != hipSuccess) return hip_fail(e, "path init");
     // Path mode scratch: pending marks L (uint16, zeroed), then the transpose of
     // D for the label resolution.
-    void *ps = nullptr;
     uint16_t *L = nullptr;
     const size_t lbytes = (size_t)(npad * npad) * sizeof(uint16_t), tbytes = (size_t)(npad * npad) * sizeof(T);
     if (P) {
-        e = hipMallocAsync(&ps, lbytes + tbytes, s);
-        if (e != hipSuccess) return fail(FW_ENOMEM, "label scratch of %zu bytes: %s", lbytes + tbytes, hipGetErrorString(e));
-        L = (uint16_t *)ps;
-        if ((e = fw::launch_fill_i32((int32_t *)L, npad * npad / 2, 0, s)) != hipSuccess) return hip_fail(e, "mark init");
+        if ((e = scr.alloc(1, lbytes + tbytes)) != hipSuccess)
+            return fail(FW_ENOMEM, "label scratch of %zu bytes: %s", lbytes + tbytes, hipGetErrorString(e));
+        L = (uint16_t *)scr.p[1];
     }
+    if (take_injected_failure(1)) return fail(FW_EHIP, "injected failure after the scratch allocations");
+    if (padded && (e = fw::launch_pad_in<T>(dist, n, D, npad, s)) != hipSuccess) return hip_fail(e, "pad");
+    if (P && (e = fw::launch_fill_i32(P, npad * npad, -1, s)) != hipSuccess) return hip_fail(e, "path init");
+    if (L && (e = fw::launch_fill_i32((int32_t *)L, npad * npad / 2, 0, s)) != hipSuccess)
+        return hip_fail(e, "mark init");
     if ((e = run_rounds<T>(D, P, L, npad, cfg, s)) != hipSuccess) return hip_fail(e, "round launch");
-    if (P) {
-        e = fw::launch_resolve<T>(D, (T *)((char *)ps + lbytes), L, P, npad, cfg.block, s);
-        hipError_t e2 = hipFreeAsync(ps, s);
-        if (e != hipSuccess) return hip_fail(e, "label resolution");
-        if (e2 != hipSuccess) return hip_fail(e2, "label scratch free");
-    }
-    if (scratch) {
+    if (P && (e = fw::launch_resolve<T>(D, (T *)((char *)scr.p[1] + lbytes), L, P, npad, cfg.block, s)) != hipSuccess)
+        return hip_fail(e, "label resolution");
+    if (padded) {
         if ((e = fw::launch_pad_out<T>(D, npad, dist, n, s)) != hipSuccess) return hip_fail(e, "unpad");
         if (path && (e = fw::launch_pad_out<int32_t>(P, npad, path, n, s)) != hipSuccess) return hip_fail(e, "unpad P");
-        if ((e = hipFreeAsync(scratch, s)) != hipSuccess) return hip_fail(e, "scratch free");
     }
+    if ((e = scr.release()) != hipSuccess) return hip_fail(e, "scratch free");
     return FW_OK;
 }
 
@@ -456,10 +484,12 @@ fw_status_t fw_apsp_batched_config(fw_dtype_t dt, int32_t batch, const int32_t *
     const int32_t njobs = (int32_t)order.size();
     // Queue in order of decreasing n (longest job first); counter slot first.
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return n_host[x] > n_host[y]; });
-    const size_t words = 1 + 2 * (size_t)njobs, bytes = words * sizeof(int64_t);
-    void *djobs = nullptr;
-    e = hipMallocAsync(&djobs, bytes, s);
-    if (e != hipSuccess) return fail(FW_ENOMEM, "job table of %zu bytes: %s", bytes, hipGetErrorString(e));
+    const size_t words = 2 + 2 * (size_t)njobs, bytes = words * sizeof(int64_t);
+    StreamScratch scr(s);
+    if ((e = scr.alloc(0, bytes)) != hipSuccess)
+        return fail(FW_ENOMEM, "job table of %zu bytes: %s", bytes, hipGetErrorString(e));
+    void *djobs = scr.p[0];
+    if (take_injected_failure(2)) return fail(FW_EHIP, "injected failure after the job table allocation");
     {
         // Pinned staging buffer, reused across calls once its previous upload is done.
         std::lock_guard<std::mutex> lk(g_stage_mu);
@@ -473,9 +503,10 @@ fw_status_t fw_apsp_batched_config(fw_dtype_t dt, int32_t batch, const int32_t *
         }
         int64_t *tab = (int64_t *)g_stage;
         tab[0] = 0;
+        tab[1] = njobs;
         for (int32_t q = 0; q < njobs; ++q) {
-            tab[1 + 2 * q] = off_host[order[(size_t)q]];
-            tab[2 + 2 * q] = n_host[order[(size_t)q]];
+            tab[2 + 2 * q] = off_host[order[(size_t)q]];
+            tab[3 + 2 * q] = n_host[order[(size_t)q]];
         }
         if ((e = hipMemcpyAsync(djobs, g_stage, bytes, hipMemcpyHostToDevice, s)) != hipSuccess) return hip_fail(e, "job upload");
         if (!g_stage_ev && (e = hipEventCreateWithFlags(&g_stage_ev, hipEventDisableTiming)) != hipSuccess)
@@ -484,12 +515,73 @@ fw_status_t fw_apsp_batched_config(fw_dtype_t dt, int32_t batch, const int32_t *
     }
     int grid = cus * occ;
     if (grid > njobs) grid = njobs;
-    e = dt == FW_F32 ? fw::launch_batched<float>((float *)dist, path, (int64_t *)djobs, njobs, small_max_n, grid, s)
-                     : fw::launch_batched<double>((double *)dist, path, (int64_t *)djobs, njobs, small_max_n, grid, s);
-    hipError_t e2 = hipFreeAsync(djobs, s);
+    e = dt == FW_F32 ? fw::launch_batched<float>((float *)dist, path, (int64_t *)djobs, small_max_n, grid, s)
+                     : fw::launch_batched<double>((double *)dist, path, (int64_t *)djobs, small_max_n, grid, s);
     if (e != hipSuccess) return hip_fail(e, "batched launch");
-    if (e2 != hipSuccess) return hip_fail(e2, "job table free");
+    if ((e = scr.release()) != hipSuccess) return hip_fail(e, "job table free");
     return FW_OK;
+}
+
+// The device-array form: the job table is built on the device (k_build_jobs)
+// into `jobs` (2 + 2*batch int64), then the persistent launch reads it.
+static fw_status_t batched_device_common(fw_dtype_t dt, int32_t batch, const int32_t *n_dev, const int64_t *off_dev,
+                                         void *dist, int32_t *path, int64_t *jobs, hipStream_t s, int dev) {
+    hipError_t e;
+    int cus = 0;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return hip_fail(e, "CU count");
+    const bool p = path != nullptr;
+    const int occ = dt == FW_F32 ? fw::batched_occupancy<float>(p) : fw::batched_occupancy<double>(p);
+    const int small_max_n = fw::tuned_batched_small_max_n(dt == FW_F64, p);
+    int grid = cus * occ;
+    if (grid > batch) grid = batch;
+    if ((e = fw::launch_build_jobs(n_dev, off_dev, batch, jobs, s)) != hipSuccess) return hip_fail(e, "job table build");
+    e = dt == FW_F32 ? fw::launch_batched<float>((float *)dist, path, jobs, small_max_n, grid, s)
+                     : fw::launch_batched<double>((double *)dist, path, jobs, small_max_n, grid, s);
+    if (e != hipSuccess) return hip_fail(e, "batched launch");
+    return FW_OK;
+}
+
+static fw_status_t batched_device_check(fw_dtype_t dt, int32_t batch, const int32_t *n_dev, const int64_t *off_dev,
+                                        const void *dist, int *dev) {
+    if (fw_status_t st = check_dtype(dt, true); st != FW_OK) return st;
+    if (batch < 1) return fail(FW_EINVAL, "batch = %d < 1", batch);
+    if (!n_dev || !off_dev || !dist) return fail(FW_EINVAL, "NULL argument");
+    hipError_t e = hipGetDevice(dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    return FW_OK;
+}
+
+fw_status_t fw_apsp_batched_device(fw_dtype_t dt, int32_t batch, const int32_t *n_dev, const int64_t *off_dev,
+                                   void *dist, int32_t *path, void *stream) {
+    g_err[0] = 0;
+    int dev = -1;
+    if (fw_status_t st = batched_device_check(dt, batch, n_dev, off_dev, dist, &dev); st != FW_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    StreamScratch scr(s);
+    const size_t bytes = (2 + 2 * (size_t)batch) * sizeof(int64_t);
+    hipError_t e;
+    if ((e = scr.alloc(0, bytes)) != hipSuccess)
+        return fail(FW_ENOMEM, "job table of %zu bytes: %s", bytes, hipGetErrorString(e));
+    if (fw_status_t st = batched_device_common(dt, batch, n_dev, off_dev, dist, path, (int64_t *)scr.p[0], s, dev);
+        st != FW_OK)
+        return st;
+    if ((e = scr.release()) != hipSuccess) return hip_fail(e, "job table free");
+    return FW_OK;
+}
+
+fw_status_t fw_apsp_batched_device_noalloc(fw_dtype_t dt, int32_t batch, const int32_t *n_dev,
+                                           const int64_t *off_dev, void *dist, int32_t *path, void *stream) {
+    g_err[0] = 0;
+    int dev = -1;
+    if (fw_status_t st = batched_device_check(dt, batch, n_dev, off_dev, dist, &dev); st != FW_OK) return st;
+    if (batch > fw::kNoAllocMaxBatch)
+        return fail(FW_EINVAL, "batch = %d above the %d graphs the static job table holds", batch,
+                    fw::kNoAllocMaxBatch);
+    int64_t *jobs = nullptr;
+    hipError_t e = fw::noalloc_jobs(dev, &jobs);
+    if (e != hipSuccess) return hip_fail(e, "job table address (hipGetSymbolAddress)");
+    return batched_device_common(dt, batch, n_dev, off_dev, dist, path, jobs, (hipStream_t)stream, dev);
 }
 
 fw_status_t fw_apsp_batched(fw_dtype_t dt, int32_t batch, const int32_t *n_host, const int64_t *off_host, void *dist,
@@ -508,11 +600,16 @@ fw_status_t fw_apsp_backward(fw_dtype_t dt, int64_t n, int32_t batch, const void
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     hipStream_t s = (hipStream_t)stream;
+    StreamScratch scr(s);
+    const size_t bytes = fw::backward_scratch_bytes((int)n, batch);
+    if ((e = scr.alloc(0, bytes)) != hipSuccess)
+        return fail(FW_ENOMEM, "backward scratch of %zu bytes: %s", bytes, hipGetErrorString(e));
     e = dt == FW_F32 ? fw::launch_backward<float>((const float *)dist, path, (const float *)grad_dist,
-                                                  (float *)grad_w, (int)n, batch, s)
+                                                  (float *)grad_w, (int)n, batch, scr.p[0], s)
                      : fw::launch_backward<double>((const double *)dist, path, (const double *)grad_dist,
-                                                   (double *)grad_w, (int)n, batch, s);
+                                                   (double *)grad_w, (int)n, batch, scr.p[0], s);
     if (e != hipSuccess) return hip_fail(e, "backward launch");
+    if ((e = scr.release()) != hipSuccess) return hip_fail(e, "backward scratch free");
     return FW_OK;
 }
 
@@ -528,6 +625,8 @@ const char *fw_status_string(int st) {
 }
 
 const char *fw_last_error(void) { return g_err; }
+
+void fw_debug_fail_next(int where) { g_fail_next.store(where == 1 || where == 2 ? where : 0); }
 
 const char *fw_version(void) { return "fwapsp 0.1 gfx950"; }
 

@@ -162,6 +162,51 @@ def test_c5_batch_closed_form(dev):
     np.testing.assert_array_equal(gW, expect)
 
 
+def test_backward_is_deterministic(dev):
+    """The same (D, P, G) gives the same gradient bit for bit on repeated calls
+    (float32 and float64), and it equals the oracle path walk over those (D, P)."""
+    import torch
+    import paper_2105_07298_amd as fw
+    for dtype, tol in ((np.float32, 1e-5), (np.float64, 1e-12)):
+        W = workloads.unit_complete(384, dtype=dtype, seed=63)
+        G = np.random.default_rng(8).standard_normal(W.shape).astype(dtype)
+        print(f"[gpu] backward determinism {np.dtype(dtype).name}", flush=True)
+        D, P = fw.apsp(torch.from_numpy(W).to(dev))
+        Gt = torch.from_numpy(G).to(dev)
+        outs = [fw.apsp_backward(D, P, Gt) for _ in range(3)]
+        torch.cuda.synchronize()
+        outs = [o.cpu().numpy() for o in outs]
+        for o in outs[1:]:
+            assert np.array_equal(o, outs[0])
+        ref = oracle.backward_pathwalk(D.cpu().numpy().astype(np.float64), P.cpu().numpy(), G.astype(np.float64))
+        np.testing.assert_allclose(outs[0], ref, rtol=tol, atol=tol * np.abs(ref).max())
+
+
+def test_backward_bad_labels_count_as_unreachable(dev):
+    """Labels outside [-1, n) in a caller's path matrix are never followed: the pair
+    (and the subtree below it in that source's tree) contributes nothing."""
+    import torch
+    import paper_2105_07298_amd as fw
+    n = 96
+    W = np.full((n, n), np.inf, dtype=np.float32)
+    np.fill_diagonal(W, 0)
+    W[np.arange(n - 1), np.arange(1, n)] = 1.0 + np.arange(n - 1, dtype=np.float32) / 128
+    Do, Po = oracle.fw(W)
+    G = np.random.default_rng(9).standard_normal((n, n))
+    Pbad = Po.copy()
+    Pbad[0, 40] = n + 5        # out of range: source 0 loses vertex 40 and everything after it
+    Pbad[3, 70] = -7           # negative non-sentinel: source 3 loses 70 onwards
+    Gm = G.copy()
+    Gm[0, 40:] = 0
+    Gm[3, 70:] = 0
+    expect = oracle.backward_pathwalk(Do, Po, Gm)
+    print("[gpu] backward with out-of-range labels", flush=True)
+    gW = fw.apsp_backward(torch.from_numpy(Do.astype(np.float32)).to(dev), torch.from_numpy(Pbad).to(dev),
+                          torch.from_numpy(G.astype(np.float32)).to(dev))
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(gW.cpu().numpy(), expect, rtol=1e-5, atol=1e-5 * np.abs(expect).max())
+
+
 def test_backward_rejects_bad_arguments(dev):
     import paper_2105_07298_amd as fw
     L = fw.lib()

@@ -227,3 +227,35 @@ def test_batched_tile_choice_invariance(dev, small_max_n):
         Do, Po = oracle.fw(g)
         np.testing.assert_array_equal(D[off[b]:off[b + 1]].reshape(n, n).astype(np.float64), Do)
         np.testing.assert_array_equal(P[off[b]:off[b + 1]].reshape(n, n), Po)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_batched_device_arrays(dev, dtype):
+    """fw_apsp_batched_device: counts and offsets in device memory, the queue built on
+    the device.  Every valid graph equals the oracle bit for bit (tie-heavy integer
+    weights, n from 1 to 300); graphs with n = 0, n = 5000 or a negative offset are
+    skipped and their bytes left untouched."""
+    import torch
+    import paper_2105_07298_amd as fw
+    rng = np.random.default_rng(13)
+    sizes = [1, 2, 31, 32, 33, 64, 65, 300] + list(rng.integers(1, 200, 40))
+    graphs = [workloads.int_graph(n=int(n), p=float(rng.uniform(0.02, 0.4)), wmax=3, seed=1100 + i)
+              for i, n in enumerate(sizes)]
+    ns, off, W = ragged(graphs, dtype)
+    # three invalid entries pointing at a sentinel region after the graphs
+    tail = W.size
+    W = np.concatenate([W, np.full(64, -3.0, dtype=dtype)])
+    ns_d = np.concatenate([ns, np.array([0, 5000, 4], dtype=np.int32)])
+    off_d = np.concatenate([off[:-1], np.array([tail, tail, -16], dtype=np.int64)])
+    Wt = torch.from_numpy(W).to(dev)
+    P = torch.full(Wt.shape, -9, dtype=torch.int32, device=dev)
+    print(f"[gpu] fw_apsp_batched_device batch={ns_d.size} dtype={W.dtype}", flush=True)
+    fw.apsp_batched_device_(Wt, torch.from_numpy(ns_d).to(dev), torch.from_numpy(off_d).to(dev), P)
+    torch.cuda.synchronize()
+    D, P = Wt.cpu().numpy(), P.cpu().numpy()
+    for b, g in enumerate(graphs):
+        n = g.shape[0]
+        Do, Po = oracle.fw(g)
+        np.testing.assert_array_equal(D[off[b]:off[b + 1]].reshape(n, n).astype(np.float64), Do)
+        np.testing.assert_array_equal(P[off[b]:off[b + 1]].reshape(n, n), Po)
+    assert np.all(D[tail:] == -3.0) and np.all(P[tail:] == -9)
