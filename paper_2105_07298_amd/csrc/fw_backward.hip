@@ -15,12 +15,12 @@
 //      vertex reached is pred_i(j).
 //   2. depth_i(j) (edges on the path): depth of pred_i(j) plus one, settled
 //      level by level.
-//   3. subtree sums, deepest level first: every vertex of a level adds its sum
-//      to its parent's (LDS atomics, double); a level is complete before the
-//      next shallower one starts.  Within one level every vertex is a child of
-//      a vertex one level up, and a parent's sum is read only after its level
-//      is complete, so S(j) is exact up to the order in which a vertex's
-//      children are added.
+//   3. subtree sums, deepest level first, by the first wave alone: a level's
+//      vertices are taken 64 at a time in increasing order; within such a
+//      group the lanes that share a parent are summed in lane order by the
+//      lowest of them, which adds that sum to the parent's (double, in LDS).
+//      A level is complete before the next shallower one starts, and every
+//      addition happens in an order fixed by the vertex numbers.
 //   4. row i of two scratch matrices: U[i][j] = pred_i(j) (-1 where source i
 //      contributes nothing to column j) and S[i][j] = S(j) in double.
 // k_backward_columns, one wave per (graph, column j): dL/dW[u][j] is the sum of
@@ -105,12 +105,38 @@ __global__ void __launch_bounds__(NT) k_backward_tree(const T *__restrict__ D, c
             break;
         }
     }
-    // 3. subtree sums from the deepest level up (level-1 vertices hang off i).
-    for (int lev = maxd; lev >= 2; --lev) {
-        for (int j = threadIdx.x; j < n; j += NT)
-            if (depth[j] == lev) atomicAdd(&S[pred[j]], S[j]);
-        __syncthreads();
+    // 3. subtree sums from the deepest level up (level-1 vertices hang off i,
+    //    whose own sum is not needed).  One wave: its LDS accesses take effect
+    //    in program order, so a level's additions are seen by the next level.
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        for (int lev = maxd; lev >= 2; --lev) {
+            for (int j0 = 0; j0 < n; j0 += 64) {
+                const int j = j0 + lane;
+                const bool on = j < n && depth[j] == lev;
+                uint64_t mask = __ballot(on);
+                if (mask == 0) continue;
+                const int par = on ? (int)pred[j] : -1;
+                const double s = on ? S[j] : 0.0;
+                const uint64_t sb = __builtin_bit_cast(uint64_t, s);
+                const int slo = (int)(uint32_t)sb, shi = (int)(uint32_t)(sb >> 32);
+                double sum = 0.0;
+                bool leader = on;
+                while (mask) {
+                    const int l = __builtin_ctzll(mask);
+                    mask &= mask - 1;
+                    const int pl = __builtin_amdgcn_readlane(par, l);
+                    const uint64_t bl = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(shi, l) << 32) |
+                                        (uint32_t)__builtin_amdgcn_readlane(slo, l);
+                    const bool same = pl == par;
+                    sum += same ? __builtin_bit_cast(double, bl) : 0.0;
+                    leader = leader && !(same && l < lane);
+                }
+                if (on && leader) S[par] += sum;  // one leader per parent in this group
+            }
+        }
     }
+    __syncthreads();
     // 4. this source's row of the (pred, subtree sum) scratch.
     const int64_t row = base + (int64_t)i * n;
     for (int j = threadIdx.x; j < n; j += NT) {

@@ -1,8 +1,11 @@
 // fw_lex.h -- the lexicographic (length, label) update in its fast form, shared
-// by the device kernels that carry the path matrix (paper Sect. 2.1: a shorter
-// candidate through k replaces the entry and its intermediate vertex; equal
-// lengths are broken towards the smaller largest-interior-vertex label, which
-// makes the labels independent of the order of the k steps).
+// by the device kernels that carry the path matrix.  Sect. 2.2 (Algorithm 1):
+// a shorter candidate through k replaces the entry and records k as its
+// intermediate vertex.  The tie-break is this library's reading, not the
+// paper's (the paper never discusses the path matrix under the blocked order):
+// equal lengths go to the smaller largest-interior-vertex label, which makes
+// the labels independent of the order of the k steps and equal to what the
+// classic loop with a strict test stores.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
