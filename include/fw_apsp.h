@@ -54,7 +54,8 @@ typedef enum {
     FW_EINVAL = -1,       /* bad argument (size, pointer, dtype, layout)         */
     FW_ENOMEM = -2,       /* scratch allocation failed                           */
     FW_EHIP = -3,         /* a HIP runtime call failed (no device, launch error) */
-    FW_EUNSUPPORTED = -4  /* valid but not supported by this build               */
+    FW_EUNSUPPORTED = -4, /* valid but not supported by this build               */
+    FW_EINPUT = -5        /* fw_validate_input: the matrix breaks the contract    */
 } fw_status_t;
 
 /*
@@ -70,6 +71,19 @@ typedef enum {
  * are isolated, so they change nothing) and back.
  */
 fw_status_t fw_apsp(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, void *stream);
+
+/*
+ * Checks a weight matrix against the input contract of the problem statement
+ * (paper Sect. 2.2: 0 on the diagonal, a weight >= 0 or +inf off it; no NaN),
+ * which the other entry points assume without checking (they compute nothing
+ * meaningful otherwise: a negative cycle has no shortest path).
+ *   dt, n, dist  as for fw_apsp (device, n*n elements, row-major); not modified.
+ * Waits for `stream` (the check's launch and its one-word read-back are ordered
+ * after earlier work on it).  Returns FW_OK, or FW_EINPUT with the first
+ * offending entry in row-major order, its value and the broken rule in
+ * fw_last_error().  Allocates one 8-byte stream-ordered word.
+ */
+fw_status_t fw_validate_input(fw_dtype_t dt, int64_t n, const void *dist, void *stream);
 
 /*
  * Tile configuration of fw_apsp, for tuning and for the tests that show results

@@ -12,7 +12,9 @@ Contents
                         (length, largest interior vertex): rows of D and of the
                         canonical P without the cubic loop.
   dial_rows(W, src, C)  the same labels by Dial's bucket queue, for integer
-                        weights in [1, C] (large sparse-ish graphs).
+                        weights in [1, C] (large sparse-ish graphs);
+                        dial_rows_generated reads each row through a callback
+                        instead (the matrix never exists in host memory).
   brute_force(W)        enumeration of every simple path, n <= 8: the definition
                         of (D, P) written out.
   backward_pathwalk     dL/dW from dL/dD by walking each pair's shortest path.
@@ -67,6 +69,7 @@ def load(path: str = _LIB):
     lib.oracle_dijkstra_rows_i64.argtypes = [i64, vp, i64, vp, vp, vp, ctypes.c_int]
     lib.oracle_dijkstra_rows_floatint.argtypes = [i64, vp, ctypes.c_int, i64, vp, vp, vp, ctypes.c_int]
     lib.oracle_dial_rows.argtypes = [i64, vp, ctypes.c_int, i64, i64, vp, vp, vp, ctypes.c_int]
+    lib.oracle_dial_rows_fn.argtypes = [i64, vp, vp, i64, i64, vp, vp, vp, ctypes.c_int]
     lib.oracle_backward_pathwalk_f64.argtypes = [i64, vp, vp, vp, vp]
     lib.oracle_backward_pathwalk_f64.restype = ctypes.c_int
     lib.oracle_reconstruct.argtypes = [i64, vp, i64, i64, vp, i64]
@@ -208,6 +211,22 @@ def dial_rows(W: np.ndarray, srcs, wmax: int, threads: int = 0):
     P = np.empty((srcs.size, n), dtype=np.int32)
     lib.oracle_dial_rows(n, _ptr(W), int(W.dtype == np.float64), int(wmax), srcs.size, _ptr(srcs), _ptr(D),
                          _ptr(P), threads)
+    return from_i64(D), P
+
+
+def dial_rows_generated(spec, rowfn: int, srcs, wmax: int, threads: int = 0):
+    """dial_rows for a graph whose weight matrix is never held in host memory: rows
+    are regenerated on demand by the C function at address rowfn, called as
+    rowfn(&spec, u, out) to fill row u (n doubles, +inf = no edge); spec is a
+    ctypes structure the function understands (the input generator's graph
+    description).  Integer weights in [1, wmax].  Returns (Drows float64, Prows int32)."""
+    lib = load()
+    n = int(spec.n)
+    srcs = np.ascontiguousarray(np.asarray(srcs, dtype=np.int64))
+    D = np.empty((srcs.size, n), dtype=np.int64)
+    P = np.empty((srcs.size, n), dtype=np.int32)
+    lib.oracle_dial_rows_fn(n, ctypes.c_void_p(rowfn), ctypes.byref(spec), int(wmax), srcs.size, _ptr(srcs),
+                            _ptr(D), _ptr(P), threads)
     return from_i64(D), P
 
 

@@ -214,8 +214,14 @@ void oracle_dijkstra_rows_floatint(int64_t n, const void *W, int is_f64, int64_t
  * pass over the row of each reached vertex.  Doubly linked lists move a vertex
  * to a lower bucket when its distance drops.
  */
-static void dial_one(int64_t n, const void *Wv, int is_f64, int64_t wmax, int64_t src, int64_t *dist, int32_t *pmax)
+/* A row source for graphs too large to hold in host memory: rowfn(ctx, u, out)
+ * writes row u of the weight matrix (n doubles, +inf = no edge) to out. */
+typedef void (*oracle_row_fn)(const void *ctx, int64_t u, double *out);
+
+static void dial_one(int64_t n, const void *Wv, int is_f64, oracle_row_fn rowfn, const void *ctx, int64_t wmax,
+                     int64_t src, int64_t *dist, int32_t *pmax)
 {
+    double *rowbuf = rowfn ? (double *)malloc(sizeof(double) * (size_t)n) : NULL;
     const int64_t nb = wmax + 1;
     int64_t *head = (int64_t *)malloc(sizeof(int64_t) * (size_t)nb);
     int64_t *nxt = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
@@ -242,12 +248,13 @@ static void dial_one(int64_t n, const void *Wv, int is_f64, int64_t wmax, int64_
             DIAL_UNLINK(u);
             --queued;
             const int32_t mu = (u == src) ? -1 : (pmax[u] > (int32_t)u ? pmax[u] : (int32_t)u);
-            const float *rf = (const float *)Wv + u * n;
-            const double *rd = (const double *)Wv + u * n;
+            const float *rf = rowfn ? NULL : (const float *)Wv + u * n;
+            const double *rd = rowfn ? rowbuf : (const double *)Wv + u * n;
+            if (rowfn) rowfn(ctx, u, rowbuf);
             /* A vertex already taken has a distance <= d < d + w, and a missing edge
              * gives +inf, so neither passes the tests below. */
             for (int64_t v = 0; v < n; ++v) {
-                const double w = is_f64 ? rd[v] : (double)rf[v];
+                const double w = (rowfn || is_f64) ? rd[v] : (double)rf[v];
                 const double sv = df + w;
                 if (sv < dd[v]) {
                     if (queued_v[v]) DIAL_UNLINK(v); else ++queued;
@@ -263,7 +270,7 @@ static void dial_one(int64_t n, const void *Wv, int is_f64, int64_t wmax, int64_
 #undef DIAL_PUSH
 #undef DIAL_UNLINK
     for (int64_t v = 0; v < n; ++v) dist[v] = (dd[v] == INFINITY) ? ORACLE_I64_INF : (int64_t)dd[v];
-    free(head); free(nxt); free(prv); free(dd); free(queued_v);
+    free(head); free(nxt); free(prv); free(dd); free(queued_v); free(rowbuf);
 }
 
 void oracle_dial_rows(int64_t n, const void *W, int is_f64, int64_t wmax, int64_t nsrc, const int64_t *srcs,
@@ -271,7 +278,18 @@ void oracle_dial_rows(int64_t n, const void *W, int is_f64, int64_t wmax, int64_
 {
 #pragma omp parallel for schedule(dynamic, 1) num_threads(pick_threads(threads))
     for (int64_t s = 0; s < nsrc; ++s)
-        dial_one(n, W, is_f64, wmax, srcs[s], dist + s * n, pmax + s * n);
+        dial_one(n, W, is_f64, NULL, NULL, wmax, srcs[s], dist + s * n, pmax + s * n);
+}
+
+/* The same with every row read through rowfn when its vertex is settled (the
+ * matrix itself never exists in host memory; each source reads each reached row
+ * once).  rowfn must be safe to call from several threads at once. */
+void oracle_dial_rows_fn(int64_t n, oracle_row_fn rowfn, const void *ctx, int64_t wmax, int64_t nsrc,
+                         const int64_t *srcs, int64_t *dist, int32_t *pmax, int threads)
+{
+#pragma omp parallel for schedule(dynamic, 1) num_threads(pick_threads(threads))
+    for (int64_t s = 0; s < nsrc; ++s)
+        dial_one(n, NULL, 1, rowfn, ctx, wmax, srcs[s], dist + s * n, pmax + s * n);
 }
 
 /* Many sources at once, one source per thread (for sampled-row verification of

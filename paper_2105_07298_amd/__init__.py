@@ -8,11 +8,11 @@ PyTorch provides device memory and streams only; no step of the method runs in i
 """
 from __future__ import annotations
 
-from ._lib import (FW_EHIP, FW_EINVAL, FW_ENOMEM, FW_EUNSUPPORTED, FW_F16, FW_F32, FW_F64, FW_OK,  # noqa: F401
+from ._lib import (FW_EHIP, FW_EINPUT, FW_EINVAL, FW_ENOMEM, FW_EUNSUPPORTED, FW_F16, FW_F32, FW_F64, FW_OK,  # noqa: F401
                    FW_P4_PANELS, FW_P4_WAVEROWS, FW_SCHED_LOOKAHEAD, FW_SCHED_PAIRS, FW_SCHED_PAIRS_LOOKAHEAD, FW_SCHED_SERIAL, FwError, fw_apsp, fw_apsp_backward, fw_apsp_batched,
                    fw_apsp_batched_config, fw_apsp_batched_device, fw_apsp_batched_device_noalloc, fw_apsp_config, fw_apsp_ooc, fw_last_error, fw_list_configs, fw_ooc_superblock,
                    fw_prof_enable,
-                   fw_prof_read, fw_query_config, fw_status_string, fw_version, lib, lookahead_applies,
+                   fw_prof_read, fw_query_config, fw_status_string, fw_validate_input, fw_version, lib, lookahead_applies,
                    pairs_applies, pairs_lookahead_applies)
 
 
@@ -57,6 +57,15 @@ def apsp_(D, P=None, block: int = 0, tile_m: int = 0, tile_n: int = 0, variant: 
     fw_apsp_config(_dtype_code(D), n, D.data_ptr(), pp, block, tile_m, tile_n, variant, schedule,
                    _stream_ptr(D.device))
     return D, P
+
+
+def validate(W):
+    """Check the device tensor W against the input contract (0 diagonal, weights
+    >= 0 or +inf, no NaN) on the library's kernel; raises FwError (FW_EINPUT)
+    naming the first offending entry.  Waits for the current stream."""
+    if not (W.is_cuda and W.dim() == 2 and W.shape[0] == W.shape[1] and W.is_contiguous()):
+        raise ValueError("W must be a contiguous square device tensor")
+    fw_validate_input(_dtype_code(W), W.shape[0], W.data_ptr(), _stream_ptr(W.device))
 
 
 def apsp(W, path: bool = True, block: int = 0, tile_m: int = 0, tile_n: int = 0, variant: int = 0,

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfwapsp.so")
 
 FW_F32, FW_F64, FW_F16 = 0, 1, 2
-FW_OK, FW_EINVAL, FW_ENOMEM, FW_EHIP, FW_EUNSUPPORTED = 0, -1, -2, -3, -4
+FW_OK, FW_EINVAL, FW_ENOMEM, FW_EHIP, FW_EUNSUPPORTED, FW_EINPUT = 0, -1, -2, -3, -4, -5
 FW_P4_PANELS, FW_P4_WAVEROWS = 1, 2
 FW_SCHED_SERIAL, FW_SCHED_LOOKAHEAD, FW_SCHED_PAIRS, FW_SCHED_PAIRS_LOOKAHEAD = 1, 2, 3, 4
 
@@ -20,7 +20,7 @@ EXPORTS = ("fw_apsp", "fw_apsp_config", "fw_query_config", "fw_list_configs", "f
            "fw_apsp_batched", "fw_apsp_batched_config", "fw_apsp_batched_device", "fw_apsp_batched_device_noalloc",
            "fw_apsp_backward",
            "fw_status_string", "fw_last_error", "fw_version", "fw_prof_enable", "fw_prof_read",
-           "fw_debug_fail_next")
+           "fw_debug_fail_next", "fw_validate_input")
 
 
 class FwConfig(ctypes.Structure):
@@ -77,6 +77,8 @@ def lib():
     L.fw_prof_enable.argtypes = [ctypes.c_int]
     L.fw_prof_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), ctypes.c_int]
     L.fw_prof_read.restype = ctypes.c_int
+    L.fw_validate_input.argtypes = [ctypes.c_int, i64, vp, vp]
+    L.fw_validate_input.restype = ctypes.c_int
     L.fw_debug_fail_next.argtypes = [ctypes.c_int]
     L.fw_debug_fail_next.restype = None
     _lib = L
@@ -153,6 +155,11 @@ def fw_apsp_batched_device_noalloc(dt, batch, n_dev, off_dev, dist, path, stream
 
 def fw_apsp_backward(dt, n, batch, dist, path, grad_dist, grad_w, stream=None):
     _check(lib().fw_apsp_backward(dt, n, batch, dist, path, grad_dist, grad_w, stream), "fw_apsp_backward")
+
+
+def fw_validate_input(dt, n, dist, stream=None):
+    """Raises FwError (status FW_EINPUT) when the matrix breaks the input contract."""
+    _check(lib().fw_validate_input(dt, n, dist, stream), "fw_validate_input")
 
 
 def fw_status_string(st: int) -> str:

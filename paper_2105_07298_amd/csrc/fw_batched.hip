@@ -44,7 +44,11 @@ template <> __device__ __forceinline__ float inf_b<float>() { return __builtin_i
 template <> __device__ __forceinline__ double inf_b<double>() { return __builtin_inf(); }
 
 __device__ __forceinline__ float bmin(float a, float b) { return __builtin_fminf(a, b); }
-__device__ __forceinline__ double bmin(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ double bmin(double a, double b) {  // the instruction: no quieting of NaN (none occur)
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
 
 template <typename T, int W> struct VecT {
     typedef T type __attribute__((ext_vector_type(W)));
@@ -92,8 +96,12 @@ struct Graph {
         return (i < n && j < n) ? v : 0u;
     }
     // Tile (I0, J0) into LDS, row-major with stride ST (labels likewise): all
-    // global loads first, then the LDS writes.
-    __device__ void stage(T *s, uint16_t *l, int I0, int J0) const {
+    // global loads first, then the LDS writes.  With kb1 > 0 (the last phase's
+    // column-panel tile, whose columns are the round's k) each label + 1 is
+    // stored as max(label + 1, kb1 + column), i.e. already combined with k + 1
+    // for its column k = J0 + column, so the product does not redo it for every
+    // entry of the tile it updates.
+    __device__ void stage(T *s, uint16_t *l, int I0, int J0, uint32_t kb1 = 0) const {
         constexpr int IT = TB * TB / NT;
         T v[IT];
         uint32_t w[PATH ? IT : 1];
@@ -107,7 +115,7 @@ struct Graph {
         for (int it = 0; it < IT; ++it) {
             const int q = (int)threadIdx.x + it * NT, rr = q / TB, cc = q % TB;
             s[rr * ST + cc] = v[it];
-            if (PATH) l[rr * ST + cc] = (uint16_t)w[it];
+            if (PATH) l[rr * ST + cc] = (uint16_t)(kb1 ? max(w[it], kb1 + (uint32_t)cc) : w[it]);
         }
     }
     // The thread's entries of tile (I0, J0): from global memory ...
@@ -186,7 +194,9 @@ struct Graph {
 
     // (d, p) <- lexmin over k in the block of (d, p) and the candidates through k:
     // A[i][k] + B[k][j] with label max(LA[i][k], kbase + k, LB[k][j]) (labels +
-    // 1); distances only: d <- min(d, A[i][k] + B[k][j]), two k per v_min3.
+    // 1; with PREMAX, LA already holds max(LA[i][k], kbase + k + 1), see
+    // stage); distances only: d <- min(d, A[i][k] + B[k][j]), two k per v_min3.
+    template <bool PREMAX = false>
     __device__ static void product(T (&d)[RM][RN], uint32_t (&p)[RM][RN], const T *A, const uint16_t *LA,
                                    const T *B, const uint16_t *LB, int kbase, int tx, int ty) {
 #pragma unroll 2
@@ -211,7 +221,7 @@ struct Graph {
                     const uint32_t kg1 = (uint32_t)(kbase + kv * V + kk + 1);
 #pragma unroll
                     for (int ii = 0; ii < RM; ++ii) {
-                        const uint32_t mi = max((uint32_t)pa[ii][kk], kg1);
+                        const uint32_t mi = PREMAX ? (uint32_t)pa[ii][kk] : max((uint32_t)pa[ii][kk], kg1);
 #pragma unroll
                         for (int h = 0; h < HN; ++h)
 #pragma unroll
@@ -328,14 +338,14 @@ __device__ void solve_graph(Graph<T, TB, PATH> g, T *sa, T *sb, uint16_t *la, ui
             const int bi0 = t / (R - 1), bj0 = t % (R - 1);
             const int bi = bi0 < r ? bi0 : bi0 + 1, bj = bj0 < r ? bj0 : bj0 + 1;
             const int I0 = bi * TB, J0 = bj * TB;
-            if (bj0 == 0) g.stage(sa, la, I0, k0);
+            if (bj0 == 0) g.stage(sa, la, I0, k0, (uint32_t)(k0 + 1));
             g.stage(sb, lb, k0, J0);
             if (PATH)
                 g.load_d0(d, p, I0, J0, tx, ty);
             else
                 g.load(d, p, I0, J0, tx, ty);
             __syncthreads();
-            G::product(d, p, sa, la, sb, lb, k0, tx, ty);
+            G::template product<true>(d, p, sa, la, sb, lb, k0, tx, ty);
             if (PATH)
                 g.store_changed(d, p, I0, J0, tx, ty);
             else

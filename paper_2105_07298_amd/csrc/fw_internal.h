@@ -151,6 +151,11 @@ hipError_t launch_pad_in(const T *src, int64_t n, T *dst, int64_t npad, hipStrea
 template <typename T>
 hipError_t launch_pad_out(const T *src, int64_t npad, T *dst, int64_t n, hipStream_t s);
 
+// Input contract check: *first <- the smallest flat index of an entry of the
+// n x n matrix D that is NaN, negative, or a non-zero diagonal entry (~0 if none).
+template <typename T>
+hipError_t launch_validate(const T *D, int64_t n, unsigned long long *first, hipStream_t s);
+
 // Kernel-class timing hooks: events around the last-phase launches of kind
 // all / rest, with the algorithmic min-plus updates each performs.
 void prof_begin_p4(hipStream_t s);

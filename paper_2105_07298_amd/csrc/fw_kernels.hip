@@ -67,7 +67,17 @@ template <> __device__ __forceinline__ double inf_v<double>() { return __builtin
 template <> __device__ __forceinline__ _Float16 inf_v<_Float16>() { return (_Float16)__builtin_inff(); }
 
 __device__ __forceinline__ float vmin(float a, float b) { return __builtin_fminf(a, b); }
-__device__ __forceinline__ double vmin(double a, double b) { return __builtin_fmin(a, b); }
+// double: the instruction itself.  The library minimum must quiet a signalling
+// NaN operand first, and where an accumulator enters a loop iteration the
+// compiler cannot tell that it is already quiet, so it re-canonicalised every
+// accumulator every iteration (one v_max_f64 per four updates in the last
+// phase).  Lengths here are never NaN (input contract), so the plain
+// instruction gives the same result.
+__device__ __forceinline__ double vmin(double a, double b) {
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
 __device__ __forceinline__ _Float16 vmin(_Float16 a, _Float16 b) { return __builtin_elementwise_min(a, b); }
 
 

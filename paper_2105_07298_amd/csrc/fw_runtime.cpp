@@ -434,6 +434,40 @@ fw_status_t fw_apsp_ooc(fw_dtype_t dt, int64_t n, void *dist_host, int32_t *path
     return FW_OK;
 }
 
+fw_status_t fw_validate_input(fw_dtype_t dt, int64_t n, const void *dist, void *stream) {
+    g_err[0] = 0;
+    if (fw_status_t st = check_common(dt, n, dist, false); st != FW_OK) return st;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    StreamScratch scr(s);
+    if ((e = scr.alloc(0, sizeof(unsigned long long))) != hipSuccess)
+        return fail(FW_ENOMEM, "validation word: %s", hipGetErrorString(e));
+    unsigned long long *first = (unsigned long long *)scr.p[0];
+    e = dt == FW_F32 ? fw::launch_validate<float>((const float *)dist, n, first, s)
+                     : dt == FW_F64 ? fw::launch_validate<double>((const double *)dist, n, first, s)
+                                    : fw::launch_validate<_Float16>((const _Float16 *)dist, n, first, s);
+    if (e != hipSuccess) return hip_fail(e, "validation launch");
+    unsigned long long idx = 0;
+    if ((e = hipMemcpyAsync(&idx, first, sizeof idx, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return hip_fail(e, "validation read-back");
+    if ((e = scr.release()) != hipSuccess) return hip_fail(e, "validation word free");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "validation wait");
+    if (idx == ~0ull) return FW_OK;
+    const size_t es = dt == FW_F32 ? 4 : dt == FW_F64 ? 8 : 2;
+    unsigned char raw[8] = {};
+    if ((e = hipMemcpy(raw, (const char *)dist + idx * es, es, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "validation entry read-back");
+    double v = 0.0;
+    if (dt == FW_F32) v = *(float *)raw;
+    if (dt == FW_F64) v = *(double *)raw;
+    if (dt == FW_F16) v = (double)*(_Float16 *)raw;
+    const long long i = (long long)(idx / (unsigned long long)n), j = (long long)(idx % (unsigned long long)n);
+    return fail(FW_EINPUT, "entry (%lld, %lld) = %g: %s", i, j, v,
+                v != v ? "NaN" : (i == j ? "diagonal entry is not 0" : "negative weight"));
+}
+
 fw_status_t fw_apsp(fw_dtype_t dt, int64_t n, void *dist, int32_t *path, void *stream) {
     return fw_apsp_config(dt, n, dist, path, nullptr, stream);
 }
@@ -620,6 +654,7 @@ const char *fw_status_string(int st) {
     case FW_ENOMEM: return "out of device memory";
     case FW_EHIP: return "HIP runtime error";
     case FW_EUNSUPPORTED: return "unsupported";
+    case FW_EINPUT: return "input outside the contract";
     }
     return "unknown status";
 }

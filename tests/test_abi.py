@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported(fw):
 
 def test_status_strings(fw):
     assert fw.fw_status_string(0) == "ok"
-    for st in (-1, -2, -3, -4):
+    for st in (-1, -2, -3, -4, -5):
         assert fw.fw_status_string(st) not in ("ok", "unknown status")
     assert fw.fw_status_string(17) == "unknown status"
     assert "gfx950" in fw.fw_version()
@@ -182,3 +182,10 @@ def test_ooc_superblock_choice(fw):
                     assert S == top or need(n, S + 256, es, path) > budget
             assert fw.lib().fw_ooc_superblock(dt, 3000, 1 if path else 0, 1000) == fw.FW_ENOMEM
     assert fw.lib().fw_ooc_superblock(9, 3000, 0, 1 << 30) == fw.FW_EINVAL
+
+
+def test_validate_argument_errors_before_device(fw):
+    L = fw.lib()
+    assert L.fw_validate_input(0, 0, 4096, None) == fw.FW_EINVAL
+    assert L.fw_validate_input(0, 16, None, None) == fw.FW_EINVAL
+    assert L.fw_validate_input(9, 16, 4096, None) == fw.FW_EINVAL

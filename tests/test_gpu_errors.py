@@ -90,3 +90,25 @@ def test_fail_next_cleared_by_zero(dev):
     Do, Po = oracle.fw(W)
     np.testing.assert_array_equal(D.cpu().numpy().astype(np.float64), Do)
     np.testing.assert_array_equal(P.cpu().numpy(), Po)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64, np.float16])
+def test_validate_input(dev, dtype):
+    """fw_validate_input accepts a matrix inside the contract (including +inf and -0.0
+    off the diagonal) and names the first entry of one that is not: a non-zero
+    diagonal entry, a NaN, a negative weight."""
+    import torch
+    import paper_2105_07298_amd as fw
+    n = 300
+    W = workloads.int_graph(n=n, p=0.3, wmax=9, seed=34).astype(dtype)
+    W[5, 7] = -0.0
+    print(f"[gpu] fw_validate_input {np.dtype(dtype).name}", flush=True)
+    fw.validate(torch.from_numpy(W).to(dev))
+    for (i, j, v, what) in ((17, 17, 1.0, "diagonal"), (200, 3, np.nan, "NaN"), (41, 250, -2.0, "negative")):
+        Wb = W.copy()
+        Wb[i, j] = v
+        Wb[290, 1] = -5.0  # a later offence: the first one in row-major order is reported
+        with pytest.raises(fw.FwError) as ei:
+            fw.validate(torch.from_numpy(Wb).to(dev))
+        assert ei.value.status == fw.FW_EINPUT
+        assert f"({i}, {j})" in str(ei.value) and what in str(ei.value), str(ei.value)

@@ -284,3 +284,19 @@ def test_dial_matches_fw_and_dijkstra(wmax, p):
     Dd64, Pd64 = oracle.dial_rows(W.astype(np.float64), srcs, wmax)
     np.testing.assert_array_equal(Dd64, Dd)
     np.testing.assert_array_equal(Pd64, Pd)
+
+
+def test_dial_with_generated_rows_equals_dial_on_the_matrix():
+    """The on-demand-row form of the Dial search (used where the matrix never exists
+    in host memory) gives the same rows of D and P as the search over the matrix,
+    in both element types."""
+    for dtype in (np.float32, np.float64):
+        n = 700
+        W = workloads.int_graph(n=n, p=0.05, wmax=20, seed=3, dtype=dtype)
+        srcs = workloads.sample_sources(n, 12)
+        Dm, Pm = oracle.dial_rows(W, srcs, 20)
+        spec = workloads.graph_spec(3, n, 0.05, workloads.W_INT, 20, dtype)
+        Dg, Pg = oracle.dial_rows_generated(spec, workloads.row_fn(), srcs, 20)
+        assert np.array_equal(Dm, Dg) and np.array_equal(Pm, Pg)
+        Do, Po = oracle.fw(W)
+        assert np.array_equal(Dg, Do[srcs]) and np.array_equal(Pg, Po[srcs])

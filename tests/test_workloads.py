@@ -104,3 +104,19 @@ def test_grad_graph_law():
     assert v.min() >= 1 and v.max() < 2
     assert np.all((v.astype(np.float64) - 1) * 2**23 == np.floor((v.astype(np.float64) - 1) * 2**23))
     assert abs(G.mean()) < 0.05 and abs(G.std() - 1) < 0.05
+
+
+def test_row_callback_matches_rows():
+    """gen_row_cb (the row source of the oracle's on-demand searches) gives the rows
+    gen_rows_f32 / gen_rows_f64 give, widened to double."""
+    import ctypes
+    for dtype in (np.float32, np.float64):
+        for law, wmax, p in ((workloads.W_INT, 100, 0.1), (workloads.W_UNIT_OPEN, 0, 1.0),
+                             (workloads.W_ONE_TEN, 0, 0.4)):
+            n = 301
+            W = workloads.rows(7, n, 0, n, p, law, wmax, dtype, g=2)
+            spec = workloads.graph_spec(7, n, p, law, wmax, dtype, g=2)
+            out = np.empty(n, dtype=np.float64)
+            for i in (0, 5, 300):
+                workloads._load().gen_row_cb(ctypes.byref(spec), i, out.ctypes.data_as(ctypes.c_void_p))
+                assert np.array_equal(out, W[i].astype(np.float64))

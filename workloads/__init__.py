@@ -28,10 +28,71 @@ _lib = None
 W_INT, W_UNIT_OPEN, W_ONE_TEN, W_ONE_TWO = 0, 1, 2, 3
 
 
+_DEV_SRC = os.path.join(_HERE, "gen_dev.hip")
+_DEV_LIB = os.path.join(_HERE, "libfwgen_dev.so")
+_dev_lib = None
+
+
+class GraphSpec(ctypes.Structure):
+    """The graph description gen_row_cb reads (gen.c's gen_graph_t)."""
+    _fields_ = [("seed", ctypes.c_uint64), ("g", ctypes.c_uint64), ("n", ctypes.c_int64),
+                ("thresh32", ctypes.c_uint64), ("law", ctypes.c_int32), ("is_f64", ctypes.c_int32),
+                ("wmax", ctypes.c_int64)]
+
+
 def build(out: str = _LIB) -> str:
     subprocess.run(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11", "-Wall",
                     "-o", out, _SRC, "-lm"], check=True)
     return out
+
+
+def build_dev(out: str = _DEV_LIB) -> str:
+    """The device twin (hipcc, gfx950), contraction off so weights round as on the host."""
+    hipcc = "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else "hipcc"
+    subprocess.run([hipcc, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+                    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-o", out, _DEV_SRC], check=True)
+    return out
+
+
+def _load_dev():
+    global _dev_lib
+    if _dev_lib is None:
+        if not os.path.exists(_DEV_LIB):
+            raise ImportError(f"{_DEV_LIB} is missing: build it with workloads.build_dev()")
+        lib = ctypes.CDLL(_DEV_LIB)
+        lib.gen_rows_dev.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                     ctypes.c_uint64, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+                                     ctypes.c_void_p]
+        lib.gen_rows_dev.restype = ctypes.c_int
+        _dev_lib = lib
+    return _dev_lib
+
+
+def rows_dev(seed: int, n: int, r0: int, r1: int, p: float, law: int, wmax: int, out, g: int = 0,
+             stream: int | None = None):
+    """rows() generated on the GPU straight into the device tensor out ((r1 - r0) * n
+    float32/float64 elements, contiguous), on the given stream (default: the current one)."""
+    import torch
+    assert out.is_cuda and out.is_contiguous() and out.numel() == (r1 - r0) * n
+    assert out.dtype in (torch.float32, torch.float64)
+    if stream is None:
+        stream = torch.cuda.current_stream(out.device).cuda_stream
+    rc = _load_dev().gen_rows_dev(seed, g, n, r0, r1, threshold(p), law, wmax, int(out.dtype == torch.float64),
+                                  out.data_ptr(), stream)
+    if rc != 0:
+        raise RuntimeError(f"gen_rows_dev launch failed ({rc})")
+    return out
+
+
+def graph_spec(seed, n, p, law, wmax=0, dtype=np.float32, g=0) -> GraphSpec:
+    """The description of graph(seed, n, p, law, wmax, dtype, g) that gen_row_cb
+    regenerates rows from."""
+    return GraphSpec(seed, g, n, threshold(p), law, int(np.dtype(dtype) == np.float64), wmax)
+
+
+def row_fn():
+    """Address of gen_row_cb (for C code that reads rows on demand)."""
+    return ctypes.cast(_load().gen_row_cb, ctypes.c_void_p).value
 
 
 def _load():
@@ -53,6 +114,8 @@ def _load():
     lib.gen_graph_n.restype = i64
     lib.gen_graph_density.argtypes = [u64, u64, ctypes.c_double, ctypes.c_double]
     lib.gen_graph_density.restype = ctypes.c_double
+    lib.gen_row_cb.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    lib.gen_row_cb.restype = None
     _lib = lib
     return lib
 

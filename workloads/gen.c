@@ -111,6 +111,31 @@ void gen_rows_f64(uint64_t seed, uint64_t g, int64_t n, int64_t r0, int64_t r1, 
     }
 }
 
+/* One row of a graph, serially, for callers that regenerate rows on demand (a
+ * search over a matrix too large to keep in host memory): the graph is described
+ * by ctx, row i is written to out as n doubles, with the value gen_rows_f32 or
+ * gen_rows_f64 gives that entry (so float rows are rounded to float first).
+ * Safe to call from several threads at once. */
+typedef struct {
+    uint64_t seed, g;
+    int64_t n;
+    uint64_t thresh32;
+    int32_t law, is_f64;
+    int64_t wmax;
+} gen_graph_t;
+
+void gen_row_cb(const void *ctx, int64_t i, double *out)
+{
+    const gen_graph_t *G = (const gen_graph_t *)ctx;
+    const uint64_t ek = gen_gkey(G->seed, 0, G->g), wk = gen_gkey(G->seed, 1, G->g);
+    for (int64_t j = 0; j < G->n; ++j) {
+        if (i == j) { out[j] = 0.0; continue; }
+        if (!present(ek, (uint64_t)i, (uint64_t)j, G->thresh32)) { out[j] = INFINITY; continue; }
+        const double w = weight_of(G->law, draw(wk, (uint64_t)i, (uint64_t)j), G->wmax, G->is_f64);
+        out[j] = G->is_f64 ? w : (double)(float)w;
+    }
+}
+
 /* Standard normal draws (Box-Muller on two stream-2 uniforms), n x n, float32.
  * u1 = (top53(h1) + 1) * 2^-53 in (0, 1], u2 = top53(h2) * 2^-53 in [0, 1),
  * h1 = draw(i, 2j), h2 = draw(i, 2j + 1); z = sqrt(-2 ln u1) cos(2 pi u2). */
