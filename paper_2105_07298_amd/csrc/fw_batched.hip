@@ -50,6 +50,18 @@ __device__ __forceinline__ double bmin(double a, double b) {  // the instruction
     return r;
 }
 
+// threadIdx.x hidden from loop-invariant code motion.  Every tile step derives
+// its LDS and global offsets from the thread index; left alone, the compiler
+// computes all of them once per graph and keeps them live through every phase,
+// which took the kernel from about 115 to about 245 registers and made it spill
+// at the 168 that three workgroups per CU allow.  Recomputing them per step
+// costs a few instructions per tile.
+__device__ __forceinline__ int opaque_tid() {
+    int v = (int)threadIdx.x;
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 template <typename T, int W> struct VecT {
     typedef T type __attribute__((ext_vector_type(W)));
 };
@@ -102,20 +114,44 @@ struct Graph {
     // for its column k = J0 + column, so the product does not redo it for every
     // entry of the tile it updates.
     __device__ void stage(T *s, uint16_t *l, int I0, int J0, uint32_t kb1 = 0) const {
-        constexpr int IT = TB * TB / NT;
+        Staged st;
+        fetch(st, I0, J0);
+        put(st, s, l, I0, J0, kb1);
+    }
+    // stage() in two halves, so that a tile's loads can be in flight while the
+    // previous tile's product runs: fetch issues the loads (the entry clamped
+    // into the graph, labels packed two per word), put substitutes the padding
+    // values and writes LDS.
+    static constexpr int IT = TB * TB / NT;
+    struct Staged {
         T v[IT];
-        uint32_t w[PATH ? IT : 1];
+        uint32_t w[PATH ? IT / 2 : 1];
+    };
+    __device__ void fetch(Staged &st, int I0, int J0) const {
+        const int tid = opaque_tid();
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
-            const int q = (int)threadIdx.x + it * NT, rr = q / TB, cc = q % TB;
-            v[it] = ld_d(I0 + rr, J0 + cc);
-            if (PATH) w[it] = ld_p(I0 + rr, J0 + cc);
+            const int q = tid + it * NT, rr = q / TB, cc = q % TB;
+            st.v[it] = elem(D, at(I0 + rr, J0 + cc));
+            if (PATH) {
+                const uint32_t w = elem((uint16_t *)P, at(I0 + rr, J0 + cc));
+                st.w[it / 2] = (it % 2) ? (st.w[it / 2] | (w << 16)) : w;
+            }
         }
+    }
+    __device__ void put(const Staged &st, T *s, uint16_t *l, int I0, int J0, uint32_t kb1 = 0) const {
+        const int tid = opaque_tid();
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
-            const int q = (int)threadIdx.x + it * NT, rr = q / TB, cc = q % TB;
-            s[rr * ST + cc] = v[it];
-            if (PATH) l[rr * ST + cc] = (uint16_t)(kb1 ? max(w[it], kb1 + (uint32_t)cc) : w[it]);
+            const int q = tid + it * NT, rr = q / TB, cc = q % TB;
+            const int i = I0 + rr, j = J0 + cc;
+            const bool in = i < n && j < n;
+            const T pad = i == j ? (T)0 : inf_b<T>();
+            s[rr * ST + cc] = in ? (PATH ? canon(st.v[it]) : st.v[it]) : pad;
+            if (PATH) {
+                const uint32_t w = in ? ((st.w[it / 2] >> (16 * (it % 2))) & 0xffffu) : 0u;
+                l[rr * ST + cc] = (uint16_t)(kb1 ? max(w, kb1 + (uint32_t)cc) : w);
+            }
         }
     }
     // The thread's entries of tile (I0, J0): from global memory ...
@@ -260,7 +296,12 @@ template <typename T, int TB, bool PATH>
 __device__ void solve_graph(Graph<T, TB, PATH> g, T *sa, T *sb, uint16_t *la, uint16_t *lb) {
     using G = Graph<T, TB, PATH>;
     constexpr int RM = G::RM, RN = G::RN, VB = G::VB, HN = G::HN, ST = G::ST;
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    int tx, ty;  // re-derived per step (opaque_tid)
+    auto thread_xy = [&]() {
+        const int tid = opaque_tid();
+        tx = tid % 16;
+        ty = tid / 16;
+    };
     const int n = g.n;
     if (PATH) {
         for (uint32_t x = threadIdx.x; x < (uint32_t)(n * n); x += NT) G::elem((uint16_t *)g.P, x) = 0;  // no label
@@ -271,6 +312,7 @@ __device__ void solve_graph(Graph<T, TB, PATH> g, T *sa, T *sb, uint16_t *la, ui
     uint32_t p[RM][RN];
     for (int r = 0; r < R; ++r) {
         const int k0 = r * TB;
+        thread_xy();
         // Phase 1: close the diagonal block in LDS.  Row k and column k do not
         // change at step k (D[k][k] = 0: their candidates equal the current
         // value with a label that is not smaller), so updating in place while
@@ -320,6 +362,7 @@ __device__ void solve_graph(Graph<T, TB, PATH> g, T *sa, T *sb, uint16_t *la, ui
         // Phases 2 and 3: each panel tile is one product with the closed block
         // (the row panel as its right operand, the column panel as its left).
         for (int t = 0; t < 2 * (R - 1); ++t) {
+            thread_xy();
             const bool rowp = t < R - 1;
             const int o0 = rowp ? t : t - (R - 1);
             const int o = o0 < r ? o0 : o0 + 1;
@@ -334,17 +377,25 @@ __device__ void solve_graph(Graph<T, TB, PATH> g, T *sa, T *sb, uint16_t *la, ui
         // Phase 4: every other tile, product of its final column-panel tile
         // (staged once per tile row) and row-panel tile; with labels, only the
         // entries that decrease are read back and written.
-        for (int t = 0; t < (R - 1) * (R - 1); ++t) {
+        // The row-panel tile of step t + 1 is loaded into registers while step
+        // t's product runs (its LDS buffer is busy until the barrier after it).
+        const int T4 = (R - 1) * (R - 1);
+        auto col_of = [&](int t) { const int bj0 = t % (R - 1); return (bj0 < r ? bj0 : bj0 + 1) * TB; };
+        typename G::Staged nb;
+        if (T4 > 0) g.fetch(nb, k0, col_of(0));
+        for (int t = 0; t < T4; ++t) {
+            thread_xy();
             const int bi0 = t / (R - 1), bj0 = t % (R - 1);
-            const int bi = bi0 < r ? bi0 : bi0 + 1, bj = bj0 < r ? bj0 : bj0 + 1;
-            const int I0 = bi * TB, J0 = bj * TB;
+            const int bi = bi0 < r ? bi0 : bi0 + 1;
+            const int I0 = bi * TB, J0 = col_of(t);
             if (bj0 == 0) g.stage(sa, la, I0, k0, (uint32_t)(k0 + 1));
-            g.stage(sb, lb, k0, J0);
+            g.put(nb, sb, lb, k0, J0);
             if (PATH)
                 g.load_d0(d, p, I0, J0, tx, ty);
             else
                 g.load(d, p, I0, J0, tx, ty);
             __syncthreads();
+            if (t + 1 < T4) g.fetch(nb, k0, col_of(t + 1));
             G::template product<true>(d, p, sa, la, sb, lb, k0, tx, ty);
             if (PATH)
                 g.store_changed(d, p, I0, J0, tx, ty);
