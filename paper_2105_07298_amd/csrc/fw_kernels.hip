@@ -273,13 +273,16 @@ __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__re
 }
 
 // k per staged chunk of the last phase's panels: the whole block, halved while
-// the two panels of a chunk take more than 40 KB of LDS (four workgroups per CU
-// need at most 40 KB each of the 160 KB).
+// the two panels of a chunk take more than the LDS share of the workgroups per CU
+// that the kernel's registers allow: 40 KB (four of the 160 KB), and 32 KB (five)
+// for the float32 64 x 64 tile, whose 95 VGPRs allow five waves per SIMD
+// (measured at n = 16384: with P 188.8 -> 186.0 ms, distances 152.1 -> 149.0 ms).
 template <typename T>
 constexpr int p4_kchunk(int TB, int BM, int BN) {
     int kc = TB;
     const int v = 16 / (int)sizeof(T);
-    while (kc > 2 * v && (BM * (kc + v) + kc * BN) * (int)sizeof(T) > 40 * 1024) kc /= 2;
+    const int cap = (sizeof(T) == 4 && BM == 64 && BN == 64) ? 32 * 1024 : 40 * 1024;
+    while (kc > 2 * v && (BM * (kc + v) + kc * BN) * (int)sizeof(T) > cap) kc /= 2;
     return kc;
 }
 
@@ -329,7 +332,11 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
     constexpr int AST = KC + V;
     // Old C values are requested before the panel loads when they fit the
     // register budget (up to 128 bytes per thread), else after the k-loop.
-    constexpr bool PREFETCH_C = RM * RN * (int)sizeof(T) <= 128;
+    // float64 never prefetches: its 4 x 4 tile's 32 prefetch registers took the
+    // launch from 121 to 167 VGPRs, i.e. from four waves per SIMD to three, and
+    // the fourth wave hides more latency than the prefetch (measured at
+    // n = 16384: with P 414.7 -> 403.9 ms, distances 348.3 -> 325.8 ms).
+    constexpr bool PREFETCH_C = RM * RN * (int)sizeof(T) <= 128 && sizeof(T) != 8;
 
     __shared__ __attribute__((aligned(16))) T As[BM * AST];
     __shared__ __attribute__((aligned(16))) T Bs[KC * BN];
