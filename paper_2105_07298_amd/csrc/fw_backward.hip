@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(NT) k_backward_tree(const T *__restrict__ D, c
     }
 }
 
-// One wave per (graph, column j); LDS: acc double[n].  Consecutive workgroups
+// One wave per (graph, column j); LDS: acc double[n], owner int16[n].  Consecutive workgroups
 // are dispatched round-robin over the 8 XCDs, so workgroup x takes column
 // (x mod 8) * per + x / 8: each XCD walks a contiguous range of columns, whose
 // strided reads of U and S share cache lines in that XCD's L2.
@@ -154,6 +154,7 @@ __global__ void __launch_bounds__(64) k_backward_columns(const int16_t *__restri
                                                         T *__restrict__ gW, int n, int per) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     double *acc = (double *)lds;
+    int16_t *owner = (int16_t *)(acc + n);
     const int x = blockIdx.x;
     const int j = (x % 8) * per + x / 8;
     if (j >= n) return;
@@ -169,6 +170,22 @@ __global__ void __launch_bounds__(64) k_backward_columns(const int16_t *__restri
             u = U[base + (int64_t)i * n + j];
             s = SV[base + (int64_t)i * n + j];
         }
+        // Fast path: when no two lanes of this group share a predecessor, every
+        // acc[u] gets at most one addition from the group, so the order is fixed
+        // without the lane loop.  A clash is detected by every lane writing its
+        // number to owner[u] and reading it back (one wave: the read follows the
+        // write); whichever lane's write lands, a lane that shares u with another
+        // reads a number not its own.
+        if (u >= 0) owner[u] = (int16_t)lane;
+        // The read must go to LDS (another lane may have written the same word):
+        // the compiler barrier keeps it from being forwarded from this lane's
+        // own store.  LDS instructions of one wave complete in order.
+        asm volatile("" ::: "memory");
+        const bool clash = u >= 0 && owner[u] != (int16_t)lane;
+        if (__ballot(clash) == 0) {
+            if (u >= 0) acc[u] += s;
+            continue;
+        }
         const uint64_t sb = __builtin_bit_cast(uint64_t, s);
         const int slo = (int)(uint32_t)sb, shi = (int)(uint32_t)(sb >> 32);
         double sum = 0.0;
@@ -183,7 +200,6 @@ __global__ void __launch_bounds__(64) k_backward_columns(const int16_t *__restri
             leader = leader && !(same && l < lane);
         }
         if (leader && u >= 0) acc[u] += sum;  // one leader per u in this group of sources
-        __syncthreads();
     }
     for (int u = lane; u < n; u += 64) gW[base + (int64_t)u * n + j] = (T)acc[u];
 }
@@ -200,7 +216,7 @@ hipError_t launch_backward(const T *D, const int32_t *P, const T *G, T *gW, int 
                        n);
     const int per = (n + 7) / 8;
     hipLaunchKernelGGL((k_backward_columns<T>), dim3((unsigned)(8 * per), (unsigned)batch), dim3(64),
-                       (size_t)n * sizeof(double), s, U, SV, gW, n, per);
+                       (size_t)n * (sizeof(double) + sizeof(int16_t)), s, U, SV, gW, n, per);
     return hipGetLastError();
 }
 

@@ -310,9 +310,25 @@ __device__ void solve_graph(Graph<T, TB, PATH> g, T *sa, T *sb, uint16_t *la, ui
     const int R = (n + TB - 1) / TB;
     T d[RM][RN];
     uint32_t p[RM][RN];
+    // The tile a step stages into sb / lb (a phase 2/3 panel tile, or a last-phase
+    // row-panel tile) is loaded into registers (nb) while the previous step's
+    // work runs, and written to LDS after that step's barrier.  Every tile loaded
+    // early is final by then: panel tiles change only in their own step, and
+    // row-panel tiles are final after phases 2/3, whose steps all end with a
+    // barrier.
+    typename G::Staged nb;
     for (int r = 0; r < R; ++r) {
         const int k0 = r * TB;
         thread_xy();
+        const int T23 = 2 * (R - 1), T4 = (R - 1) * (R - 1);
+        auto panel_of = [&](int t, int &I0, int &J0) {
+            const bool rowp = t < R - 1;
+            const int o0 = rowp ? t : t - (R - 1);
+            const int o = o0 < r ? o0 : o0 + 1;
+            I0 = rowp ? k0 : o * TB;
+            J0 = rowp ? o * TB : k0;
+        };
+        auto col_of = [&](int t) { const int bj0 = t % (R - 1); return (bj0 < r ? bj0 : bj0 + 1) * TB; };
         // Phase 1: close the diagonal block in LDS.  Row k and column k do not
         // change at step k (D[k][k] = 0: their candidates equal the current
         // value with a label that is not smaller), so updating in place while
@@ -320,6 +336,11 @@ __device__ void solve_graph(Graph<T, TB, PATH> g, T *sa, T *sb, uint16_t *la, ui
         g.stage(sa, la, k0, k0);
         __syncthreads();
         G::load_lds(d, p, sa, la, tx, ty);
+        if (T23 > 0) {  // the first panel tile, under phase 1
+            int I0, J0;
+            panel_of(0, I0, J0);
+            g.fetch(nb, I0, J0);
+        }
         for (int k = 0; k < TB; ++k) {
             T a[RM];
             uint32_t pa[RM];
@@ -361,15 +382,21 @@ __device__ void solve_graph(Graph<T, TB, PATH> g, T *sa, T *sb, uint16_t *la, ui
         // The closed diagonal block stays in sa / la for the panels.
         // Phases 2 and 3: each panel tile is one product with the closed block
         // (the row panel as its right operand, the column panel as its left).
-        for (int t = 0; t < 2 * (R - 1); ++t) {
+        for (int t = 0; t < T23; ++t) {
             thread_xy();
             const bool rowp = t < R - 1;
-            const int o0 = rowp ? t : t - (R - 1);
-            const int o = o0 < r ? o0 : o0 + 1;
-            const int I0 = rowp ? k0 : o * TB, J0 = rowp ? o * TB : k0;
-            g.stage(sb, lb, I0, J0);  // the old panel tile
+            int I0, J0;
+            panel_of(t, I0, J0);
+            g.put(nb, sb, lb, I0, J0);  // the old panel tile
             __syncthreads();
             G::load_lds(d, p, sb, lb, tx, ty);
+            if (t + 1 < T23) {  // the next panel tile, or the first row-panel tile of phase 4
+                int I1, J1;
+                panel_of(t + 1, I1, J1);
+                g.fetch(nb, I1, J1);
+            } else {
+                g.fetch(nb, k0, col_of(0));
+            }
             G::product(d, p, rowp ? sa : sb, rowp ? la : lb, rowp ? sb : sa, rowp ? lb : la, k0, tx, ty);
             g.store(d, p, I0, J0, tx, ty);
             __syncthreads();
@@ -377,12 +404,6 @@ __device__ void solve_graph(Graph<T, TB, PATH> g, T *sa, T *sb, uint16_t *la, ui
         // Phase 4: every other tile, product of its final column-panel tile
         // (staged once per tile row) and row-panel tile; with labels, only the
         // entries that decrease are read back and written.
-        // The row-panel tile of step t + 1 is loaded into registers while step
-        // t's product runs (its LDS buffer is busy until the barrier after it).
-        const int T4 = (R - 1) * (R - 1);
-        auto col_of = [&](int t) { const int bj0 = t % (R - 1); return (bj0 < r ? bj0 : bj0 + 1) * TB; };
-        typename G::Staged nb;
-        if (T4 > 0) g.fetch(nb, k0, col_of(0));
         for (int t = 0; t < T4; ++t) {
             thread_xy();
             const int bi0 = t / (R - 1), bj0 = t % (R - 1);
