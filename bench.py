@@ -49,7 +49,7 @@ DT_CODE = {"f32": 0, "f64": 1, "f16": 2}
 # The last-phase kernel's source: its file and the headers it includes (the
 # measured traffic in TRAFFIC_FILE is valid for these exact sources only).
 KERNEL_SRC = [os.path.join(ROOT, "paper_2105_07298_amd", "csrc", f)
-              for f in ("fw_kernels.hip", "fw_internal.h", "fw_lex.h", "fw_tiles.h")]
+              for f in ("fw_kernels.hip", "fw_internal.h", "fw_lex.h", "fw_tiles.h", "fw_device.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 

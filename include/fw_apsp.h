@@ -192,10 +192,11 @@ fw_status_t fw_apsp_batched(fw_dtype_t dt, int32_t batch, const int32_t *n_host,
 /*
  * Choices of fw_apsp_batched, for tuning and for the tests that show results
  * do not depend on them.
- *   small_max_n  tile choice: a graph is processed in 64 x 64 tiles when
- *                n > small_max_n and 64-tiles pad it to no more vertices than
- *                32-tiles would (n mod 64 = 0 or > 32), otherwise in 32 x 32
- *                tiles; -1 keeps the tuned choice.
+ *   small_max_n  tile choice: k >= 0 processes a graph in 32 x 32 tiles when
+ *                n <= k and in 64 x 64 tiles otherwise; -1 keeps the tuned
+ *                choice (made per size class of 32 vertices, n in
+ *                (32c, 32c + 32], from timings of both tilings; 64 x 64 above
+ *                2048 vertices).
  *   route        which graphs fw_apsp solves instead of the persistent launch:
  *                0 the rule given at fw_apsp_batched, -1 none, k > 0 every
  *                graph with n >= k.

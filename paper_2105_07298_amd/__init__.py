@@ -104,7 +104,8 @@ def apsp_batched_(Dcat, ns, offsets, Pcat=None, small_max_n: int = -1, route: in
     n_b x n_b weight matrix row-major at element offset offsets[b]; overwritten
     with distances.  ns (int32) and offsets (int64) are host sequences of length
     batch.  Pcat (int32, same length as Dcat) receives the path matrices.
-    small_max_n: graphs with n <= small_max_n use 32 x 32 tiles (-1 = tuned).
+    small_max_n: graphs with n <= small_max_n use 32 x 32 tiles, the others 64 x 64
+    (-1 = the tuned choice per 32-vertex size class).
     route: graphs solved by fw_apsp instead of the persistent launch (0 = those
     that would hold far more than their share of the batch's work, -1 = none,
     k > 0 = every graph with n >= k).

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfwapsp.so")
 
-SOURCES = ["fw_kernels.hip", "fw_batched.hip", "fw_backward.hip", "fw_validate.hip", "fw_runtime.cpp", "fw_ooc.cpp"]
+SOURCES = ["fw_kernels.hip", "fw_ooc_kernels.hip", "fw_batched.hip", "fw_backward.hip", "fw_validate.hip", "fw_runtime.cpp", "fw_ooc.cpp"]
 
 # Packed FP32 instructions are kept out of the generated code (the feature is
 # disabled, not merely avoided): two scalar adds plus one 3-way min per pair of

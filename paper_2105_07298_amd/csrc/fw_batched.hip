@@ -468,13 +468,13 @@ constexpr int batched_wgs_per_cu() {
 
 // Persistent batched kernel.  jobs[0] holds the queue counter (0 when the launch
 // starts), jobs[1] the number of jobs, and jobs[2 + 2q], jobs[3 + 2q] the offset
-// and n of queue slot q.  A graph uses 64 x 64 tiles when n > small_max_n (from
-// the tuning table) and 64-tiles pad it to no more vertices than 32-tiles would
-// (n mod 64 = 0 or > 32); otherwise 32 x 32 tiles.  Both share the LDS arrays,
-// sized for 64.
+// and n of queue slot q.  A graph uses 32 x 32 tiles when n <= small_max_n;
+// above, its size class c = (n - 1) / 32 decides: 64 x 64 tiles when c >= 64 or
+// bit c of tile64 is set (the tuning table holds the measured choice per class),
+// 32 x 32 otherwise.  Both share the LDS arrays, sized for 64.
 template <typename T, bool PATH>
 __global__ void __launch_bounds__(NT, (batched_wgs_per_cu<T, PATH>())) k_batched(T *__restrict__ dist, int32_t *__restrict__ path,
-                                               int64_t *__restrict__ jobs, int small_max_n) {
+                                               int64_t *__restrict__ jobs, int small_max_n, uint64_t tile64) {
     constexpr int ST = Graph<T, 64, PATH>::ST;
     __shared__ __attribute__((aligned(16))) T sa[64 * ST];
     __shared__ __attribute__((aligned(16))) T sb[64 * ST];
@@ -493,7 +493,8 @@ __global__ void __launch_bounds__(NT, (batched_wgs_per_cu<T, PATH>())) k_batched
         const int64_t off = ((int64_t)__builtin_amdgcn_readfirstlane((int)(off0 >> 32)) << 32) |
                             (uint32_t)__builtin_amdgcn_readfirstlane((int)off0);
         const int n = __builtin_amdgcn_readfirstlane((int)jobs[3 + 2 * q]);
-        const bool small = (n <= small_max_n) || (((n + 63) & ~63) != ((n + 31) & ~31));
+        const int c = (n - 1) >> 5;
+        const bool small = (n <= small_max_n) || (c < 64 && !((tile64 >> c) & 1));
         if (small) {
             Graph<T, 32, PATH> g{dist + off, PATH ? path + off : nullptr, n};
             solve_graph<T, 32, PATH>(g, sa, sb, la, lb);
@@ -573,11 +574,13 @@ static __device__ __align__(256) int64_t scratch[2 + 2 * (size_t)kNoAllocMaxBatc
 }  // namespace
 
 template <typename T>
-hipError_t launch_batched(T *dist, int32_t *path, int64_t *jobs, int small_max_n, int grid, hipStream_t s) {
+hipError_t launch_batched(T *dist, int32_t *path, int64_t *jobs, BatchedTiles tiles, int grid, hipStream_t s) {
     if (path)
-        hipLaunchKernelGGL((k_batched<T, true>), dim3(grid), dim3(NT), 0, s, dist, path, jobs, small_max_n);
+        hipLaunchKernelGGL((k_batched<T, true>), dim3(grid), dim3(NT), 0, s, dist, path, jobs, tiles.small_max_n,
+                           tiles.tile64);
     else
-        hipLaunchKernelGGL((k_batched<T, false>), dim3(grid), dim3(NT), 0, s, dist, path, jobs, small_max_n);
+        hipLaunchKernelGGL((k_batched<T, false>), dim3(grid), dim3(NT), 0, s, dist, path, jobs, tiles.small_max_n,
+                           tiles.tile64);
     return hipGetLastError();
 }
 
@@ -614,7 +617,7 @@ int batched_occupancy(bool path) {
 
 template int batched_occupancy<float>(bool);
 template int batched_occupancy<double>(bool);
-template hipError_t launch_batched<float>(float *, int32_t *, int64_t *, int, int, hipStream_t);
-template hipError_t launch_batched<double>(double *, int32_t *, int64_t *, int, int, hipStream_t);
+template hipError_t launch_batched<float>(float *, int32_t *, int64_t *, BatchedTiles, int, hipStream_t);
+template hipError_t launch_batched<double>(double *, int32_t *, int64_t *, BatchedTiles, int, hipStream_t);
 
 }  // namespace fw

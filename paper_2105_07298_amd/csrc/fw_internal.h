@@ -67,11 +67,16 @@ hipError_t launch_resolve(const T *D, T *DT, const uint16_t *L, int32_t *P, int6
 
 // Persistent batched launch (one workgroup per graph at a time).  jobs is a
 // device table of 2 + 2*njobs int64: [0] the queue counter (must be 0), [1]
-// njobs, then (element offset, n) per queue slot in processing order.  Graphs
-// with n <= small_max_n, or that 64-tiles would pad further than 32-tiles, use
-// 32 x 32 tiles; the others 64 x 64.
+// njobs, then (element offset, n) per queue slot in processing order.  The tile
+// of a graph: 32 x 32 when n <= tiles.small_max_n, else by its size class
+// c = (n - 1) / 32: 64 x 64 when c >= 64 or bit c of tiles.tile64 is set, 32 x 32
+// otherwise.
+struct BatchedTiles {
+    int small_max_n;
+    uint64_t tile64;
+};
 template <typename T>
-hipError_t launch_batched(T *dist, int32_t *path, int64_t *jobs, int small_max_n, int grid, hipStream_t s);
+hipError_t launch_batched(T *dist, int32_t *path, int64_t *jobs, BatchedTiles tiles, int grid, hipStream_t s);
 
 // The same table built on the device from device arrays nv[batch] (vertex
 // counts) and off[batch] (element offsets), ordered by decreasing n; graphs
@@ -90,9 +95,9 @@ template <typename T>
 int batched_occupancy(bool path);
 
 // Tuning table lookup (tune_table.inc): tile configuration for fw_apsp and the
-// small-graph split of fw_apsp_batched.
+// per-size-class tile choice of fw_apsp_batched.
 TileCfg tuned_config(int dtype, bool path, int64_t n);  // dtype: an fw_dtype_t code
-int tuned_batched_small_max_n(bool f64, bool path);
+BatchedTiles tuned_batched_tiles(bool f64, bool path);
 
 // Gradient dL/dW (every entry written) from (D, P) and G = dL/dD for batch
 // graphs of n vertices each (contiguous, stride n*n), n <= 4096.  scratch holds

@@ -36,51 +36,13 @@
 #define FW_TILE_FN __host__ __device__ __forceinline__
 #include "fw_internal.h"
 #include "fw_lex.h"
+#include "fw_device.h"
 
 #include <limits.h>
 #include <type_traits>
 
 namespace fw {
 namespace {
-
-constexpr int NT = 256;  // threads per workgroup, every kernel
-
-template <typename T> struct V16;
-template <> struct V16<float> {
-    typedef float type __attribute__((ext_vector_type(4)));
-    static constexpr int n = 4;
-};
-template <> struct V16<double> {
-    typedef double type __attribute__((ext_vector_type(2)));
-    static constexpr int n = 2;
-};
-template <> struct V16<_Float16> {
-    typedef _Float16 type __attribute__((ext_vector_type(8)));
-    static constexpr int n = 8;
-};
-typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
-template <typename T> constexpr bool is_half_v = std::is_same_v<T, _Float16>;
-
-template <typename T> __device__ __forceinline__ T inf_v();
-template <> __device__ __forceinline__ float inf_v<float>() { return __builtin_inff(); }
-template <> __device__ __forceinline__ double inf_v<double>() { return __builtin_inf(); }
-template <> __device__ __forceinline__ _Float16 inf_v<_Float16>() { return (_Float16)__builtin_inff(); }
-
-__device__ __forceinline__ float vmin(float a, float b) { return __builtin_fminf(a, b); }
-// double: the instruction itself.  The library minimum must quiet a signalling
-// NaN operand first, and where an accumulator enters a loop iteration the
-// compiler cannot tell that it is already quiet, so it re-canonicalised every
-// accumulator every iteration (one v_max_f64 per four updates in the last
-// phase).  Lengths here are never NaN (input contract), so the plain
-// instruction gives the same result.
-__device__ __forceinline__ double vmin(double a, double b) {
-    double r;
-    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
-__device__ __forceinline__ _Float16 vmin(_Float16 a, _Float16 b) { return __builtin_elementwise_min(a, b); }
-
-
 
 // ---------------------------------------------------------------------------
 // Phase 1: close the diagonal block.  The block and its P stay in LDS; thread
@@ -609,179 +571,6 @@ __global__ void __launch_bounds__(NT) k_phase4w(T *__restrict__ D, uint16_t *__r
 }
 
 // ---------------------------------------------------------------------------
-// General min-plus update C <- min(C, A (x) B) for the out-of-core driver: C is
-// M x N, A is M x K, B is K x N, each with its own leading dimension (M, N
-// multiples of the tile edges, K of KT).  Same register-blocked tiles as
-// k_phase4, but each workgroup walks all of K in chunks of KT, re-staging the
-// two panel chunks in LDS, so that its C tile is read and written once per
-// product.  Distances only.
-template <typename T, int KT, int BM, int BN>
-__global__ void __launch_bounds__(NT) k_minplus(T *__restrict__ C, int64_t ldc, const T *__restrict__ A, int64_t lda,
-                                               const T *__restrict__ B, int64_t ldb, int64_t K, TileSel sel) {
-    constexpr int RM = BM / 16, RN = BN / 16;
-    using vec = typename V16<T>::type;
-    constexpr int V = V16<T>::n;
-    constexpr int TX = BN / RN, TY = NT / TX;
-    static_assert(TY * RM == BM && RN % V == 0, "tile shape");
-    constexpr int HN = RN / V, CS = BN / HN;
-    constexpr int AST = KT + V;
-    __shared__ __attribute__((aligned(16))) T As[BM * AST];
-    __shared__ __attribute__((aligned(16))) T Bs[KT * BN];
-
-    int bi, bj;
-    if (!select_tile<false>(sel, blockIdx.x, bi, bj)) return;
-    const int64_t I0 = (int64_t)bi * BM, J0 = (int64_t)bj * BN;
-    const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
-
-    T acc[RM][RN];
-#pragma unroll
-    for (int ii = 0; ii < RM; ++ii)
-#pragma unroll
-        for (int jj = 0; jj < RN; ++jj) acc[ii][jj] = inf_v<T>();
-
-    for (int64_t k0 = 0; k0 < K; k0 += KT) {
-        __syncthreads();  // the previous chunk is consumed
-        for (int q = tid; q < BM * (KT / V); q += NT) {
-            const int row = q / (KT / V), kv = q % (KT / V);
-            *(vec *)(As + row * AST + kv * V) = *(const vec *)(A + (I0 + row) * lda + k0 + kv * V);
-        }
-        for (int q = tid; q < KT * (BN / V); q += NT) {
-            const int krow = q / (BN / V), cv = q % (BN / V);
-            *(vec *)(Bs + krow * BN + cv * V) = *(const vec *)(B + (k0 + krow) * ldb + J0 + cv * V);
-        }
-        __syncthreads();
-#pragma unroll 2
-        for (int kv = 0; kv < KT / V; ++kv) {
-            vec a[RM];
-#pragma unroll
-            for (int ii = 0; ii < RM; ++ii) a[ii] = *(const vec *)(As + (ty + TY * ii) * AST + kv * V);
-#pragma unroll
-            for (int kk = 0; kk < V; kk += 2) {
-                vec b0[HN], b1[HN];
-#pragma unroll
-                for (int h = 0; h < HN; ++h) {
-                    b0[h] = *(const vec *)(Bs + (kv * V + kk) * BN + h * CS + tx * V);
-                    b1[h] = *(const vec *)(Bs + (kv * V + kk + 1) * BN + h * CS + tx * V);
-                }
-#pragma unroll
-                for (int ii = 0; ii < RM; ++ii)
-#pragma unroll
-                    for (int h = 0; h < HN; ++h)
-#pragma unroll
-                        for (int e = 0; e < V; ++e) {
-                            T &x = acc[ii][h * V + e];
-                            x = vmin(vmin(x, a[ii][kk] + b0[h][e]), a[ii][kk + 1] + b1[h][e]);
-                        }
-            }
-        }
-    }
-#pragma unroll
-    for (int ii = 0; ii < RM; ++ii)
-#pragma unroll
-        for (int h = 0; h < HN; ++h) {
-            T *cp = C + (I0 + ty + TY * ii) * ldc + J0 + h * CS + tx * V;
-            vec nv = *(const vec *)cp;
-            bool ch = false;
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const T s = acc[ii][h * V + e];
-                ch |= s < nv[e];
-                nv[e] = vmin(nv[e], s);
-            }
-            if (ch) *(vec *)cp = nv;
-        }
-}
-
-// Lexicographic form of the general update, for the out-of-core driver with
-// path labels: (C, PC) <- lexmin over k of (A[i][k] + B[k][j],
-// max(PA[i][k], kbase + k, PB[k][j])) and the old (C, PC) -- the rule phases 1-3
-// apply, with kbase the global index of A's first column.  64 x 64 tiles, 16 x 16
-// threads with 4 x 4 entries each (rows ty + 16 ii, columns tx + 16 jj), panel
-// chunks of KT values of k with their labels in LDS.
-template <typename T, int KT>
-__global__ void __launch_bounds__(NT) k_minplus_lex(T *__restrict__ C, int32_t *__restrict__ PC, int64_t ldc,
-                                                   const T *__restrict__ A, const int32_t *__restrict__ PA, int64_t lda,
-                                                   const T *__restrict__ B, const int32_t *__restrict__ PB, int64_t ldb,
-                                                   int64_t K, int32_t kbase, TileSel sel) {
-    constexpr int TS = 16, RM = 4, BM = 64, BN = 64, STA = KT + 1, STB = BN + 1;
-    __shared__ T sa[BM * STA];
-    __shared__ uint32_t spa[BM * STA];  // labels + 1, as in phases 1-3
-    __shared__ T sb[KT * STB];
-    __shared__ uint32_t spb[KT * STB];
-    int bi, bj;
-    if (!select_tile<false>(sel, blockIdx.x, bi, bj)) return;
-    const int64_t I0 = (int64_t)bi * BM, J0 = (int64_t)bj * BN;
-    const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
-    T d[RM][RM], d0[RM][RM];
-    uint32_t p[RM][RM], p0[RM][RM];
-#pragma unroll
-    for (int ii = 0; ii < RM; ++ii)
-#pragma unroll
-        for (int jj = 0; jj < RM; ++jj) {
-            const int64_t g = (I0 + ty + TS * ii) * ldc + J0 + tx + TS * jj;
-            d[ii][jj] = d0[ii][jj] = canon(C[g]);
-            p[ii][jj] = p0[ii][jj] = (uint32_t)(PC[g] + 1);
-        }
-    for (int64_t k0 = 0; k0 < K; k0 += KT) {
-        __syncthreads();  // the previous chunk is consumed
-        for (int q = threadIdx.x; q < BM * KT; q += NT) {
-            const int row = q / KT, kk = q % KT;
-            const int64_t g = (I0 + row) * lda + k0 + kk;
-            sa[row * STA + kk] = canon(A[g]);
-            spa[row * STA + kk] = (uint32_t)(PA[g] + 1);
-        }
-        for (int q = threadIdx.x; q < KT * BN; q += NT) {
-            const int kr = q / BN, c = q % BN;
-            const int64_t g = (k0 + kr) * ldb + J0 + c;
-            sb[kr * STB + c] = canon(B[g]);
-            spb[kr * STB + c] = (uint32_t)(PB[g] + 1);
-        }
-        __syncthreads();
-        for (int kk = 0; kk < KT; ++kk) {
-            T a[RM], b[RM];
-            uint32_t pa[RM], pb[RM];
-#pragma unroll
-            for (int ii = 0; ii < RM; ++ii) {
-                a[ii] = sa[(ty + TS * ii) * STA + kk];
-                pa[ii] = spa[(ty + TS * ii) * STA + kk];
-            }
-#pragma unroll
-            for (int jj = 0; jj < RM; ++jj) {
-                b[jj] = sb[kk * STB + tx + TS * jj];
-                pb[jj] = spb[kk * STB + tx + TS * jj];
-            }
-            const uint32_t kg1 = (uint32_t)(kbase + k0 + kk + 1);
-#pragma unroll
-            for (int ii = 0; ii < RM; ++ii) {
-                const uint32_t mi = max(pa[ii], kg1);
-#pragma unroll
-                for (int jj = 0; jj < RM; ++jj) lex_take_u(d[ii][jj], p[ii][jj], a[ii] + b[jj], max(mi, pb[jj]));
-            }
-        }
-    }
-#pragma unroll
-    for (int ii = 0; ii < RM; ++ii)
-#pragma unroll
-        for (int jj = 0; jj < RM; ++jj) {
-            if (d[ii][jj] == d0[ii][jj] && p[ii][jj] == p0[ii][jj]) continue;
-            const int64_t g = (I0 + ty + TS * ii) * ldc + J0 + tx + TS * jj;
-            C[g] = d[ii][jj];
-            PC[g] = (int32_t)p[ii][jj] - 1;
-        }
-}
-
-// Labels of a block closed in isolation (local vertex indices, -1 where the
-// entry did not change) turned into global ones: unchanged entries keep their
-// old label, changed ones get base + local.
-__global__ void k_merge_labels(int32_t *__restrict__ P, const int32_t *__restrict__ Plocal, int64_t count,
-                               int32_t base) {
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < count; x += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t l = Plocal[x];
-        if (l >= 0) P[x] = base + l;
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Label resolution (path mode, after the last round).  Entry (i, j) pending
 // from round r (L = r + 1) last decreased in the last phase of round r, to
 // S = min over k in K_r of A[i][k] + B[k][j].  For every k that attains S, the
@@ -969,10 +758,6 @@ __global__ void k_pad_out(const T *__restrict__ src, int64_t npad, T *__restrict
     }
 }
 
-inline unsigned grid_for(int64_t n) {
-    int64_t g = (n + NT - 1) / NT;
-    return (unsigned)(g < 8192 ? (g < 1 ? 1 : g) : 8192);
-}
 
 template <typename T, int TB>
 void launch_p123(T *D, int32_t *P, uint16_t *L, int64_t ld, int r, hipStream_t s) {
@@ -1153,36 +938,6 @@ bool pairs_supported(TileCfg c) {
 }
 
 template <typename T>
-hipError_t launch_minplus(T *C, int64_t ldc, const T *A, int64_t lda, const T *B, int64_t ldb, int64_t M, int64_t N,
-                          int64_t K, hipStream_t s) {
-    constexpr int KT = 64, BM = 64, BN = 64;
-    if (M % BM || N % BN || K % KT || M <= 0 || N <= 0 || K <= 0) return hipErrorInvalidValue;
-    TileSel sel;
-    if (!make_tile_sel((int)(M / BM), (int)(N / BN), 0, 0, 0, 1, 0, sel)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_minplus<T, KT, BM, BN>), dim3(8 * sel.per_xcd), dim3(NT), 0, s, C, ldc, A, lda, B, ldb, K,
-                       sel);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_minplus_lex(T *C, int32_t *PC, int64_t ldc, const T *A, const int32_t *PA, int64_t lda, const T *B,
-                              const int32_t *PB, int64_t ldb, int64_t M, int64_t N, int64_t K, int32_t kbase,
-                              hipStream_t s) {
-    constexpr int KT = 32;
-    if (M % 64 || N % 64 || K % KT || M <= 0 || N <= 0 || K <= 0) return hipErrorInvalidValue;
-    TileSel sel;
-    if (!make_tile_sel((int)(M / 64), (int)(N / 64), 0, 0, 0, 1, 0, sel)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_minplus_lex<T, KT>), dim3(8 * sel.per_xcd), dim3(NT), 0, s, C, PC, ldc, A, PA, lda, B, PB,
-                       ldb, K, kbase, sel);
-    return hipGetLastError();
-}
-
-hipError_t launch_merge_labels(int32_t *P, const int32_t *Plocal, int64_t count, int32_t base, hipStream_t s) {
-    hipLaunchKernelGGL(k_merge_labels, dim3(grid_for(count)), dim3(NT), 0, s, P, Plocal, count, base);
-    return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_resolve(const T *D, T *DT, const uint16_t *L, int32_t *P, int64_t ld, int block, hipStream_t s) {
     hipLaunchKernelGGL((k_transpose<T>), dim3((unsigned)(ld / 64), (unsigned)(ld / 64)), dim3(NT), 0, s, D, DT, ld);
     const dim3 grid((unsigned)((ld + NT - 1) / NT), (unsigned)(ld < 65535 ? ld : 65535));
@@ -1231,18 +986,8 @@ hipError_t launch_pad_out(const T *src, int64_t npad, T *dst, int64_t n, hipStre
 template bool config_supported<float>(TileCfg);
 template bool config_supported<double>(TileCfg);
 template int list_configs<float>(TileCfg *, int);
-template hipError_t launch_minplus_lex<float>(float *, int32_t *, int64_t, const float *, const int32_t *, int64_t,
-                                              const float *, const int32_t *, int64_t, int64_t, int64_t, int64_t,
-                                              int32_t, hipStream_t);
-template hipError_t launch_minplus_lex<double>(double *, int32_t *, int64_t, const double *, const int32_t *, int64_t,
-                                               const double *, const int32_t *, int64_t, int64_t, int64_t, int64_t,
-                                               int32_t, hipStream_t);
 template hipError_t launch_fill_blank<float>(float *, int64_t, int64_t, int64_t, bool, hipStream_t);
 template hipError_t launch_fill_blank<double>(double *, int64_t, int64_t, int64_t, bool, hipStream_t);
-template hipError_t launch_minplus<float>(float *, int64_t, const float *, int64_t, const float *, int64_t, int64_t,
-                                          int64_t, int64_t, hipStream_t);
-template hipError_t launch_minplus<double>(double *, int64_t, const double *, int64_t, const double *, int64_t,
-                                           int64_t, int64_t, int64_t, hipStream_t);
 template int list_configs<double>(TileCfg *, int);
 template hipError_t launch_phase123<float>(float *, int32_t *, uint16_t *, int64_t, int, int, hipStream_t);
 template hipError_t launch_phase123<double>(double *, int32_t *, uint16_t *, int64_t, int, int, hipStream_t);

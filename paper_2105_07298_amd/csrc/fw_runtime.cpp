@@ -79,7 +79,7 @@ size_t g_stage_cap = 0;
 hipEvent_t g_stage_ev = nullptr;
 
 struct TuneEntry { int dtype, path; long long n_lo, n_hi; int block, tile_m, tile_n, variant, schedule; };
-struct TuneBatchedEntry { int dtype, path, small_max_n; };
+struct TuneBatchedEntry { int dtype, path; unsigned long long tile64; };
 #include "tune_table.inc"
 
 fw::TileCfg default_cfg(fw_dtype_t dt, int64_t n, bool path) { return fw::tuned_config((int)dt, path, n); }
@@ -320,10 +320,12 @@ TileCfg tuned_config(int dtype, bool path, int64_t n) {
     if (dtype == FW_F16) return {64, 64, 128, FW_VARIANT_PANELS, FW_SCHEDULE_SERIAL};
     return {64, 64, 64, FW_VARIANT_PANELS, FW_SCHEDULE_SERIAL};
 }
-int tuned_batched_small_max_n(bool f64, bool path) {
+BatchedTiles tuned_batched_tiles(bool f64, bool path) {
     for (const TuneBatchedEntry &t : kTuneBatched)
-        if (t.dtype == (f64 ? FW_F64 : FW_F32) && t.path == (int)path) return t.small_max_n;
-    return 0;
+        if (t.dtype == (f64 ? FW_F64 : FW_F32) && t.path == (int)path) return {0, (uint64_t)t.tile64};
+    // untuned: 64-tiles above 768 vertices, and above 64 wherever they pad no
+    // further than 32-tiles
+    return {0, 0xFFFFFFFFFFAAAAA8ull};
 }
 
 void prof_begin_p4(hipStream_t s) {
@@ -489,8 +491,8 @@ fw_status_t fw_apsp_batched_config(fw_dtype_t dt, int32_t batch, const int32_t *
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     hipStream_t s = (hipStream_t)stream;
-    const int small_max_n = (cfg && cfg->small_max_n >= 0) ? cfg->small_max_n
-                                                          : fw::tuned_batched_small_max_n(dt == FW_F64, path != nullptr);
+    const fw::BatchedTiles tiles = (cfg && cfg->small_max_n >= 0) ? fw::BatchedTiles{cfg->small_max_n, ~0ull}
+                                                                  : fw::tuned_batched_tiles(dt == FW_F64, path != nullptr);
     int cus = 0;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
         return hip_fail(e, "CU count");
@@ -549,8 +551,8 @@ fw_status_t fw_apsp_batched_config(fw_dtype_t dt, int32_t batch, const int32_t *
     }
     int grid = cus * occ;
     if (grid > njobs) grid = njobs;
-    e = dt == FW_F32 ? fw::launch_batched<float>((float *)dist, path, (int64_t *)djobs, small_max_n, grid, s)
-                     : fw::launch_batched<double>((double *)dist, path, (int64_t *)djobs, small_max_n, grid, s);
+    e = dt == FW_F32 ? fw::launch_batched<float>((float *)dist, path, (int64_t *)djobs, tiles, grid, s)
+                     : fw::launch_batched<double>((double *)dist, path, (int64_t *)djobs, tiles, grid, s);
     if (e != hipSuccess) return hip_fail(e, "batched launch");
     if ((e = scr.release()) != hipSuccess) return hip_fail(e, "job table free");
     return FW_OK;
@@ -566,12 +568,12 @@ static fw_status_t batched_device_common(fw_dtype_t dt, int32_t batch, const int
         return hip_fail(e, "CU count");
     const bool p = path != nullptr;
     const int occ = dt == FW_F32 ? fw::batched_occupancy<float>(p) : fw::batched_occupancy<double>(p);
-    const int small_max_n = fw::tuned_batched_small_max_n(dt == FW_F64, p);
+    const fw::BatchedTiles tiles = fw::tuned_batched_tiles(dt == FW_F64, p);
     int grid = cus * occ;
     if (grid > batch) grid = batch;
     if ((e = fw::launch_build_jobs(n_dev, off_dev, batch, jobs, s)) != hipSuccess) return hip_fail(e, "job table build");
-    e = dt == FW_F32 ? fw::launch_batched<float>((float *)dist, path, jobs, small_max_n, grid, s)
-                     : fw::launch_batched<double>((double *)dist, path, jobs, small_max_n, grid, s);
+    e = dt == FW_F32 ? fw::launch_batched<float>((float *)dist, path, jobs, tiles, grid, s)
+                     : fw::launch_batched<double>((double *)dist, path, jobs, tiles, grid, s);
     if (e != hipSuccess) return hip_fail(e, "batched launch");
     return FW_OK;
 }

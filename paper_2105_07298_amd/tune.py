@@ -10,9 +10,13 @@ It times, with HIP events on the current stream,
     graphs with weights uniform in (0, 1), and for binary16 on complete graphs
     with integer weights in [1, 1000] (its exact range);
   * fw_apsp_batched on batches of equal-size graphs (weights in [1, 10],
-    density 0.5) in 32 x 32 tiles and in 64 x 64 tiles, for the sizes from 16
-    to 512 that both tilings pad alike; the split point small_max_n is the
-    largest such n below the first size at which 64 x 64 tiles are faster.
+    density 0.5) in 32 x 32 tiles and in 64 x 64 tiles, at the top size
+    n = 32 (c + 1) of every size class c (n in (32c, 32c + 32]) up to 768
+    vertices; a class takes 64 x 64 tiles when they were faster there (both
+    tilings pad every n of a class to the same size as its top one), and every
+    class above the timed range takes them (their padding costs at most
+    (1 + 32/768)^3 = 1.13 times the work there, against the 1.4 to 1.7 times
+    that 64 x 64 tiles gained at 384 to 512 vertices when this was written).
 and writes DIR/tune_table.json (every timing) and DIR/tune_table.inc (the
 table the library compiles; copy it to csrc/ and rebuild).  Tuning never changes
 results: the tests check that every configuration gives the same D and P.
@@ -27,7 +31,7 @@ import time
 
 # size ranges [lo, hi) of the table and the n timed for each
 BUCKETS = [(0, 512, 256), (512, 2048, 1024), (2048, 8192, 4096), (8192, 1 << 40, 16384)]
-BATCHED_N = [16, 24, 32, 48, 64, 80, 96, 128, 160, 192, 256, 320, 384, 512]
+BATCHED_CLASSES = 24  # size classes timed: n up to 32 * 24 = 768
 
 
 def _timeit(fn, torch, reps, warmup=1):
@@ -84,18 +88,18 @@ def tune_apsp(fw, torch, log, dtypes=("f32", "f64", "f16")):
 
 
 def tune_batched(fw, torch, log):
-    """small_max_n: the largest size, among those that 32- and 64-tiles pad alike
-    (the kernel takes 32-tiles for the others anyway), below the first one at
-    which 64-tiles are faster."""
+    """tile64: bit c set when 64 x 64 tiles solve graphs of size class c
+    (n in (32c, 32c + 32]) faster than 32 x 32 tiles; classes above the timed
+    range are set."""
     import numpy as np
     import workloads
     table = []
-    sizes = [n for n in BATCHED_N if ((n + 63) // 64) * 64 == ((n + 31) // 32) * 32]
     for dt in ("f32", "f64"):
         npdt = np.float32 if dt == "f32" else np.float64
         for path in (False, True):
-            small_max_n, done = 0, False
-            for n in sizes:
+            mask = ((1 << 64) - 1) & ~((1 << BATCHED_CLASSES) - 1)
+            for c in range(BATCHED_CLASSES):
+                n = 32 * (c + 1)
                 count = int(max(64, min(4096, 2.0e9 / n ** 3 * 64)))
                 g = workloads.graph(11, n, 0.5, workloads.W_ONE_TEN, 0, npdt)
                 W = torch.from_numpy(np.tile(g.ravel(), count)).cuda()
@@ -113,13 +117,11 @@ def tune_batched(fw, torch, log):
                                 "count": count, "ms": round(res[label], 4)})
                 print(f"batched {dt} path={path} n={n} x{count}: 32-tiles {res[32]:.3f} ms, "
                       f"64-tiles {res[64]:.3f} ms", flush=True)
-                if not done and res[32] <= res[64]:
-                    small_max_n = n
-                else:
-                    done = True
+                if res[64] < res[32]:
+                    mask |= 1 << c
                 del W, D, P
             table.append({"dtype": fw.FW_F64 if dt == "f64" else fw.FW_F32, "path": path,
-                          "small_max_n": small_max_n})
+                          "tile64": f"0x{mask:016X}"})
     return table
 
 
@@ -128,7 +130,8 @@ def write_inc(path, apsp_table, batched_table, arch):
         "// Tile configuration table.  Generated by paper_2105_07298_amd/tune.py from",
         f"// timings on {arch} (do not edit by hand; rerun the tuner instead).",
         "// fw_apsp:          {dtype, path, n_lo, n_hi, block, tile_m, tile_n, variant, schedule}  n_lo <= n < n_hi",
-        "// fw_apsp_batched:  {dtype, path, small_max_n}      dtype: 0 float32, 1 float64, 2 binary16",
+        "// fw_apsp_batched:  {dtype, path, tile64}  bit c of tile64: 64 x 64 tiles for n in (32c, 32c + 32]",
+        "//                   dtype: 0 float32, 1 float64, 2 binary16",
         f"// generated {time.strftime('%Y-%m-%d')}",
         "static const TuneEntry kTuneApsp[] = {",
     ]
@@ -139,7 +142,7 @@ def write_inc(path, apsp_table, batched_table, arch):
     lines.append("};")
     lines.append("static const TuneBatchedEntry kTuneBatched[] = {")
     for t in batched_table:
-        lines.append(f"    {{{int(t['dtype'])}, {int(t['path'])}, {t['small_max_n']}}},")
+        lines.append(f"    {{{int(t['dtype'])}, {int(t['path'])}, {t['tile64']}ull}},")
     lines.append("};")
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")

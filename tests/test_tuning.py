@@ -16,7 +16,8 @@ def entries():
         f = [x.strip() for x in m.group(1).split(",")]
         hi = (1 << 40) if "<<" in f[3] else int(f[3])
         rows.append((int(f[0]), int(f[1]), int(f[2]), hi, int(f[4]), int(f[5]), int(f[6]), int(f[7]), int(f[8])))
-    brows = [tuple(int(x) for x in m.group(1).split(",")) for m in re.finditer(r"\{([^{}]*)\}", batched)]
+    brows = [tuple(int(x.strip().rstrip("ul"), 0) for x in m.group(1).split(","))
+             for m in re.finditer(r"\{([^{}]*)\}", batched)]
     return rows, brows
 
 
@@ -43,4 +44,7 @@ def test_batched_table_complete():
     _, brows = entries()
     keys = {(b[0], b[1]) for b in brows}
     assert keys == {(0, 0), (0, 1), (1, 0), (1, 1)}
-    assert all(0 <= b[2] <= 4096 for b in brows)
+    # tile64 masks: 64 x 64 tiles never for n <= 32 (they would pad it to 64),
+    # always above the 768 vertices the tuner times
+    assert all(0 <= b[2] < (1 << 64) and not (b[2] & 1) for b in brows)
+    assert all((b[2] >> 24) == (1 << 40) - 1 for b in brows)
