@@ -211,6 +211,53 @@ def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False, config=None,
     return sec, stats, per
 
 
+def time_large(fw, torch, dtype, runs, warmup, meter=None):
+    """The large single graph: n = 65536, edge probability 0.1, integer weights in
+    [1, 100], distances and path matrix.  Before every call the input is generated
+    on the device (the generator's device twin) straight into D, outside the
+    timing; each call is timed by events on the current stream, and the energy
+    counter is read around each timed call alone."""
+    import workloads
+    n = 65536
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    D = torch.empty((n, n), dtype=tdt, device="cuda")
+    P = torch.empty((n, n), dtype=torch.int32, device="cuda")
+    per, runs_e = [], []
+    for r in range(warmup + runs):
+        workloads.rows_dev(3, n, 0, n, 0.1, workloads.W_INT, 100, D)
+        torch.cuda.synchronize()
+        timed = r >= warmup
+        if timed and meter is not None:
+            meter.start()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fw.apsp_(D, P)
+        e1.record()
+        torch.cuda.synchronize()
+        if timed:
+            per.append(e0.elapsed_time(e1))
+            if meter is not None:
+                runs_e.append(meter.stop(1, 2.0 * n ** 3))
+    del D, P
+    torch.cuda.empty_cache()
+    sec = sum(per) / len(per) / 1e3
+    out = {"n": n, "dtype": dtype, "path": True, "gflops": round(gflops(n, sec), 2),
+           "ms_per_call": round(sec * 1e3, 1), "timing": run_stats(per),
+           "workload": "edge probability 0.1, integer weights in [1, 100], missing edges +inf",
+           "note": f"{warmup} untimed call(s) first; input regenerated on the device before every call, "
+                   "outside the timing"}
+    if meter is not None:
+        js = [e["joules_per_step"] for e in runs_e if e.get("joules_per_step")]
+        if len(js) == len(runs_e) and js:
+            j = sum(js) / len(js)
+            out["energy"] = {"joules_per_call": round(j, 1), "avg_power_w": round(j / sec, 1),
+                             "gflops_per_w": round(2.0 * n ** 3 / j / 1e9, 2), "dtype": dtype,
+                             "source": "amdsmi energy accumulator around each timed call"}
+        else:
+            out["energy"] = dict(runs_e[-1] if runs_e else {}, dtype=dtype)
+    return out
+
+
 def time_batched(fw, torch, steps=15, warmup=2):
     """The batched workload: 10,000 graphs, n uniform in [16, 512], density uniform in
     [0.1, 1.0), float32 weights in [1, 10], path matrices, one persistent launch."""
@@ -504,6 +551,7 @@ def main():
     ap.add_argument("--no-energy", action="store_true", help="skip the amdsmi energy reading")
     ap.add_argument("--config", default="", help="block,tile_m,tile_n,variant,schedule instead of the tuned choice")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the n = 65536 secondary figures")
     ap.add_argument("--batched-only", action="store_true",
                     help="time only the batched workload (10,000 graphs) and print its line")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -596,6 +644,11 @@ def main():
                 sec_out[f"{dt_}_path_n{n2}"] = {"gflops": round(gflops(n2, s), 2), "ms_per_step": round(s * 1e3, 3),
                                                 "timing": run_stats(p2),
                                                 "roofline_frac": roofline(n2, dt_, st, True)["frac"]}
+        if not args.no_large:
+            meter_l = None if args.no_energy else EnergyMeter(torch)
+            for dt_, runs, wu in (("f32", 2, 1), ("f64", 2, 0)):
+                print(f"[bench] secondary n=65536 {dt_} path=True", file=sys.stderr, flush=True)
+                sec_out[f"large_{dt_}_path_n65536"] = time_large(fw, torch, dt_, runs, wu, meter_l)
         print("[bench] secondary out of core n=32768", file=sys.stderr, flush=True)
         sec_out["ooc_f32_dist"] = time_ooc(fw, torch, runs=K)
         print("[bench] secondary out of core n=16384 with the path matrix", file=sys.stderr, flush=True)

@@ -98,79 +98,119 @@ __global__ void __launch_bounds__(NT) k_minplus(T *__restrict__ C, int64_t ldc, 
 // Lexicographic form of the general update, for the out-of-core driver with
 // path labels: (C, PC) <- lexmin over k of (A[i][k] + B[k][j],
 // max(PA[i][k], kbase + k, PB[k][j])) and the old (C, PC) -- the rule phases 1-3
-// apply, with kbase the global index of A's first column.  64 x 64 tiles, 16 x 16
-// threads with 4 x 4 entries each (rows ty + 16 ii, columns tx + 16 jj), panel
-// chunks of KT values of k with their labels in LDS.
+// apply, with kbase the global index of A's first column.  The tiles of
+// k_minplus with the labels beside the lengths: 64 x 64 entries, each thread
+// rows ty + 16 ii and a group of V adjacent columns (V = 16 bytes of lengths),
+// panel chunks of KT values of k staged in LDS with their labels + 1, and
+// every LDS read a 16-byte (lengths) or V-label vector: for float32 one read
+// per 4 updates.  The update itself is lex_take_u (one double minimum on the
+// packed key for float32).  Written back: the vectors in which an entry changed.
 template <typename T, int KT>
 __global__ void __launch_bounds__(NT) k_minplus_lex(T *__restrict__ C, int32_t *__restrict__ PC, int64_t ldc,
                                                    const T *__restrict__ A, const int32_t *__restrict__ PA, int64_t lda,
                                                    const T *__restrict__ B, const int32_t *__restrict__ PB, int64_t ldb,
                                                    int64_t K, int32_t kbase, TileSel sel) {
-    constexpr int TS = 16, RM = 4, BM = 64, BN = 64, STA = KT + 1, STB = BN + 1;
-    __shared__ T sa[BM * STA];
-    __shared__ uint32_t spa[BM * STA];  // labels + 1, as in phases 1-3
-    __shared__ T sb[KT * STB];
-    __shared__ uint32_t spb[KT * STB];
+    constexpr int BM = 64, BN = 64;
+    using vec = typename V16<T>::type;
+    constexpr int V = V16<T>::n;
+    typedef uint32_t lvec __attribute__((ext_vector_type(V)));  // V labels + 1
+    constexpr int TX = BN / V, TY = NT / TX, RI = BM / TY;
+    static_assert(RI * TY == BM && TX * V == BN, "tile shape");
+    constexpr int AST = KT + V;  // row stride of the A chunk (16-byte rows, shifted banks)
+    __shared__ __attribute__((aligned(16))) T As[BM * AST];
+    __shared__ __attribute__((aligned(16))) uint32_t Al[BM * AST];
+    __shared__ __attribute__((aligned(16))) T Bs[KT * BN];
+    __shared__ __attribute__((aligned(16))) uint32_t Bl[KT * BN];
+
     int bi, bj;
     if (!select_tile<false>(sel, blockIdx.x, bi, bj)) return;
     const int64_t I0 = (int64_t)bi * BM, J0 = (int64_t)bj * BN;
-    const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
-    T d[RM][RM], d0[RM][RM];
-    uint32_t p[RM][RM], p0[RM][RM];
+    const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
+
+    T d[RI][V];
+    uint32_t p[RI][V];
 #pragma unroll
-    for (int ii = 0; ii < RM; ++ii)
+    for (int ii = 0; ii < RI; ++ii) {
+        const int64_t g = (I0 + ty + TY * ii) * ldc + J0 + tx * V;
+        const vec c = *(const vec *)(C + g);
+        const lvec l = *(const lvec *)(PC + g);
 #pragma unroll
-        for (int jj = 0; jj < RM; ++jj) {
-            const int64_t g = (I0 + ty + TS * ii) * ldc + J0 + tx + TS * jj;
-            d[ii][jj] = d0[ii][jj] = canon(C[g]);
-            p[ii][jj] = p0[ii][jj] = (uint32_t)(PC[g] + 1);
+        for (int e = 0; e < V; ++e) {
+            d[ii][e] = canon(c[e]);
+            p[ii][e] = l[e] + 1u;
         }
+    }
+
     for (int64_t k0 = 0; k0 < K; k0 += KT) {
         __syncthreads();  // the previous chunk is consumed
-        for (int q = threadIdx.x; q < BM * KT; q += NT) {
-            const int row = q / KT, kk = q % KT;
-            const int64_t g = (I0 + row) * lda + k0 + kk;
-            sa[row * STA + kk] = canon(A[g]);
-            spa[row * STA + kk] = (uint32_t)(PA[g] + 1);
+        for (int q = tid; q < BM * (KT / V); q += NT) {
+            const int row = q / (KT / V), kv = q % (KT / V);
+            const int64_t g = (I0 + row) * lda + k0 + kv * V;
+            vec a = *(const vec *)(A + g);
+            lvec l = *(const lvec *)(PA + g);
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                a[e] = canon(a[e]);
+                l[e] += 1u;
+            }
+            *(vec *)(As + row * AST + kv * V) = a;
+            *(lvec *)(Al + row * AST + kv * V) = l;
         }
-        for (int q = threadIdx.x; q < KT * BN; q += NT) {
-            const int kr = q / BN, c = q % BN;
-            const int64_t g = (k0 + kr) * ldb + J0 + c;
-            sb[kr * STB + c] = canon(B[g]);
-            spb[kr * STB + c] = (uint32_t)(PB[g] + 1);
+        for (int q = tid; q < KT * (BN / V); q += NT) {
+            const int krow = q / (BN / V), cv = q % (BN / V);
+            const int64_t g = (k0 + krow) * ldb + J0 + cv * V;
+            vec b = *(const vec *)(B + g);
+            lvec l = *(const lvec *)(PB + g);
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                b[e] = canon(b[e]);
+                l[e] += 1u;
+            }
+            *(vec *)(Bs + krow * BN + cv * V) = b;
+            *(lvec *)(Bl + krow * BN + cv * V) = l;
         }
         __syncthreads();
-        for (int kk = 0; kk < KT; ++kk) {
-            T a[RM], b[RM];
-            uint32_t pa[RM], pb[RM];
+        for (int kv = 0; kv < KT / V; ++kv) {
+            vec a[RI];
+            lvec la[RI];
 #pragma unroll
-            for (int ii = 0; ii < RM; ++ii) {
-                a[ii] = sa[(ty + TS * ii) * STA + kk];
-                pa[ii] = spa[(ty + TS * ii) * STA + kk];
+            for (int ii = 0; ii < RI; ++ii) {
+                a[ii] = *(const vec *)(As + (ty + TY * ii) * AST + kv * V);
+                la[ii] = *(const lvec *)(Al + (ty + TY * ii) * AST + kv * V);
             }
 #pragma unroll
-            for (int jj = 0; jj < RM; ++jj) {
-                b[jj] = sb[kk * STB + tx + TS * jj];
-                pb[jj] = spb[kk * STB + tx + TS * jj];
-            }
-            const uint32_t kg1 = (uint32_t)(kbase + k0 + kk + 1);
+            for (int kk = 0; kk < V; ++kk) {
+                const int k = kv * V + kk;
+                const vec b = *(const vec *)(Bs + k * BN + tx * V);
+                const lvec lb = *(const lvec *)(Bl + k * BN + tx * V);
+                const uint32_t kg1 = (uint32_t)(kbase + k0 + k + 1);
 #pragma unroll
-            for (int ii = 0; ii < RM; ++ii) {
-                const uint32_t mi = max(pa[ii], kg1);
+                for (int ii = 0; ii < RI; ++ii)
 #pragma unroll
-                for (int jj = 0; jj < RM; ++jj) lex_take_u(d[ii][jj], p[ii][jj], a[ii] + b[jj], max(mi, pb[jj]));
+                    for (int e = 0; e < V; ++e)
+                        lex_take_u(d[ii][e], p[ii][e], a[ii][kk] + b[e], max(max(la[ii][kk], lb[e]), kg1));
             }
         }
     }
 #pragma unroll
-    for (int ii = 0; ii < RM; ++ii)
+    for (int ii = 0; ii < RI; ++ii) {
+        const int64_t g = (I0 + ty + TY * ii) * ldc + J0 + tx * V;
+        const vec c = *(const vec *)(C + g);
+        const lvec l = *(const lvec *)(PC + g);
+        vec nc;
+        lvec nl;
+        bool ch = false;
 #pragma unroll
-        for (int jj = 0; jj < RM; ++jj) {
-            if (d[ii][jj] == d0[ii][jj] && p[ii][jj] == p0[ii][jj]) continue;
-            const int64_t g = (I0 + ty + TS * ii) * ldc + J0 + tx + TS * jj;
-            C[g] = d[ii][jj];
-            PC[g] = (int32_t)p[ii][jj] - 1;
+        for (int e = 0; e < V; ++e) {
+            nc[e] = d[ii][e];
+            nl[e] = p[ii][e] - 1u;
+            ch |= !(d[ii][e] == c[e]) || nl[e] != l[e];
         }
+        if (ch) {
+            *(vec *)(C + g) = nc;
+            *(lvec *)(PC + g) = nl;
+        }
+    }
 }
 
 // Labels of a block closed in isolation (local vertex indices, -1 where the
