@@ -25,6 +25,7 @@
 
 #include <algorithm>
 #include <thread>
+#include <utility>
 #include <vector>
 
 #include "../../include/fw_apsp.h"
@@ -43,9 +44,10 @@ namespace {
 struct Streams {
     hipStream_t cs = nullptr, h2d = nullptr, d2h = nullptr;
     hipEvent_t loaded[2] = {nullptr, nullptr}, computed[2] = {nullptr, nullptr}, stored[2] = {nullptr, nullptr};
-    hipEvent_t start = nullptr;
+    hipEvent_t start = nullptr, bands = nullptr, rows_done = nullptr, cols_done = nullptr;
     ~Streams() {
-        for (hipEvent_t e : {loaded[0], loaded[1], computed[0], computed[1], stored[0], stored[1], start})
+        for (hipEvent_t e : {loaded[0], loaded[1], computed[0], computed[1], stored[0], stored[1], start, bands,
+                             rows_done, cols_done})
             if (e) (void)hipEventDestroy(e);
         for (hipStream_t s : {cs, h2d, d2h})
             if (s) (void)hipStreamDestroy(s);
@@ -54,7 +56,8 @@ struct Streams {
         hipError_t e;
         for (hipStream_t *s : {&cs, &h2d, &d2h})
             if ((e = hipStreamCreateWithFlags(s, hipStreamNonBlocking)) != hipSuccess) return e;
-        for (hipEvent_t *ev : {&loaded[0], &loaded[1], &computed[0], &computed[1], &stored[0], &stored[1], &start})
+        for (hipEvent_t *ev : {&loaded[0], &loaded[1], &computed[0], &computed[1], &stored[0], &stored[1], &start,
+                               &bands, &rows_done, &cols_done})
             if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess) return e;
         return hipSuccess;
     }
@@ -119,8 +122,52 @@ hipError_t run_ooc(int64_t n, T *H, int32_t *HP, int64_t S, hipStream_t user, co
     auto edge = [&](int64_t b) { return std::min(S, n - b * S); };
     const hipMemcpyKind H2D = hipMemcpyHostToDevice, D2H = hipMemcpyDeviceToHost, D2D = hipMemcpyDeviceToDevice;
     const fw_dtype_t dt = sizeof(T) == 4 ? FW_F32 : FW_F64;
+    // A band's copy between host and device, without the diagonal super-block's
+    // part (columns [K0, K0 + SK) of the row band, rows of the column band): that
+    // part of a band buffer is never read, and leaving it out keeps the band's
+    // transfers apart from the diagonal block's, so they can run on other streams
+    // while the block is closed.
+    auto row_band_copy = [&](void *dev, int64_t ldd, void *host, size_t e, int64_t K0, int64_t SK,
+                             hipMemcpyKind kind, hipStream_t s) -> hipError_t {
+        for (auto [c0, c1] : {std::pair<int64_t, int64_t>{0, K0}, {K0 + SK, n}}) {
+            if (c1 <= c0) continue;
+            char *d = (char *)dev + c0 * e, *h = (char *)host + (K0 * n + c0) * e;
+            hipError_t err = kind == hipMemcpyHostToDevice
+                                 ? hipMemcpy2DAsync(d, ldd * e, h, n * e, (c1 - c0) * e, SK, kind, s)
+                                 : hipMemcpy2DAsync(h, n * e, d, ldd * e, (c1 - c0) * e, SK, kind, s);
+            if (err != hipSuccess) return err;
+        }
+        return hipSuccess;
+    };
+    auto col_band_copy = [&](void *dev, void *host, size_t e, int64_t K0, int64_t SK, hipMemcpyKind kind,
+                             hipStream_t s) -> hipError_t {
+        for (auto [r0, r1] : {std::pair<int64_t, int64_t>{0, K0}, {K0 + SK, n}}) {
+            if (r1 <= r0) continue;
+            char *d = (char *)dev + r0 * S * e, *h = (char *)host + (r0 * n + K0) * e;
+            hipError_t err = kind == hipMemcpyHostToDevice
+                                 ? hipMemcpy2DAsync(d, S * e, h, n * e, SK * e, r1 - r0, kind, s)
+                                 : hipMemcpy2DAsync(h, n * e, d, S * e, SK * e, r1 - r0, kind, s);
+            if (err != hipSuccess) return err;
+        }
+        return hipSuccess;
+    };
     for (int64_t R = 0; R < NS; ++R) {
         const int64_t K0 = R * S, SK = edge(R);
+        // 0. the two bands go up on the upload stream while the diagonal block is
+        // closed (padding rows and columns: +inf, label -1)
+        if (NS > 1) {
+            FW_TRY(launch_fill_blank<T>(RB, NP, S, NP, false, st.h2d));
+            FW_TRY(launch_fill_blank<T>(CB, S, NP, S, false, st.h2d));
+            FW_TRY(row_band_copy(RB, NP, H, es, K0, SK, H2D, st.h2d));
+            FW_TRY(col_band_copy(CB, H, es, K0, SK, H2D, st.h2d));
+            if (path) {
+                FW_TRY(launch_fill_i32(RBP, S * NP, -1, st.h2d));
+                FW_TRY(launch_fill_i32(CBP, NP * S, -1, st.h2d));
+                FW_TRY(row_band_copy(RBP, NP, HP, is, K0, SK, H2D, st.h2d));
+                FW_TRY(col_band_copy(CBP, HP, is, K0, SK, H2D, st.h2d));
+            }
+            FW_TRY(hipEventRecord(st.bands, st.h2d));
+        }
         // 1. diagonal super-block, closed in core
         FW_TRY(launch_fill_blank<T>(Dd, S, S, S, true, cs));  // padding vertices are isolated
         FW_TRY(hipMemcpy2DAsync(Dd, S * es, H + K0 * n + K0, n * es, SK * es, SK, H2D, cs));
@@ -138,13 +185,8 @@ hipError_t run_ooc(int64_t n, T *H, int32_t *HP, int64_t S, hipStream_t user, co
             FW_TRY(hipMemcpy2DAsync(HP + K0 * n + K0, n * is, Pd, S * is, SK * is, SK, D2H, cs));
         }
         if (NS == 1) break;
-        // 2. row band
-        FW_TRY(launch_fill_blank<T>(RB, NP, S, NP, false, cs));  // padding rows and columns: +inf
-        FW_TRY(hipMemcpy2DAsync(RB, NP * es, H + K0 * n, n * es, n * es, SK, H2D, cs));
-        if (path) {
-            FW_TRY(launch_fill_i32(RBP, S * NP, -1, cs));
-            FW_TRY(hipMemcpy2DAsync(RBP, NP * is, HP + K0 * n, n * is, n * is, SK, H2D, cs));
-        }
+        FW_TRY(hipStreamWaitEvent(cs, st.bands, 0));
+        // 2. row band; its download overlaps the column band's products
         for (int64_t J = 0; J < NS; ++J) {
             if (J == R) continue;
             FW_TRY(hipMemcpy2DAsync(TMP, S * es, RB + J * S, NP * es, S * es, S, D2D, cs));
@@ -156,15 +198,11 @@ hipError_t run_ooc(int64_t n, T *H, int32_t *HP, int64_t S, hipStream_t user, co
                 FW_TRY(launch_minplus<T>(RB + J * S, NP, Dd, S, TMP, S, S, S, S, cs));
             }
         }
-        FW_TRY(hipMemcpy2DAsync(H + K0 * n, n * es, RB, NP * es, n * es, SK, D2H, cs));
-        if (path) FW_TRY(hipMemcpy2DAsync(HP + K0 * n, n * is, RBP, NP * is, n * is, SK, D2H, cs));
-        // 3. column band
-        FW_TRY(launch_fill_blank<T>(CB, S, NP, S, false, cs));
-        FW_TRY(hipMemcpy2DAsync(CB, S * es, H + K0, n * es, SK * es, n, H2D, cs));
-        if (path) {
-            FW_TRY(launch_fill_i32(CBP, NP * S, -1, cs));
-            FW_TRY(hipMemcpy2DAsync(CBP, S * is, HP + K0, n * is, SK * is, n, H2D, cs));
-        }
+        FW_TRY(hipEventRecord(st.rows_done, cs));
+        FW_TRY(hipStreamWaitEvent(st.d2h, st.rows_done, 0));
+        FW_TRY(row_band_copy(RB, NP, H, es, K0, SK, D2H, st.d2h));
+        if (path) FW_TRY(row_band_copy(RBP, NP, HP, is, K0, SK, D2H, st.d2h));
+        // 3. column band; its download overlaps the other super-tiles' products
         for (int64_t I = 0; I < NS; ++I) {
             if (I == R) continue;
             FW_TRY(hipMemcpyAsync(TMP, CB + I * S * S, (size_t)(S * S) * es, D2D, cs));
@@ -176,11 +214,14 @@ hipError_t run_ooc(int64_t n, T *H, int32_t *HP, int64_t S, hipStream_t user, co
                 FW_TRY(launch_minplus<T>(CB + I * S * S, S, TMP, S, Dd, S, S, S, S, cs));
             }
         }
-        FW_TRY(hipMemcpy2DAsync(H + K0, n * es, CB, S * es, SK * es, n, D2H, cs));
-        if (path) FW_TRY(hipMemcpy2DAsync(HP + K0, n * is, CBP, S * is, SK * is, n, D2H, cs));
+        FW_TRY(hipEventRecord(st.cols_done, cs));
+        FW_TRY(hipStreamWaitEvent(st.d2h, st.cols_done, 0));
+        FW_TRY(col_band_copy(CB, H, es, K0, SK, D2H, st.d2h));
+        if (path) FW_TRY(col_band_copy(CBP, HP, is, K0, SK, D2H, st.d2h));
         // 4. the other super-tiles: upload (h2d) -> product (cs) -> download (d2h).
-        // Uploads may start during steps 1-3: those tiles are disjoint from
-        // the blocks and bands written back there.
+        // Uploads may start during steps 1-3 (after the bands' on the same
+        // stream): those tiles are disjoint from the blocks and bands written
+        // back there.
         int64_t t = 0;
         for (int64_t I = 0; I < NS; ++I) {
             if (I == R) continue;
