@@ -30,7 +30,8 @@ import sys
 import time
 
 # size ranges [lo, hi) of the table and the n timed for each
-BUCKETS = [(0, 512, 256), (512, 2048, 1024), (2048, 8192, 4096), (8192, 1 << 40, 16384)]
+BUCKETS = [(0, 384, 256), (384, 768, 512), (768, 1536, 1024), (1536, 3072, 2048), (3072, 6144, 4096),
+           (6144, 12288, 8192), (12288, 1 << 40, 16384)]
 BATCHED_CLASSES = 24  # size classes timed: n up to 32 * 24 = 768
 
 
