@@ -324,9 +324,12 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
     // Stage columns kb + kc .. kb + kc + KC - 1 of the column panel D[I, K] and
     // the same rows of the row panel D[K, J], for the block that starts at kb;
     // the block's own rows / columns are masked in a tile wider than the block.
+    // A tile no wider than the block never needs it (every selection then skips
+    // the block's tile rows and columns: nsr, nsc >= 1), and the test is left
+    // out of the code.
     auto stage = [&](int64_t kb, int kc) {
-        const bool mask_rows = sel.nsr == 0 && (I0 <= kb) && (kb < I0 + BM);
-        const bool mask_cols = sel.nsc == 0 && (J0 <= kb) && (kb < J0 + BN);
+        const bool mask_rows = BM > TB && sel.nsr == 0 && (I0 <= kb) && (kb < I0 + BM);
+        const bool mask_cols = BN > TB && sel.nsc == 0 && (J0 <= kb) && (kb < J0 + BN);
         const vec vinf = inf_v<T>();
         for (int q = tid; q < BM * (KC / V); q += NT) {
             const int row = q / (KC / V), kv = q % (KC / V);
