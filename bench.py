@@ -289,7 +289,7 @@ def time_ooc(fw, torch, n=32768, S=8192, path=False, runs=15):
     import numpy as np
     import workloads
     nb = -(-n // S)
-    blocks = 4 * S * S + 2 * S * nb * S
+    blocks = 4 * S * S + 4 * S * nb * S
     budget = blocks * 4 + ((blocks + S * S) * 4 if path else 0)
     assert fw.fw_ooc_superblock(fw.FW_F32, n, path, budget) == S
     H = torch.empty((n, n), dtype=torch.float32, pin_memory=True)

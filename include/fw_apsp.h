@@ -155,8 +155,8 @@ fw_status_t fw_query_config(fw_dtype_t dt, int64_t n, int32_t path, fw_config_t 
  * lets the transfers overlap the computation.  The blocked method runs over
  * super-blocks of edge S (fw_ooc_superblock): each super-round closes its
  * diagonal super-block in device memory with fw_apsp, updates its row and
- * column bands, and streams every other S x S super-tile through the device
- * once.  P follows the same lexicographic rule as fw_apsp, so both give the
+ * column bands, updates the next super-round's bands in place on the device,
+ * and streams every other S x S super-tile through the device once.  P follows the same lexicographic rule as fw_apsp, so both give the
  * same P for the same D.  device_bytes bounds the device working set (0: 90%
  * of the free memory).  Ordered after earlier work on `stream`; returns when
  * the host arrays hold the result.  FW_ENOMEM if device_bytes cannot hold even
@@ -166,8 +166,9 @@ fw_status_t fw_apsp_ooc(fw_dtype_t dt, int64_t n, void *dist_host, int32_t *path
                         void *stream);
 
 /* The super-block edge fw_apsp_ooc uses for (dt, n, path != 0, device_bytes):
- * the largest multiple of 256 whose working set fits -- 4*S^2 + 2*S*ceil(n/S)*S
- * elements, plus as many int32 labels and S^2 more with the path matrix -- or
+ * the largest multiple of 256 whose working set fits -- 4*S^2 + 4*S*ceil(n/S)*S
+ * elements (four blocks and two sets of row and column bands), plus as many
+ * int32 labels and S^2 more with the path matrix -- or
  * a negative status.  Host only. */
 int64_t fw_ooc_superblock(fw_dtype_t dt, int64_t n, int32_t path, size_t device_bytes);
 

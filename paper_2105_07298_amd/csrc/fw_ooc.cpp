@@ -7,10 +7,13 @@
 //      super-column J (one min-plus product each, as phases 2 of the blocked
 //      method with the closed diagonal block);
 //   3. the column band D[:,K] likewise, min(D[I,K], D_old[I,K] (x) D*[K,K]);
-//   4. every other super-tile streams through the device once:
-//      D[I,J] <- min(D[I,J], D[I,K] (x) D[K,J]), with its upload, product and
-//      download on three streams and two device buffers, so that transfers in
-//      both directions overlap the products.
+//   4. every other super-tile is updated, D[I,J] <- min(D[I,J], D[I,K] (x) D[K,J]):
+//      first super-row and super-column R + 1, straight into a second set of
+//      band buffers where super-round R + 1 finds its bands (and its diagonal
+//      block) without a round trip through host memory; then the rest, each
+//      streamed through the device once, with its upload, product and download
+//      on three streams and two device buffers, so that transfers in both
+//      directions overlap the products.
 // With the path matrix, every block carries its labels and the products apply
 // the lexicographic rule (length, largest interior vertex) of phases 1-3 with
 // global vertex indices.  The diagonal closure runs on the block alone, whose
@@ -35,7 +38,9 @@ namespace fw {
 
 size_t ooc_working_bytes(int64_t n, int64_t S, size_t es, bool path) {
     const int64_t NS = (n + S - 1) / S, NP = NS * S;
-    const size_t blocks = (size_t)(4 * S * S + 2 * S * NP);  // diagonal, temp, 2 tile buffers; row and column bands
+    // diagonal, temp, 2 tile buffers; two sets of row and column bands (this
+    // super-round's and the next one's)
+    const size_t blocks = (size_t)(4 * S * S + 4 * S * NP);
     return blocks * es + (path ? blocks * sizeof(int32_t) + (size_t)(S * S) * sizeof(int32_t) : 0);
 }
 
@@ -44,10 +49,10 @@ namespace {
 struct Streams {
     hipStream_t cs = nullptr, h2d = nullptr, d2h = nullptr;
     hipEvent_t loaded[2] = {nullptr, nullptr}, computed[2] = {nullptr, nullptr}, stored[2] = {nullptr, nullptr};
-    hipEvent_t start = nullptr, bands = nullptr, rows_done = nullptr, cols_done = nullptr;
+    hipEvent_t start = nullptr, bands = nullptr, rows_done = nullptr, cols_done = nullptr, ahead = nullptr;
     ~Streams() {
         for (hipEvent_t e : {loaded[0], loaded[1], computed[0], computed[1], stored[0], stored[1], start, bands,
-                             rows_done, cols_done})
+                             rows_done, cols_done, ahead})
             if (e) (void)hipEventDestroy(e);
         for (hipStream_t s : {cs, h2d, d2h})
             if (s) (void)hipStreamDestroy(s);
@@ -57,7 +62,7 @@ struct Streams {
         for (hipStream_t *s : {&cs, &h2d, &d2h})
             if ((e = hipStreamCreateWithFlags(s, hipStreamNonBlocking)) != hipSuccess) return e;
         for (hipEvent_t *ev : {&loaded[0], &loaded[1], &computed[0], &computed[1], &stored[0], &stored[1], &start,
-                               &bands, &rows_done, &cols_done})
+                               &bands, &rows_done, &cols_done, &ahead})
             if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess) return e;
         return hipSuccess;
     }
@@ -91,13 +96,24 @@ hipError_t run_ooc(int64_t n, T *H, int32_t *HP, int64_t S, hipStream_t user, co
     DeviceBuffer buf;
     FW_TRY(hipMalloc(&buf.p, ooc_working_bytes(n, S, es, path)));
     T *Dd = (T *)buf.p, *TMP = Dd + S * S, *Cb[2] = {TMP + S * S, TMP + 2 * S * S};
-    T *RB = Cb[1] + S * S;  // S x NP, leading dimension NP
-    T *CB = RB + S * NP;    // NP x S, leading dimension S
+    // Band sets: RBs[b] is S x NP (leading dimension NP), CBs[b] NP x S (leading
+    // dimension S); super-round R reads set R % 2 and fills set (R + 1) % 2.
+    T *RBs[2], *CBs[2];
+    RBs[0] = Cb[1] + S * S;
+    CBs[0] = RBs[0] + S * NP;
+    RBs[1] = CBs[0] + NP * S;
+    CBs[1] = RBs[1] + S * NP;
     // Labels, same shapes (path mode), plus the diagonal block's local labels.
-    int32_t *Pd = path ? (int32_t *)(CB + NP * S) : nullptr, *TMPP = path ? Pd + S * S : nullptr;
+    int32_t *Pd = path ? (int32_t *)(CBs[1] + NP * S) : nullptr, *TMPP = path ? Pd + S * S : nullptr;
     int32_t *CbP[2] = {path ? TMPP + S * S : nullptr, path ? TMPP + 2 * S * S : nullptr};
-    int32_t *RBP = path ? CbP[1] + S * S : nullptr, *CBP = path ? RBP + S * NP : nullptr;
-    int32_t *Ploc = path ? CBP + NP * S : nullptr;
+    int32_t *RBPs[2] = {nullptr, nullptr}, *CBPs[2] = {nullptr, nullptr};
+    if (path) {
+        RBPs[0] = CbP[1] + S * S;
+        CBPs[0] = RBPs[0] + S * NP;
+        RBPs[1] = CBPs[0] + NP * S;
+        CBPs[1] = RBPs[1] + S * NP;
+    }
+    int32_t *Ploc = path ? CBPs[1] + NP * S : nullptr;
     const hipStream_t cs = st.cs;
     if (path) {  // P starts as "no interior vertex"
         const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
@@ -110,12 +126,17 @@ hipError_t run_ooc(int64_t n, T *H, int32_t *HP, int64_t S, hipStream_t user, co
     // Order after the caller's earlier work on its stream.
     FW_TRY(hipEventRecord(st.start, user));
     FW_TRY(hipStreamWaitEvent(cs, st.start, 0));
-    // Tile buffers start blank; uploads into them wait for that.
+    // Tile buffers and the first band set start blank (padding rows and columns:
+    // +inf, label -1); uploads into them wait for that.
     FW_TRY(launch_fill_blank<T>(Cb[0], S, S, S, false, cs));
     FW_TRY(launch_fill_blank<T>(Cb[1], S, S, S, false, cs));
+    FW_TRY(launch_fill_blank<T>(RBs[0], NP, S, NP, false, cs));
+    FW_TRY(launch_fill_blank<T>(CBs[0], S, NP, S, false, cs));
     if (path) {
         FW_TRY(launch_fill_i32(CbP[0], S * S, -1, cs));
         FW_TRY(launch_fill_i32(CbP[1], S * S, -1, cs));
+        FW_TRY(launch_fill_i32(RBPs[0], S * NP, -1, cs));
+        FW_TRY(launch_fill_i32(CBPs[0], NP * S, -1, cs));
     }
     FW_TRY(hipEventRecord(st.start, cs));
     FW_TRY(hipStreamWaitEvent(st.h2d, st.start, 0));
@@ -153,27 +174,43 @@ hipError_t run_ooc(int64_t n, T *H, int32_t *HP, int64_t S, hipStream_t user, co
     };
     for (int64_t R = 0; R < NS; ++R) {
         const int64_t K0 = R * S, SK = edge(R);
-        // 0. the two bands go up on the upload stream while the diagonal block is
-        // closed (padding rows and columns: +inf, label -1)
-        if (NS > 1) {
-            FW_TRY(launch_fill_blank<T>(RB, NP, S, NP, false, st.h2d));
-            FW_TRY(launch_fill_blank<T>(CB, S, NP, S, false, st.h2d));
+        const int cur = (int)(R & 1), nxt = cur ^ 1;
+        T *RB = RBs[cur], *CB = CBs[cur];
+        int32_t *RBP = RBPs[cur], *CBP = CBPs[cur];
+        // 0. The bands.  Super-round 0 uploads them (on the upload stream, while
+        // the diagonal block is closed); a later one finds them in its band set,
+        // computed there by the previous super-round's first products, except the
+        // two tiles that were in that super-round's own bands: (R, R - 1) from its
+        // column band and (R - 1, R) from its row band.
+        if (NS > 1 && R == 0) {
             FW_TRY(row_band_copy(RB, NP, H, es, K0, SK, H2D, st.h2d));
             FW_TRY(col_band_copy(CB, H, es, K0, SK, H2D, st.h2d));
             if (path) {
-                FW_TRY(launch_fill_i32(RBP, S * NP, -1, st.h2d));
-                FW_TRY(launch_fill_i32(CBP, NP * S, -1, st.h2d));
                 FW_TRY(row_band_copy(RBP, NP, HP, is, K0, SK, H2D, st.h2d));
                 FW_TRY(col_band_copy(CBP, HP, is, K0, SK, H2D, st.h2d));
             }
             FW_TRY(hipEventRecord(st.bands, st.h2d));
+        } else if (R > 0) {
+            const int64_t Q = R - 1;
+            FW_TRY(hipMemcpy2DAsync(RB + Q * S, NP * es, CBs[nxt] + R * S * S, S * es, S * es, S, D2D, cs));
+            FW_TRY(hipMemcpy2DAsync(CB + Q * S * S, S * es, RBs[nxt] + R * S, NP * es, S * es, S, D2D, cs));
+            if (path) {
+                FW_TRY(hipMemcpy2DAsync(RBP + Q * S, NP * is, CBPs[nxt] + R * S * S, S * is, S * is, S, D2D, cs));
+                FW_TRY(hipMemcpy2DAsync(CBP + Q * S * S, S * is, RBPs[nxt] + R * S, NP * is, S * is, S, D2D, cs));
+            }
+            FW_TRY(hipEventRecord(st.bands, cs));  // the other set is free after these copies
         }
-        // 1. diagonal super-block, closed in core
+        // 1. diagonal super-block, closed in core: from the host in super-round 0,
+        // else from the row band (its tile (R, R), computed by the previous
+        // super-round)
         FW_TRY(launch_fill_blank<T>(Dd, S, S, S, true, cs));  // padding vertices are isolated
-        FW_TRY(hipMemcpy2DAsync(Dd, S * es, H + K0 * n + K0, n * es, SK * es, SK, H2D, cs));
-        if (path) {
-            FW_TRY(launch_fill_i32(Pd, S * S, -1, cs));
-            FW_TRY(hipMemcpy2DAsync(Pd, S * is, HP + K0 * n + K0, n * is, SK * is, SK, H2D, cs));
+        if (path) FW_TRY(launch_fill_i32(Pd, S * S, -1, cs));
+        if (R == 0) {
+            FW_TRY(hipMemcpy2DAsync(Dd, S * es, H + K0 * n + K0, n * es, SK * es, SK, H2D, cs));
+            if (path) FW_TRY(hipMemcpy2DAsync(Pd, S * is, HP + K0 * n + K0, n * is, SK * is, SK, H2D, cs));
+        } else {
+            FW_TRY(hipMemcpy2DAsync(Dd, S * es, RB + K0, NP * es, SK * es, SK, D2D, cs));
+            if (path) FW_TRY(hipMemcpy2DAsync(Pd, S * is, RBP + K0, NP * is, SK * is, SK, D2D, cs));
         }
         if (fw_apsp(dt, S, Dd, Ploc, cs) != FW_OK) {
             *what = "in-core closure of the diagonal super-block";
@@ -185,7 +222,7 @@ hipError_t run_ooc(int64_t n, T *H, int32_t *HP, int64_t S, hipStream_t user, co
             FW_TRY(hipMemcpy2DAsync(HP + K0 * n + K0, n * is, Pd, S * is, SK * is, SK, D2H, cs));
         }
         if (NS == 1) break;
-        FW_TRY(hipStreamWaitEvent(cs, st.bands, 0));
+        if (R == 0) FW_TRY(hipStreamWaitEvent(cs, st.bands, 0));
         // 2. row band; its download overlaps the column band's products
         for (int64_t J = 0; J < NS; ++J) {
             if (J == R) continue;
@@ -218,15 +255,70 @@ hipError_t run_ooc(int64_t n, T *H, int32_t *HP, int64_t S, hipStream_t user, co
         FW_TRY(hipStreamWaitEvent(st.d2h, st.cols_done, 0));
         FW_TRY(col_band_copy(CB, H, es, K0, SK, D2H, st.d2h));
         if (path) FW_TRY(col_band_copy(CBP, HP, is, K0, SK, D2H, st.d2h));
-        // 4. the other super-tiles: upload (h2d) -> product (cs) -> download (d2h).
-        // Uploads may start during steps 1-3 (after the bands' on the same
-        // stream): those tiles are disjoint from the blocks and bands written
-        // back there.
-        int64_t t = 0;
-        for (int64_t I = 0; I < NS; ++I) {
-            if (I == R) continue;
+        // 4a. Lookahead: super-row and super-column R + 1 of this super-round's
+        // update go straight into the next band set, where super-round R + 1
+        // reads them as its bands; they are neither downloaded now nor uploaded
+        // then (their host copies are stale until super-round R + 1 writes its
+        // bands back, and nothing reads them before).  The set is blanked first:
+        // its padding rows and columns must read +inf, and the set last held
+        // super-round R - 1's bands.
+        const int64_t L = R + 1;
+        const bool ahead = L < NS;
+        if (ahead) {
+            T *RN = RBs[nxt], *CN = CBs[nxt];
+            int32_t *RNP = RBPs[nxt], *CNP = CBPs[nxt];
+            FW_TRY(hipStreamWaitEvent(st.h2d, st.bands, 0));
+            FW_TRY(launch_fill_blank<T>(RN, NP, S, NP, false, st.h2d));
+            FW_TRY(launch_fill_blank<T>(CN, S, NP, S, false, st.h2d));
+            if (path) {
+                FW_TRY(launch_fill_i32(RNP, S * NP, -1, st.h2d));
+                FW_TRY(launch_fill_i32(CNP, NP * S, -1, st.h2d));
+            }
+            const int64_t SL = edge(L);
+            for (int64_t J = 0; J < NS; ++J) {  // tiles (L, J), the diagonal one included
+                if (J == R) continue;
+                FW_TRY(hipMemcpy2DAsync(RN + J * S, NP * es, H + L * S * n + J * S, n * es, edge(J) * es, SL, H2D,
+                                        st.h2d));
+                if (path)
+                    FW_TRY(hipMemcpy2DAsync(RNP + J * S, NP * is, HP + L * S * n + J * S, n * is, edge(J) * is, SL,
+                                            H2D, st.h2d));
+            }
+            for (int64_t I = 0; I < NS; ++I) {  // tiles (I, L)
+                if (I == R || I == L) continue;
+                FW_TRY(hipMemcpy2DAsync(CN + I * S * S, S * es, H + I * S * n + L * S, n * es, SL * es, edge(I), H2D,
+                                        st.h2d));
+                if (path)
+                    FW_TRY(hipMemcpy2DAsync(CNP + I * S * S, S * is, HP + I * S * n + L * S, n * is, SL * is, edge(I),
+                                            H2D, st.h2d));
+            }
+            FW_TRY(hipEventRecord(st.ahead, st.h2d));
+            FW_TRY(hipStreamWaitEvent(cs, st.ahead, 0));
             for (int64_t J = 0; J < NS; ++J) {
                 if (J == R) continue;
+                if (path)
+                    FW_TRY(launch_minplus_lex<T>(RN + J * S, RNP + J * S, NP, CB + L * S * S, CBP + L * S * S, S,
+                                                 RB + J * S, RBP + J * S, NP, S, S, S, (int32_t)K0, cs));
+                else
+                    FW_TRY(launch_minplus<T>(RN + J * S, NP, CB + L * S * S, S, RB + J * S, NP, S, S, S, cs));
+            }
+            for (int64_t I = 0; I < NS; ++I) {
+                if (I == R || I == L) continue;
+                if (path)
+                    FW_TRY(launch_minplus_lex<T>(CN + I * S * S, CNP + I * S * S, S, CB + I * S * S, CBP + I * S * S, S,
+                                                 RB + L * S, RBP + L * S, NP, S, S, S, (int32_t)K0, cs));
+                else
+                    FW_TRY(launch_minplus<T>(CN + I * S * S, S, CB + I * S * S, S, RB + L * S, NP, S, S, S, cs));
+            }
+        }
+        // 4b. the other super-tiles: upload (h2d) -> product (cs) -> download (d2h).
+        // Uploads may start during steps 1-3 (after the bands' and the lookahead
+        // tiles' on the same stream): those tiles are disjoint from the blocks and
+        // bands written back there.
+        int64_t t = 0;
+        for (int64_t I = 0; I < NS; ++I) {
+            if (I == R || (ahead && I == L)) continue;
+            for (int64_t J = 0; J < NS; ++J) {
+                if (J == R || (ahead && J == L)) continue;
                 const int b = (int)(t & 1);
                 const int64_t SI = edge(I), SJ = edge(J);
                 T *h = H + I * S * n + J * S;

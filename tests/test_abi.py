@@ -165,11 +165,11 @@ def test_backward_argument_errors_before_device(fw):
 
 def test_ooc_superblock_choice(fw):
     """The super-block edge is the largest multiple of 256 whose working set fits
-    the byte budget: 4 S^2 + 2 S ceil(n/S) S elements, and with the path matrix
+    the byte budget: 4 S^2 + 4 S ceil(n/S) S elements, and with the path matrix
     as many int32 labels plus S^2 more."""
     def need(n, S, es, path):
         nb = -(-n // S)
-        blocks = 4 * S * S + 2 * S * nb * S
+        blocks = 4 * S * S + 4 * S * nb * S
         return blocks * es + ((blocks + S * S) * 4 if path else 0)
     for dt, es in ((fw.FW_F32, 4), (fw.FW_F64, 8)):
         for path in (False, True):

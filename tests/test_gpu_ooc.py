@@ -20,7 +20,7 @@ def run_ooc(W, S_want, path):
     n = W.shape[0]
     es = W.itemsize
     nb = -(-n // S_want)
-    blocks = 4 * S_want * S_want + 2 * S_want * nb * S_want
+    blocks = 4 * S_want * S_want + 4 * S_want * nb * S_want
     budget = blocks * es + ((blocks + S_want * S_want) * 4 if path else 0)
     S = fw.fw_ooc_superblock(dt, n, path, budget)
     assert S == S_want, (S, S_want)
