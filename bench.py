@@ -169,10 +169,13 @@ def timed_steps(torch, step, steps, warmup):
     return ev[0].elapsed_time(ev[steps]) / 1e3, per
 
 
-def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False, config=None, energy=None):
+def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False, config=None, energy=None, prof_apart=False):
     """Mean seconds per fw_apsp step (D <- W, P <- -1, all rounds), the per-step
     times and last-phase stats.  config: (block, tile_m, tile_n, variant, schedule),
-    default the tuned choice."""
+    default the tuned choice.  The last-phase stats come from events around every
+    bulk launch of the timed steps; with prof_apart, from 3 more steps after them
+    instead, so that the timed steps carry no event records (a few microseconds per
+    launch, which matter at small n)."""
     import numpy as np
     import workloads
     block, tm, tn, var, sch = config or fw.fw_query_config(DT_CODE[dtype], n, path)
@@ -191,7 +194,7 @@ def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False, config=None,
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    if prof:
+    if prof and not prof_apart:
         fw.fw_prof_read(reset=True)
         fw.fw_prof_enable(True)
     if energy is not None:
@@ -201,6 +204,10 @@ def time_apsp(fw, torch, n, dtype, path, steps, warmup, prof=False, config=None,
         energy.result = energy.stop(steps, 2.0 * n ** 3)
     sec = total / steps
     stats = None
+    if prof and prof_apart:
+        fw.fw_prof_read(reset=True)
+        fw.fw_prof_enable(True)
+        timed_steps(torch, step, 3, 0)
     if prof:
         fw.fw_prof_enable(False)
         cnt, tot_ms, upd = fw.fw_prof_read(reset=True)
@@ -281,11 +288,13 @@ def time_batched(fw, torch, steps=15, warmup=2):
             "timing": run_stats(per)}
 
 
-def time_ooc(fw, torch, n=32768, S=8192, path=False, runs=15):
+def time_ooc(fw, torch, n=32768, S=8192, path=False, runs=15, warmup=1):
     """Out of core: an n x n float32 complete graph (weights in (0,1)) in pinned host
     memory, through a device budget that holds super-blocks of edge S (n / S
-    super-rounds).  Each timed call (transfers included) starts from the same
-    weights, regenerated into the pinned buffer before it, outside the timing."""
+    super-rounds).  Each call (transfers included) starts from the same weights,
+    regenerated into the pinned buffer before it, outside the timing; `warmup`
+    untimed calls come first (the first call of a process also pays one-time
+    driver costs)."""
     import numpy as np
     import workloads
     nb = -(-n // S)
@@ -296,19 +305,20 @@ def time_ooc(fw, torch, n=32768, S=8192, path=False, runs=15):
     HP = torch.empty((n, n), dtype=torch.int32, pin_memory=True) if path else None
     Hn = H.numpy()
     times = []
-    for _ in range(runs):
+    for r in range(warmup + runs):
         for i0 in range(0, n, 4096):  # the generator writes straight into the pinned rows
             i1 = min(n, i0 + 4096)
             workloads.rows(2, n, i0, i1, 1.0, workloads.W_UNIT_OPEN, 0, np.float32, 0, Hn[i0:i1])
         torch.cuda.synchronize()
         t = time.perf_counter()
         fw.apsp_ooc_(H, HP, budget)
-        times.append(time.perf_counter() - t)
+        if r >= warmup:
+            times.append(time.perf_counter() - t)
     sec = sum(times) / len(times)
     return {"n": n, "superblock": S, "device_bytes": budget, "seconds": round(sec, 3),
             "gflops": round(gflops(n, sec), 2), "dtype": "f32", "path": path,
             "timing": run_stats([t * 1e3 for t in times]),
-            "note": "matrix in pinned host memory; host-to-device and device-to-host transfers included"}
+            "warmup": warmup, "note": "matrix in pinned host memory; host-to-device and device-to-host transfers included"}
 
 
 def time_fwd_bwd(fw, torch, steps=15, warmup=2):
@@ -629,7 +639,7 @@ def main():
                 continue
             print(f"[bench] secondary n={args.n} {dt_} path={pth}", file=sys.stderr, flush=True)
             m2 = EnergyMeter(torch) if (dt_ == "f64" and pth and not args.no_energy) else None
-            s, st, p2 = time_apsp(fw, torch, args.n, dt_, pth, K, Wu, prof=True, energy=m2)
+            s, st, p2 = time_apsp(fw, torch, args.n, dt_, pth, K, Wu, prof=True, energy=m2, prof_apart=True)
             key = f"{dt_}_{'path' if pth else 'dist'}"
             sec_out[key] = {"gflops": round(gflops(args.n, s), 2), "ms_per_step": round(s * 1e3, 2),
                             "timing": run_stats(p2), "roofline_frac": roofline(args.n, dt_, st, pth)["frac"]}
@@ -640,7 +650,7 @@ def main():
         for n2 in (4096, 8192):
             for dt_ in ("f32", "f64"):
                 print(f"[bench] secondary n={n2} {dt_} path=True", file=sys.stderr, flush=True)
-                s, st, p2 = time_apsp(fw, torch, n2, dt_, True, K, Wu, prof=True)
+                s, st, p2 = time_apsp(fw, torch, n2, dt_, True, K, Wu, prof=True, prof_apart=True)
                 sec_out[f"{dt_}_path_n{n2}"] = {"gflops": round(gflops(n2, s), 2), "ms_per_step": round(s * 1e3, 3),
                                                 "timing": run_stats(p2),
                                                 "roofline_frac": roofline(n2, dt_, st, True)["frac"]}

@@ -27,9 +27,7 @@
 #include <stdint.h>
 
 #include <algorithm>
-#include <thread>
 #include <utility>
-#include <vector>
 
 #include "../../include/fw_apsp.h"
 #include "fw_internal.h"
@@ -115,14 +113,10 @@ hipError_t run_ooc(int64_t n, T *H, int32_t *HP, int64_t S, hipStream_t user, co
     }
     int32_t *Ploc = path ? CBPs[1] + NP * S : nullptr;
     const hipStream_t cs = st.cs;
-    if (path) {  // P starts as "no interior vertex"
-        const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-        std::vector<std::thread> th;
-        const int64_t total = n * n, per = (total + nt - 1) / nt;
-        for (unsigned t = 0; t < nt; ++t)
-            th.emplace_back([=] { std::fill(HP + std::min(total, t * per), HP + std::min(total, (t + 1) * per), -1); });
-        for (auto &x : th) x.join();
-    }
+    // P starts as "no interior vertex" (-1).  The host array is output only:
+    // super-round 0 reads every tile once, and its labels are then the -1 the
+    // device buffers are filled with, not an upload; every tile is written
+    // back by the end of super-round 1 (super-round 0 alone when NS = 1).
     // Order after the caller's earlier work on its stream.
     FW_TRY(hipEventRecord(st.start, user));
     FW_TRY(hipStreamWaitEvent(cs, st.start, 0));
@@ -185,10 +179,6 @@ hipError_t run_ooc(int64_t n, T *H, int32_t *HP, int64_t S, hipStream_t user, co
         if (NS > 1 && R == 0) {
             FW_TRY(row_band_copy(RB, NP, H, es, K0, SK, H2D, st.h2d));
             FW_TRY(col_band_copy(CB, H, es, K0, SK, H2D, st.h2d));
-            if (path) {
-                FW_TRY(row_band_copy(RBP, NP, HP, is, K0, SK, H2D, st.h2d));
-                FW_TRY(col_band_copy(CBP, HP, is, K0, SK, H2D, st.h2d));
-            }
             FW_TRY(hipEventRecord(st.bands, st.h2d));
         } else if (R > 0) {
             const int64_t Q = R - 1;
@@ -207,7 +197,6 @@ hipError_t run_ooc(int64_t n, T *H, int32_t *HP, int64_t S, hipStream_t user, co
         if (path) FW_TRY(launch_fill_i32(Pd, S * S, -1, cs));
         if (R == 0) {
             FW_TRY(hipMemcpy2DAsync(Dd, S * es, H + K0 * n + K0, n * es, SK * es, SK, H2D, cs));
-            if (path) FW_TRY(hipMemcpy2DAsync(Pd, S * is, HP + K0 * n + K0, n * is, SK * is, SK, H2D, cs));
         } else {
             FW_TRY(hipMemcpy2DAsync(Dd, S * es, RB + K0, NP * es, SK * es, SK, D2D, cs));
             if (path) FW_TRY(hipMemcpy2DAsync(Pd, S * is, RBP + K0, NP * is, SK * is, SK, D2D, cs));
@@ -279,7 +268,7 @@ hipError_t run_ooc(int64_t n, T *H, int32_t *HP, int64_t S, hipStream_t user, co
                 if (J == R) continue;
                 FW_TRY(hipMemcpy2DAsync(RN + J * S, NP * es, H + L * S * n + J * S, n * es, edge(J) * es, SL, H2D,
                                         st.h2d));
-                if (path)
+                if (path && R > 0)
                     FW_TRY(hipMemcpy2DAsync(RNP + J * S, NP * is, HP + L * S * n + J * S, n * is, edge(J) * is, SL,
                                             H2D, st.h2d));
             }
@@ -287,7 +276,7 @@ hipError_t run_ooc(int64_t n, T *H, int32_t *HP, int64_t S, hipStream_t user, co
                 if (I == R || I == L) continue;
                 FW_TRY(hipMemcpy2DAsync(CN + I * S * S, S * es, H + I * S * n + L * S, n * es, SL * es, edge(I), H2D,
                                         st.h2d));
-                if (path)
+                if (path && R > 0)
                     FW_TRY(hipMemcpy2DAsync(CNP + I * S * S, S * is, HP + I * S * n + L * S, n * is, SL * is, edge(I),
                                             H2D, st.h2d));
             }
@@ -325,7 +314,8 @@ hipError_t run_ooc(int64_t n, T *H, int32_t *HP, int64_t S, hipStream_t user, co
                 int32_t *hp = path ? HP + I * S * n + J * S : nullptr;
                 if (t >= 2) FW_TRY(hipStreamWaitEvent(st.h2d, st.stored[b], 0));  // buffer b is free again
                 FW_TRY(hipMemcpy2DAsync(Cb[b], S * es, h, n * es, SJ * es, SI, H2D, st.h2d));
-                if (path) FW_TRY(hipMemcpy2DAsync(CbP[b], S * is, hp, n * is, SJ * is, SI, H2D, st.h2d));
+                if (path && R > 0) FW_TRY(hipMemcpy2DAsync(CbP[b], S * is, hp, n * is, SJ * is, SI, H2D, st.h2d));
+                if (path && R == 0) FW_TRY(launch_fill_i32(CbP[b], S * S, -1, st.h2d));
                 FW_TRY(hipEventRecord(st.loaded[b], st.h2d));
                 FW_TRY(hipStreamWaitEvent(cs, st.loaded[b], 0));
                 if (path)
