@@ -1,8 +1,10 @@
 """Out-of-core APSP (fw_apsp_ooc): the matrix stays in pinned host memory and
-streams through a device working set sized so that several super-rounds run,
-with a ragged last super-block.  Integer weights: D and P bit-exact against the
-oracle; real weights: D within the float32 / float64 tolerance of the float64
-oracle, and P satisfies the oracle's invariants."""
+streams through a device working set sized so that 1, 2, 3 or 4 super-rounds run
+(with two, the next super-round's bands are the lookahead's diagonal tile plus the
+two tiles copied over on the device), with a ragged last super-block.  The host
+path array is left uninitialised: it is output only.  Integer weights: D and P
+bit-exact against the oracle; real weights: D within the float32 / float64
+tolerance of the float64 oracle, and P satisfies the oracle's invariants."""
 import numpy as np
 import pytest
 
@@ -33,7 +35,7 @@ def run_ooc(W, S_want, path):
 
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
-@pytest.mark.parametrize("n,S", [(3000, 1024), (1000, 1024), (777, 256)])
+@pytest.mark.parametrize("n,S", [(3000, 1024), (1500, 1024), (1000, 1024), (777, 256)])
 @pytest.mark.parametrize("path", [False, True])
 def test_ooc_integer_bit_exact(dtype, n, S, path):
     W = workloads.int_graph(n=n, p=0.3, wmax=100, seed=31 + n, dtype=dtype)
