@@ -596,100 +596,117 @@ __global__ void __launch_bounds__(NT) k_phase4w(T *__restrict__ D, uint16_t *__r
 // (a sub-path decreased later by less than the sum's rounding step); then the k
 // with the smallest sum is taken and the label is k itself, which still encodes
 // a path of length D[i][j] up to rounding.
-template <typename T, int TB>
-__device__ __forceinline__ void resolve_one(const T *__restrict__ D, const T *__restrict__ DT,
-                                            const uint16_t *__restrict__ L, int32_t *__restrict__ P, int64_t ld,
-                                            int64_t i, int64_t j) {
-    using vec = typename V16<T>::type;
-    constexpr int V = V16<T>::n;
-    const int64_t ij = i * ld + j;
-    const int lv = L[ij];
-    if (lv == 0) return;
-    const int64_t k0 = (int64_t)(lv - 1) * TB;
-    const T d = D[ij];
-    const T *arow = D + i * ld + k0;
-    const T *brow = DT + j * ld + k0;
-    uint64_t hits = 0;
-    T best = inf_v<T>();
-    int kbest = 0;
-#pragma unroll 4
-    for (int kv = 0; kv < TB / V; ++kv) {
-        const vec a = *(const vec *)(arow + kv * V);
-        const vec b = *(const vec *)(brow + kv * V);
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-            const T s = a[e] + b[e];
-            const int k = kv * V + e;
-            hits |= (s == d) ? (1ull << k) : 0ull;
-            kbest = (s < best) ? k : kbest;
-            best = vmin(best, s);
-        }
-    }
-    int32_t M = INT_MAX;
-    while (hits) {
-        const int k = __builtin_ctzll(hits);
-        hits &= hits - 1;
-        const int64_t kg = k0 + k;
-        if (L[i * ld + kg] > lv || L[kg * ld + j] > lv) continue;  // decreased after round r
-        M = min(M, max(max(P[i * ld + kg], P[kg * ld + j]), (int32_t)kg));
-    }
-    P[ij] = (M == INT_MAX) ? (int32_t)(k0 + kbest) : M;
-}
-
-// The same with each entry's label + 1 and mark packed in one word
-// (W = mark << 16 | label + 1, ld <= 65535), so that a candidate k costs one
+// For ld <= 65535 each entry's label + 1 and mark are packed in one word
+// (W = mark << 16 | label + 1, k_pack_marks), so that a candidate k costs one
 // gathered word of (k, j) instead of a label and a mark.  A word read here is
 // either still pending (its mark and the label it had when marked) or already
 // resolved (its mark and its final label): the argument above gives the same
 // minimum either way.  A resolved word keeps its mark, so whether a neighbour
 // entry counts as decreased after round r never depends on whether another
 // thread has resolved it yet, and the result does not depend on timing.
-template <typename T, int TB>
-__device__ __forceinline__ void resolve_one_packed(const T *__restrict__ D, const T *__restrict__ DT,
-                                                   uint32_t *__restrict__ W, int64_t ld, int64_t i, int64_t j) {
-    using vec = typename V16<T>::type;
-    constexpr int V = V16<T>::n;
-    const int64_t ij = i * ld + j;
-    const uint32_t lv = W[ij] >> 16;
-    if (lv == 0) return;
-    const int64_t k0 = (int64_t)(lv - 1) * TB;
-    const T d = D[ij];
-    const T *arow = D + i * ld + k0;
-    const T *brow = DT + j * ld + k0;
-    uint64_t hits = 0;
-    T best = inf_v<T>();
-    int kbest = 0;
-#pragma unroll 4
-    for (int kv = 0; kv < TB / V; ++kv) {
-        const vec a = *(const vec *)(arow + kv * V);
-        const vec b = *(const vec *)(brow + kv * V);
-#pragma unroll
-        for (int e = 0; e < V; ++e) {
-            const T s = a[e] + b[e];
-            const int k = kv * V + e;
-            hits |= (s == d) ? (1ull << k) : 0ull;
-            kbest = (s < best) ? k : kbest;
-            best = vmin(best, s);
-        }
-    }
-    uint32_t M = 0xffffffffu;
-    while (hits) {
-        const int k = __builtin_ctzll(hits);
-        hits &= hits - 1;
-        const int64_t kg = k0 + k;
-        const uint32_t wik = W[i * ld + kg], wkj = W[kg * ld + j];
-        if ((wik >> 16) > lv || (wkj >> 16) > lv) continue;  // decreased after round lv - 1
-        M = min(M, max(max(wik & 0xffffu, wkj & 0xffffu), (uint32_t)(kg + 1)));
-    }
-    W[ij] = (lv << 16) | ((M == 0xffffffffu) ? (uint32_t)(k0 + kbest + 1) : M);
+// The resolve itself.  A wave takes the pending entries among its 64
+// consecutive columns of row i, four at a time, with 16 lanes per entry and
+// TB / 16 consecutive candidates k per lane: every load instruction then reads
+// whole segments of four entries, where one thread per entry made each load
+// touch 64 different cache lines.  The lanes that find an exact hit gather its
+// words (in parallel), the group's minimum label is reduced across its 16 lanes
+// (one DPP row), and the group's first lane writes the entry.  An entry without
+// a usable hit (rare: rounding) gets the first strict minimum, from the group's
+// first lane.  Each entry's mark and length are read once, coalesced, by the
+// lane of its column and handed to its group (readlane), and the results go
+// through LDS to one coalesced store per wave.  PACKED: marks and labels in W
+// (above); else marks in L and labels in P, for ld > 65535.  Labels are handled
+// as label + 1 (unsigned).
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_min(uint32_t v) {
+    return min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false));
 }
-
-template <typename T, int TB>
-__global__ void __launch_bounds__(NT) k_resolve_packed(const T *__restrict__ D, const T *__restrict__ DT,
-                                                      uint32_t *__restrict__ W, int64_t ld) {
-    const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (j >= ld) return;
-    for (int64_t i = blockIdx.y; i < ld; i += gridDim.y) resolve_one_packed<T, TB>(D, DT, W, ld, i, j);
+template <typename T> __device__ __forceinline__ T readlane_t(T v, int l);
+template <> __device__ __forceinline__ float readlane_t(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+template <> __device__ __forceinline__ double readlane_t(double v, int l) {
+    const int64_t x = __builtin_bit_cast(int64_t, v);
+    const int lo = __builtin_amdgcn_readlane((int)x, l), hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+    return __builtin_bit_cast(double, ((int64_t)hi << 32) | (uint32_t)lo);
+}
+template <> __device__ __forceinline__ _Float16 readlane_t(_Float16 v, int l) {
+    return __builtin_bit_cast(_Float16, (uint16_t)__builtin_amdgcn_readlane((int)__builtin_bit_cast(uint16_t, v), l));
+}
+template <typename T, int TB, bool PACKED>
+__global__ void __launch_bounds__(NT) k_resolve(const T *__restrict__ D, const T *__restrict__ DT,
+                                               uint32_t *__restrict__ W, const uint16_t *__restrict__ L,
+                                               int32_t *__restrict__ P, int64_t ld) {
+    constexpr int CPL = TB / 16;  // candidates per lane
+    static_assert(CPL * 16 == TB, "resolve group");
+    typedef T cvec __attribute__((ext_vector_type(CPL)));
+    __shared__ uint32_t res[NT];  // each wave's results, by column, for one coalesced store
+    const int lane = threadIdx.x & 63, g = lane >> 4, p = lane & 15, wbase = threadIdx.x & ~63;
+    const int64_t jb = (int64_t)blockIdx.x * NT + wbase;  // the wave's first column
+    auto mark_of = [&](int64_t x) -> uint32_t { return PACKED ? W[x] >> 16 : (uint32_t)L[x]; };
+    auto label1_of = [&](int64_t x) -> uint32_t { return PACKED ? W[x] & 0xffffu : (uint32_t)(P[x] + 1); };
+    for (int64_t i = blockIdx.y; i < ld; i += gridDim.y) {  // grid y is capped at 65535 rows
+        const int64_t j = jb + lane;
+        const uint32_t mk = j < ld ? mark_of(i * ld + j) : 0u;
+        const T dj = j < ld ? D[i * ld + j] : T(0);
+        uint64_t mask = __ballot(mk != 0);  // the same in every lane
+        const uint64_t pending = mask;
+        while (mask) {
+            int e[4];
+            uint32_t me[4];
+            T de[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                e[q] = mask ? __builtin_ctzll(mask) : -1;
+                me[q] = mask ? (uint32_t)__builtin_amdgcn_readlane((int)mk, e[q]) : 0u;
+                de[q] = mask ? readlane_t(dj, e[q]) : T(0);
+                if (mask) mask &= mask - 1;
+            }
+            const int eg = g == 0 ? e[0] : g == 1 ? e[1] : g == 2 ? e[2] : e[3];
+            const uint32_t lv = g == 0 ? me[0] : g == 1 ? me[1] : g == 2 ? me[2] : me[3];
+            const T d = g == 0 ? de[0] : g == 1 ? de[1] : g == 2 ? de[2] : de[3];
+            if (eg < 0) continue;
+            const int64_t je = jb + eg;
+            const int64_t k0 = (int64_t)(lv - 1) * TB, kl = k0 + p * CPL;
+            const cvec a = *(const cvec *)(D + i * ld + kl);
+            const cvec b = *(const cvec *)(DT + je * ld + kl);
+            uint32_t hm = 0;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) hm |= (a[c] + b[c] == d) ? (1u << c) : 0u;
+            uint32_t M = 0xffffffffu;
+            while (hm) {  // this lane's exact hits: their two words each
+                const int64_t kg = kl + __builtin_ctz(hm);
+                hm &= hm - 1;
+                if (mark_of(i * ld + kg) <= lv && mark_of(kg * ld + je) <= lv)  // else decreased after round lv - 1
+                    M = min(M, max(max(label1_of(i * ld + kg), label1_of(kg * ld + je)), (uint32_t)(kg + 1)));
+            }
+            M = dpp_min<0xB1>(M);   // quad_perm [1, 0, 3, 2]
+            M = dpp_min<0x4E>(M);   // quad_perm [2, 3, 0, 1]
+            M = dpp_min<0x141>(M);  // row_half_mirror
+            M = dpp_min<0x140>(M);  // row_mirror: the minimum of all 16 lanes
+            if (p == 0) {
+                if (M == 0xffffffffu) {
+                    T best = inf_v<T>();
+                    int kbest = 0;
+                    for (int k = 0; k < TB; ++k) {
+                        const T sk = D[i * ld + k0 + k] + DT[je * ld + k0 + k];
+                        kbest = (sk < best) ? k : kbest;
+                        best = vmin(best, sk);
+                    }
+                    M = (uint32_t)(k0 + kbest + 1);
+                }
+                res[wbase + eg] = M;
+            }
+        }
+        __syncthreads();  // every group's result is in res
+        if ((pending >> lane) & 1) {
+            if constexpr (PACKED)
+                W[i * ld + j] = (mk << 16) | res[threadIdx.x];
+            else
+                P[i * ld + j] = (int32_t)res[threadIdx.x] - 1;
+        }
+        __syncthreads();  // res is free for the next row
+    }
 }
 
 // P (labels, -1 = none) and L (marks) -> W = mark << 16 | label + 1, in P's
@@ -702,17 +719,6 @@ __global__ void __launch_bounds__(NT) k_pack_marks(int32_t *__restrict__ P, cons
 __global__ void __launch_bounds__(NT) k_unpack_labels(int32_t *__restrict__ P, int64_t count) {
     for (int64_t x = (int64_t)blockIdx.x * NT + threadIdx.x; x < count; x += (int64_t)gridDim.x * NT)
         P[x] = (int32_t)((uint32_t)P[x] & 0xffffu) - 1;
-}
-
-template <typename T, int TB>
-__global__ void __launch_bounds__(NT) k_resolve(const T *__restrict__ D, const T *__restrict__ DT,
-                                               const uint16_t *__restrict__ L, int32_t *__restrict__ P,
-                                               int64_t ld) {
-    const int64_t j = (int64_t)blockIdx.x * NT + threadIdx.x;
-    if (j >= ld) return;
-    for (int64_t i = blockIdx.y; i < ld; i += gridDim.y) {  // grid y is capped at 65535 rows
-        resolve_one<T, TB>(D, DT, L, P, ld, i, j);
-    }
 }
 
 // Tiled transpose: DT[j][i] = D[i][j] (ld x ld, ld a multiple of 64).
@@ -949,16 +955,16 @@ hipError_t launch_resolve(const T *D, T *DT, const uint16_t *L, int32_t *P, int6
         uint32_t *W = (uint32_t *)P;
         hipLaunchKernelGGL(k_pack_marks, dim3(grid_for(ld * ld)), dim3(NT), 0, s, P, L, ld * ld);
         if (block == 64)
-            hipLaunchKernelGGL((k_resolve_packed<T, 64>), grid, dim3(NT), 0, s, D, DT, W, ld);
+            hipLaunchKernelGGL((k_resolve<T, 64, true>), grid, dim3(NT), 0, s, D, DT, W, L, P, ld);
         else
-            hipLaunchKernelGGL((k_resolve_packed<T, 32>), grid, dim3(NT), 0, s, D, DT, W, ld);
+            hipLaunchKernelGGL((k_resolve<T, 32, true>), grid, dim3(NT), 0, s, D, DT, W, L, P, ld);
         hipLaunchKernelGGL(k_unpack_labels, dim3(grid_for(ld * ld)), dim3(NT), 0, s, P, ld * ld);
         return hipGetLastError();
     }
     if (block == 64)
-        hipLaunchKernelGGL((k_resolve<T, 64>), grid, dim3(NT), 0, s, D, DT, L, P, ld);
+        hipLaunchKernelGGL((k_resolve<T, 64, false>), grid, dim3(NT), 0, s, D, DT, nullptr, L, P, ld);
     else
-        hipLaunchKernelGGL((k_resolve<T, 32>), grid, dim3(NT), 0, s, D, DT, L, P, ld);
+        hipLaunchKernelGGL((k_resolve<T, 32, false>), grid, dim3(NT), 0, s, D, DT, nullptr, L, P, ld);
     return hipGetLastError();
 }
 
