@@ -613,34 +613,25 @@ __global__ void __launch_bounds__(NT) k_phase4w(T *__restrict__ D, uint16_t *__r
 // (one DPP row), and the group's first lane writes the entry.  An entry without
 // a usable hit (rare: rounding) gets the first strict minimum, from the group's
 // first lane.  Each entry's mark and length are read once, coalesced, by the
-// lane of its column and handed to its group (readlane), and the results go
-// through LDS to one coalesced store per wave.  PACKED: marks and labels in W
-// (above); else marks in L and labels in P, for ld > 65535.  Labels are handled
-// as label + 1 (unsigned).
+// lane of its column and listed in LDS (pending entries only, in column order);
+// a group takes EPG entries per pass, their loads all in flight together; the
+// results go through LDS to one coalesced store per wave.  PACKED: marks and
+// labels in W (above); else marks in L and labels in P, for ld > 65535.  Labels
+// are handled as label + 1 (unsigned).
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp_min(uint32_t v) {
     return min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, 0xF, 0xF, false));
 }
-template <typename T> __device__ __forceinline__ T readlane_t(T v, int l);
-template <> __device__ __forceinline__ float readlane_t(float v, int l) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-template <> __device__ __forceinline__ double readlane_t(double v, int l) {
-    const int64_t x = __builtin_bit_cast(int64_t, v);
-    const int lo = __builtin_amdgcn_readlane((int)x, l), hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
-    return __builtin_bit_cast(double, ((int64_t)hi << 32) | (uint32_t)lo);
-}
-template <> __device__ __forceinline__ _Float16 readlane_t(_Float16 v, int l) {
-    return __builtin_bit_cast(_Float16, (uint16_t)__builtin_amdgcn_readlane((int)__builtin_bit_cast(uint16_t, v), l));
-}
-template <typename T, int TB, bool PACKED>
+template <typename T, int TB, bool PACKED, int EPG>
 __global__ void __launch_bounds__(NT) k_resolve(const T *__restrict__ D, const T *__restrict__ DT,
                                                uint32_t *__restrict__ W, const uint16_t *__restrict__ L,
                                                int32_t *__restrict__ P, int64_t ld) {
     constexpr int CPL = TB / 16;  // candidates per lane
     static_assert(CPL * 16 == TB, "resolve group");
     typedef T cvec __attribute__((ext_vector_type(CPL)));
-    __shared__ uint32_t res[NT];  // each wave's results, by column, for one coalesced store
+    __shared__ uint32_t res[NT];                 // results by column, for one coalesced store per wave
+    __shared__ uint32_t s_col[NT], s_mark[NT];   // each wave's pending entries, compacted
+    __shared__ T s_len[NT];
     const int lane = threadIdx.x & 63, g = lane >> 4, p = lane & 15, wbase = threadIdx.x & ~63;
     const int64_t jb = (int64_t)blockIdx.x * NT + wbase;  // the wave's first column
     auto mark_of = [&](int64_t x) -> uint32_t { return PACKED ? W[x] >> 16 : (uint32_t)L[x]; };
@@ -649,63 +640,75 @@ __global__ void __launch_bounds__(NT) k_resolve(const T *__restrict__ D, const T
         const int64_t j = jb + lane;
         const uint32_t mk = j < ld ? mark_of(i * ld + j) : 0u;
         const T dj = j < ld ? D[i * ld + j] : T(0);
-        uint64_t mask = __ballot(mk != 0);  // the same in every lane
-        const uint64_t pending = mask;
-        while (mask) {
-            int e[4];
-            uint32_t me[4];
-            T de[4];
+        const uint64_t pending = __ballot(mk != 0);  // the same in every lane
+        const int npend = __builtin_popcountll(pending);
+        if (mk != 0) {
+            const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(pending >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)pending, 0));
+            s_col[wbase + rank] = lane;
+            s_mark[wbase + rank] = mk;
+            s_len[wbase + rank] = dj;
+        }
+        __syncthreads();  // the lists are written
+        // Passes of 4 * EPG entries: group g takes list slots base + 4 m + g.
+        for (int base = 0; base < npend; base += 4 * EPG) {
+            int col[EPG];
+            uint32_t lv[EPG];
+            T d[EPG];
+            cvec a[EPG], b[EPG];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                e[q] = mask ? __builtin_ctzll(mask) : -1;
-                me[q] = mask ? (uint32_t)__builtin_amdgcn_readlane((int)mk, e[q]) : 0u;
-                de[q] = mask ? readlane_t(dj, e[q]) : T(0);
-                if (mask) mask &= mask - 1;
+            for (int m = 0; m < EPG; ++m) {
+                const int sl = base + 4 * m + g;
+                const bool ok = sl < npend;
+                col[m] = ok ? (int)s_col[wbase + sl] : -1;
+                lv[m] = ok ? s_mark[wbase + sl] : 1u;
+                d[m] = ok ? s_len[wbase + sl] : T(0);
+                const int64_t je = jb + (ok ? col[m] : 0), kl = (int64_t)(lv[m] - 1) * TB + p * CPL;
+                a[m] = *(const cvec *)(D + i * ld + kl);
+                b[m] = *(const cvec *)(DT + je * ld + kl);
             }
-            const int eg = g == 0 ? e[0] : g == 1 ? e[1] : g == 2 ? e[2] : e[3];
-            const uint32_t lv = g == 0 ? me[0] : g == 1 ? me[1] : g == 2 ? me[2] : me[3];
-            const T d = g == 0 ? de[0] : g == 1 ? de[1] : g == 2 ? de[2] : de[3];
-            if (eg < 0) continue;
-            const int64_t je = jb + eg;
-            const int64_t k0 = (int64_t)(lv - 1) * TB, kl = k0 + p * CPL;
-            const cvec a = *(const cvec *)(D + i * ld + kl);
-            const cvec b = *(const cvec *)(DT + je * ld + kl);
-            uint32_t hm = 0;
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) hm |= (a[c] + b[c] == d) ? (1u << c) : 0u;
-            uint32_t M = 0xffffffffu;
-            while (hm) {  // this lane's exact hits: their two words each
-                const int64_t kg = kl + __builtin_ctz(hm);
-                hm &= hm - 1;
-                if (mark_of(i * ld + kg) <= lv && mark_of(kg * ld + je) <= lv)  // else decreased after round lv - 1
-                    M = min(M, max(max(label1_of(i * ld + kg), label1_of(kg * ld + je)), (uint32_t)(kg + 1)));
-            }
-            M = dpp_min<0xB1>(M);   // quad_perm [1, 0, 3, 2]
-            M = dpp_min<0x4E>(M);   // quad_perm [2, 3, 0, 1]
-            M = dpp_min<0x141>(M);  // row_half_mirror
-            M = dpp_min<0x140>(M);  // row_mirror: the minimum of all 16 lanes
-            if (p == 0) {
-                if (M == 0xffffffffu) {
-                    T best = inf_v<T>();
-                    int kbest = 0;
-                    for (int k = 0; k < TB; ++k) {
-                        const T sk = D[i * ld + k0 + k] + DT[je * ld + k0 + k];
-                        kbest = (sk < best) ? k : kbest;
-                        best = vmin(best, sk);
-                    }
-                    M = (uint32_t)(k0 + kbest + 1);
+            for (int m = 0; m < EPG; ++m) {
+                const int64_t je = jb + (col[m] >= 0 ? col[m] : 0);
+                const int64_t k0 = (int64_t)(lv[m] - 1) * TB, kl = k0 + p * CPL;
+                uint32_t hm = 0;
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) hm |= (a[m][c] + b[m][c] == d[m]) ? (1u << c) : 0u;
+                if (col[m] < 0) hm = 0;
+                uint32_t M = 0xffffffffu;
+                while (hm) {  // this lane's exact hits: their two words each
+                    const int64_t kg = kl + __builtin_ctz(hm);
+                    hm &= hm - 1;
+                    if (mark_of(i * ld + kg) <= lv[m] && mark_of(kg * ld + je) <= lv[m])  // else decreased after round lv - 1
+                        M = min(M, max(max(label1_of(i * ld + kg), label1_of(kg * ld + je)), (uint32_t)(kg + 1)));
                 }
-                res[wbase + eg] = M;
+                M = dpp_min<0xB1>(M);   // quad_perm [1, 0, 3, 2]
+                M = dpp_min<0x4E>(M);   // quad_perm [2, 3, 0, 1]
+                M = dpp_min<0x141>(M);  // row_half_mirror
+                M = dpp_min<0x140>(M);  // row_mirror: the minimum of all 16 lanes
+                if (p == 0 && col[m] >= 0) {
+                    if (M == 0xffffffffu) {
+                        T best = inf_v<T>();
+                        int kbest = 0;
+                        for (int k = 0; k < TB; ++k) {
+                            const T sk = D[i * ld + k0 + k] + DT[je * ld + k0 + k];
+                            kbest = (sk < best) ? k : kbest;
+                            best = vmin(best, sk);
+                        }
+                        M = (uint32_t)(k0 + kbest + 1);
+                    }
+                    res[wbase + col[m]] = M;
+                }
             }
         }
         __syncthreads();  // every group's result is in res
-        if ((pending >> lane) & 1) {
+        if (mk != 0) {
             if constexpr (PACKED)
                 W[i * ld + j] = (mk << 16) | res[threadIdx.x];
             else
                 P[i * ld + j] = (int32_t)res[threadIdx.x] - 1;
         }
-        __syncthreads();  // res is free for the next row
+        __syncthreads();  // res and the lists are free for the next row
     }
 }
 
@@ -946,6 +949,8 @@ bool pairs_supported(TileCfg c) {
     return c.variant == FW_VARIANT_PANELS && c.tile_m == c.block && c.tile_n == c.block;
 }
 
+constexpr int kResolveEPG = 2;  // entries per 16-lane group and pass in k_resolve
+
 template <typename T>
 hipError_t launch_resolve(const T *D, T *DT, const uint16_t *L, int32_t *P, int64_t ld, int block, hipStream_t s) {
     hipLaunchKernelGGL((k_transpose<T>), dim3((unsigned)(ld / 64), (unsigned)(ld / 64)), dim3(NT), 0, s, D, DT, ld);
@@ -955,16 +960,16 @@ hipError_t launch_resolve(const T *D, T *DT, const uint16_t *L, int32_t *P, int6
         uint32_t *W = (uint32_t *)P;
         hipLaunchKernelGGL(k_pack_marks, dim3(grid_for(ld * ld)), dim3(NT), 0, s, P, L, ld * ld);
         if (block == 64)
-            hipLaunchKernelGGL((k_resolve<T, 64, true>), grid, dim3(NT), 0, s, D, DT, W, L, P, ld);
+            hipLaunchKernelGGL((k_resolve<T, 64, true, kResolveEPG>), grid, dim3(NT), 0, s, D, DT, W, L, P, ld);
         else
-            hipLaunchKernelGGL((k_resolve<T, 32, true>), grid, dim3(NT), 0, s, D, DT, W, L, P, ld);
+            hipLaunchKernelGGL((k_resolve<T, 32, true, kResolveEPG>), grid, dim3(NT), 0, s, D, DT, W, L, P, ld);
         hipLaunchKernelGGL(k_unpack_labels, dim3(grid_for(ld * ld)), dim3(NT), 0, s, P, ld * ld);
         return hipGetLastError();
     }
     if (block == 64)
-        hipLaunchKernelGGL((k_resolve<T, 64, false>), grid, dim3(NT), 0, s, D, DT, nullptr, L, P, ld);
+        hipLaunchKernelGGL((k_resolve<T, 64, false, kResolveEPG>), grid, dim3(NT), 0, s, D, DT, nullptr, L, P, ld);
     else
-        hipLaunchKernelGGL((k_resolve<T, 32, false>), grid, dim3(NT), 0, s, D, DT, nullptr, L, P, ld);
+        hipLaunchKernelGGL((k_resolve<T, 32, false, kResolveEPG>), grid, dim3(NT), 0, s, D, DT, nullptr, L, P, ld);
     return hipGetLastError();
 }
 
