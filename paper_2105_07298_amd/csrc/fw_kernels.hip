@@ -55,9 +55,15 @@ namespace {
 // (few entries each, every SIMD busy within a step) or 256 (one wave per SIMD).
 // The 256-thread form is the one that fits on a CU beside the last phase's
 // workgroups when it runs concurrently with them (the lookahead schedules):
-// 1024 threads need four waves on every SIMD of one CU, i.e. a CU from which
-// every last-phase workgroup has left.
-template <typename T> constexpr int p1_ts() { return sizeof(T) == 8 ? 16 : 32; }
+// 1024 threads need four waves on every SIMD of one CU, i.e. a CU that two or
+// more last-phase workgroups have left, which seldom happens while the
+// last-phase launch is still placing workgroups.  It is used for 64-deep
+// float32 and float64 blocks, whose fused last-phase launches run beside
+// phases 1-3 of the next pair (measured at n = 16384, float32 with P: phase 1
+// waited 522 us for a CU beside a launch of six workgroups per CU, and took
+// 69 us in the 256-thread form).  binary16 and 32-deep blocks keep 1024 threads:
+// their last-phase launches are short, and phase 1's own duration counts.
+template <typename T, int TB> constexpr int p1_ts() { return (sizeof(T) == 8 || (sizeof(T) == 4 && TB == 64)) ? 16 : 32; }
 template <typename T, int TB, bool PATH, int TS>
 __global__ void __launch_bounds__(TS *TS) k_phase1(T *__restrict__ D, int32_t *__restrict__ P,
                                                   uint16_t *__restrict__ L, int64_t ld, int r) {
@@ -67,9 +73,10 @@ __global__ void __launch_bounds__(TS *TS) k_phase1(T *__restrict__ D, int32_t *_
     __shared__ uint32_t sp[PATH ? TB * ST : 1];  // labels + 1
     const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
     const int64_t k0 = (int64_t)r * TB;
+    static_assert(RM * RM <= 32, "phase 1 change mask");
     T d[RM][RM];
     uint32_t p[RM][RM];
-    bool changed[RM][RM];
+    uint32_t changed = 0;  // bit ii * RM + jj: entry (ii, jj) changed
 #pragma unroll
     for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
@@ -78,7 +85,6 @@ __global__ void __launch_bounds__(TS *TS) k_phase1(T *__restrict__ D, int32_t *_
             const int64_t g = (k0 + row) * ld + k0 + col;
             d[ii][jj] = PATH ? canon(D[g]) : D[g];
             sd[row * ST + col] = d[ii][jj];
-            changed[ii][jj] = false;
             if (PATH) {
                 p[ii][jj] = (uint32_t)(P[g] + 1);
                 sp[row * ST + col] = p[ii][jj];
@@ -112,12 +118,12 @@ __global__ void __launch_bounds__(TS *TS) k_phase1(T *__restrict__ D, int32_t *_
                     if (p[ii][jj] != p0 || d[ii][jj] != d0) {
                         sd[idx] = d[ii][jj];
                         sp[idx] = p[ii][jj];
-                        changed[ii][jj] = true;
+                        changed |= 1u << (ii * RM + jj);
                     }
                 } else if (s < d[ii][jj]) {
                     d[ii][jj] = s;
                     sd[idx] = s;
-                    changed[ii][jj] = true;
+                    changed |= 1u << (ii * RM + jj);
                 }
             }
         __syncthreads();
@@ -126,7 +132,7 @@ __global__ void __launch_bounds__(TS *TS) k_phase1(T *__restrict__ D, int32_t *_
     for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
         for (int jj = 0; jj < RM; ++jj) {
-            if (!changed[ii][jj]) continue;
+            if (!((changed >> (ii * RM + jj)) & 1)) continue;
             const int64_t g = (k0 + ty + TS * ii) * ld + k0 + tx + TS * jj;
             D[g] = d[ii][jj];
             if (PATH) {
@@ -169,15 +175,15 @@ __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__re
     // A = D[I0.., K] and B = D[K, J0..]: for a row panel A is the closed diagonal
     // block and B the old tile, for a column panel the other way round.
     const int tx = threadIdx.x % TS, ty = threadIdx.x / TS;
-    T d[RM][RM], d0[RM][RM];
-    uint32_t p[RM][RM], p0[RM][RM];
+    T d[RM][RM];
+    uint32_t p[RM][RM];
 #pragma unroll
     for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
         for (int jj = 0; jj < RM; ++jj) {
             const int64_t g = (I0 + ty + TS * ii) * ld + J0 + tx + TS * jj;
-            d[ii][jj] = d0[ii][jj] = PATH ? canon(D[g]) : D[g];
-            if (PATH) p[ii][jj] = p0[ii][jj] = (uint32_t)(P[g] + 1);
+            d[ii][jj] = PATH ? canon(D[g]) : D[g];
+            if (PATH) p[ii][jj] = (uint32_t)(P[g] + 1);
         }
     for (int kc = 0; kc < TB; kc += KC) {
         if (kc) __syncthreads();  // every thread is done with the previous chunk
@@ -220,12 +226,17 @@ __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__re
                 }
         }
     }
+    // Store the entries that changed.  The old values are read again rather
+    // than kept in registers through the k-loop (which would cost the kernel
+    // its fit beside the last phase's workgroups): nothing else writes the tile
+    // while this workgroup runs, so they are still in memory.
 #pragma unroll
     for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
         for (int jj = 0; jj < RM; ++jj) {
-            if (d[ii][jj] == d0[ii][jj] && (!PATH || p[ii][jj] == p0[ii][jj])) continue;
             const int64_t g = (I0 + ty + TS * ii) * ld + J0 + tx + TS * jj;
+            const T d0 = PATH ? canon(D[g]) : D[g];
+            if (d[ii][jj] == d0 && (!PATH || p[ii][jj] == (uint32_t)(P[g] + 1))) continue;
             D[g] = d[ii][jj];
             if (PATH) {
                 P[g] = (int32_t)p[ii][jj] - 1;
@@ -234,19 +245,48 @@ __global__ void __launch_bounds__(NT) k_phase23(T *__restrict__ D, int32_t *__re
         }
 }
 
+// Last-phase LDS panels are filled by direct global-to-LDS loads: one wave
+// instruction moves 64 16-byte vectors and lands lane l's vector at the wave's
+// LDS address + 16 l, so each panel is laid out in whole 64-vector slots.  A
+// rows are padded by one vector (its slot is filled with a harmless reload) so
+// that the rows a wave reads start in different banks.
+template <typename T>
+constexpr int p4_slots_a(int BM, int kc) { return (BM * (kc / (16 / (int)sizeof(T)) + 1) + 63) / 64 * 64; }
+template <typename T>
+constexpr int p4_slots_b(int BN, int kc) { return (kc * (BN / (16 / (int)sizeof(T))) + 63) / 64 * 64; }
+
+// Two panel buffers: chunk c + 1 of k loads while chunk c is swept.
+constexpr int kP4Buffers = 2;
+
 // k per staged chunk of the last phase's panels: the whole block, halved while
-// the two panels of a chunk take more than the LDS share of the workgroups per CU
-// that the kernel's registers allow: 40 KB (four of the 160 KB), and 32 KB (five)
-// for the float32 64 x 64 tile, whose 95 VGPRs allow five waves per SIMD
-// (measured at n = 16384: with P 188.8 -> 186.0 ms, distances 152.1 -> 149.0 ms).
+// both buffers take more than the LDS share of the workgroups per CU that the
+// kernel's registers allow: 40 KB (four of the 160 KB), and 32 KB (five) for
+// the float32 64 x 64 tile, whose registers allow five waves per SIMD.
 template <typename T>
 constexpr int p4_kchunk(int TB, int BM, int BN) {
     int kc = TB;
     const int v = 16 / (int)sizeof(T);
     const int cap = (sizeof(T) == 4 && BM == 64 && BN == 64) ? 32 * 1024 : 40 * 1024;
-    while (kc > 2 * v && (BM * (kc + v) + kc * BN) * (int)sizeof(T) > cap) kc /= 2;
+    while (kc > 2 * v && kP4Buffers * (p4_slots_a<T>(BM, kc) + p4_slots_b<T>(BN, kc)) * 16 > cap) kc /= 2;
     return kc;
 }
+
+// One 16-byte direct load from global memory into LDS for this lane.  lds must
+// be the same for every lane of the wave (it becomes the wave's base address);
+// the vector lands at lds + 16 * lane.  Completion is counted by vmcnt.
+__device__ __forceinline__ void lds_load16(const void *g, void *lds) {
+    __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void *)g,
+                                     (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
+}
+// The value itself, in a register the compiler cannot see through: a 32-bit
+// offset stays 32 bits at its use, so the load takes the scalar-base plus
+// 32-bit-offset form instead of a hoisted 64-bit address per lane.
+__device__ __forceinline__ uint32_t opaque(uint32_t x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+// Wait until this wave's direct loads (every vector memory load) have landed.
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
 
 // ---------------------------------------------------------------------------
 // Phase 4: C = D[I0:I0+BM, J0:J0+BN] <- min(C, D[I, K] (x) D[K, J]) for every
@@ -286,22 +326,33 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
     static_assert(TY * RM == BM, "tile rows");
     static_assert(RN % V == 0, "micro-tile width");
     constexpr int HN = RN / V, CS = BN / HN;
-    // The panels of a round are staged KC values of k at a time (KC = TB unless
-    // both panels of the whole block would take more than 40 KB of LDS, which
-    // would leave room for fewer than four workgroups per CU).
+    // The panels of a round are staged KC values of k at a time in two buffers
+    // (KC = TB unless both buffers would take more than the LDS share in
+    // p4_kchunk), each chunk's direct loads in flight while the previous chunk
+    // is swept.
     constexpr int KC = p4_kchunk<T>(TB, BM, BN);
     static_assert(TB % KC == 0 && KC % V == 0, "k chunk");
     constexpr int AST = KC + V;
-    // Old C values are requested before the panel loads when they fit the
-    // register budget (up to 128 bytes per thread), else after the k-loop.
-    // float64 never prefetches: its 4 x 4 tile's 32 prefetch registers took the
-    // launch from 121 to 167 VGPRs, i.e. from four waves per SIMD to three, and
-    // the fourth wave hides more latency than the prefetch (measured at
-    // n = 16384: with P 414.7 -> 403.9 ms, distances 348.3 -> 325.8 ms).
-    constexpr bool PREFETCH_C = RM * RN * (int)sizeof(T) <= 128 && sizeof(T) != 8;
+    constexpr int KV = KC / V;  // vectors of k per A row
+    constexpr int SA = p4_slots_a<T>(BM, KC), SB = p4_slots_b<T>(BN, KC);
+    constexpr int CPR = TB / KC, NCH = (FUSE ? 2 : 1) * CPR;  // chunks per round, per launch
+    // Old C values are requested before the panel loads (binary16, up to 128
+    // bytes per thread) or after the k-loop.  float32 and float64 load them
+    // after: the registers a prefetch holds through the k-loop cost a workgroup
+    // per CU (float32 64 x 64 tile: 100 VGPRs, four workgroups, with it; 76 and
+    // six without), and the extra workgroups hide more latency (measured at
+    // n = 16384 with the direct-load staging: float32 with P 178.8 -> 174.4 ms,
+    // distances 146.3 -> 144.7 ms).
+    constexpr bool PREFETCH_C = is_half_v<T> && RM * RN * (int)sizeof(T) <= 128;
+    // float64 sweeps one vector of k per loop iteration: unrolled twice, the
+    // compiler's schedule took the fused launch from four waves per SIMD to three.
+    constexpr int SWEEP_UNROLL = sizeof(T) == 8 ? 1 : 2;
 
-    __shared__ __attribute__((aligned(16))) T As[BM * AST];
-    __shared__ __attribute__((aligned(16))) T Bs[KC * BN];
+    // Two buffers as distinct LDS objects, each named statically where it is
+    // used: the compiler can then tell the next chunk's direct loads from the
+    // current chunk's reads and does not wait for the former before the latter.
+    __shared__ __attribute__((aligned(16))) T As0[SA * V], As1[kP4Buffers == 2 ? SA * V : 1];
+    __shared__ __attribute__((aligned(16))) T Bs0[SB * V], Bs1[kP4Buffers == 2 ? SB * V : 1];
 
     int bi, bj;
     if (!select_tile<BAND>(sel, blockIdx.x, bi, bj)) return;
@@ -321,28 +372,53 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
             for (int h = 0; h < HN; ++h) c[ii][h] = *(const vec *)c_ptr(ii, h);
     }
 
-    // Stage columns kb + kc .. kb + kc + KC - 1 of the column panel D[I, K] and
-    // the same rows of the row panel D[K, J], for the block that starts at kb;
-    // the block's own rows / columns are masked in a tile wider than the block.
-    // A tile no wider than the block never needs it (every selection then skips
-    // the block's tile rows and columns: nsr, nsc >= 1), and the test is left
-    // out of the code.
-    auto stage = [&](int64_t kb, int kc) {
+    // Start loading columns kb + kc .. kb + kc + KC - 1 of the column panel
+    // D[I, K] and the same rows of the row panel D[K, J] into buffers nA, nB:
+    // wave w issues slot groups w, w + 4, ...  A lane's byte offset from the
+    // chunk's first element is the same for every chunk (below 2^32: fewer
+    // than 128 rows of at most a few hundred thousand elements); a padding or
+    // overflow slot reloads the chunk's first vector.
+    const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
+    const uint32_t lane = (uint32_t)tid % 64;
+    constexpr int WPG = NT / 64, GA = SA / 64, GB = SB / 64;
+    constexpr int MA = (GA + WPG - 1) / WPG, MB = (GB + WPG - 1) / WPG;
+    uint32_t offa[MA], offb[MB];
+#pragma unroll
+    for (int t = 0; t < MA; ++t) {
+        const uint32_t q = (uint32_t)(wave + t * WPG) * 64 + lane, row = q / (KV + 1), kv = q % (KV + 1);
+        offa[t] = (q < (uint32_t)(BM * (KV + 1)) && kv < (uint32_t)KV) ? (uint32_t)((row * ld + kv * V) * sizeof(T)) : 0u;
+    }
+#pragma unroll
+    for (int t = 0; t < MB; ++t) {
+        const uint32_t q = (uint32_t)(wave + t * WPG) * 64 + lane, krow = q / (BN / V), cv = q % (BN / V);
+        offb[t] = q < (uint32_t)(KC * (BN / V)) ? (uint32_t)((krow * ld + cv * V) * sizeof(T)) : 0u;
+    }
+    auto issue = [&](T *nA, T *nB, int64_t kb, int kc) {
+        const char *ga = (const char *)(D + I0 * ld + kb + kc);
+#pragma unroll
+        for (int t = 0; t < MA; ++t)
+            if (wave + t * WPG < GA) lds_load16(ga + opaque(offa[t]), nA + (wave + t * WPG) * 64 * V);
+        const char *gb = (const char *)(D + (kb + kc) * ld + J0);
+#pragma unroll
+        for (int t = 0; t < MB; ++t)
+            if (wave + t * WPG < GB) lds_load16(gb + opaque(offb[t]), nB + (wave + t * WPG) * 64 * V);
+    };
+    // After a chunk has landed: in a tile wider than the block, the block's own
+    // rows (columns) of the staged panels become +inf.  A tile no wider than the
+    // block never needs it (every selection then skips the block's tile rows and
+    // columns: nsr, nsc >= 1), and the test is left out of the code.
+    auto mask = [&](T *A, T *B, int64_t kb) {
         const bool mask_rows = BM > TB && sel.nsr == 0 && (I0 <= kb) && (kb < I0 + BM);
         const bool mask_cols = BN > TB && sel.nsc == 0 && (J0 <= kb) && (kb < J0 + BN);
+        if (!mask_rows && !mask_cols) return;
         const vec vinf = inf_v<T>();
-        for (int q = tid; q < BM * (KC / V); q += NT) {
-            const int row = q / (KC / V), kv = q % (KC / V);
-            vec v = *(const vec *)(D + (I0 + row) * ld + kb + kc + kv * V);
-            if (mask_rows && (uint64_t)(I0 + row - kb) < (uint64_t)TB) v = vinf;
-            *(vec *)(As + row * AST + kv * V) = v;
-        }
-        for (int q = tid; q < KC * (BN / V); q += NT) {
-            const int krow = q / (BN / V), cv = q % (BN / V);
-            vec v = *(const vec *)(D + (kb + kc + krow) * ld + J0 + cv * V);
-            if (mask_cols && (uint64_t)(J0 + cv * V - kb) < (uint64_t)TB) v = vinf;
-            *(vec *)(Bs + krow * BN + cv * V) = v;
-        }
+        if (mask_rows)
+            for (int q = tid; q < TB * KV; q += NT)
+                *(vec *)(A + (kb - I0 + q / KV) * AST + (q % KV) * V) = vinf;
+        if (mask_cols)
+            for (int q = tid; q < KC * (TB / V); q += NT)
+                *(vec *)(B + (q / (TB / V)) * BN + kb - J0 + (q % (TB / V)) * V) = vinf;
+        __syncthreads();
     };
 
     // acc <- min over the staged block of A[i][k] + B[k][j].  binary16 keeps
@@ -354,19 +430,19 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
     constexpr int AW = is_half_v<T> ? 2 : 1;
     using AccV = std::conditional_t<is_half_v<T>, half2_t, T>;
     AccV acc[RM][RN / AW];
-    auto sweep = [&]() {
-#pragma unroll 2
+    auto sweep = [&](const T *As_, const T *Bs_) {
+#pragma unroll SWEEP_UNROLL
         for (int kv = 0; kv < KC / V; ++kv) {
             vec a[RM];
 #pragma unroll
-            for (int ii = 0; ii < RM; ++ii) a[ii] = *(const vec *)(As + (ty + TY * ii) * AST + kv * V);
+            for (int ii = 0; ii < RM; ++ii) a[ii] = *(const vec *)(As_ + (ty + TY * ii) * AST + kv * V);
 #pragma unroll
             for (int kk = 0; kk < V; kk += 2) {
                 vec b0[HN], b1[HN];
 #pragma unroll
                 for (int h = 0; h < HN; ++h) {
-                    b0[h] = *(const vec *)(Bs + (kv * V + kk) * BN + h * CS + tx * V);
-                    b1[h] = *(const vec *)(Bs + (kv * V + kk + 1) * BN + h * CS + tx * V);
+                    b0[h] = *(const vec *)(Bs_ + (kv * V + kk) * BN + h * CS + tx * V);
+                    b1[h] = *(const vec *)(Bs_ + (kv * V + kk + 1) * BN + h * CS + tx * V);
                 }
 #pragma unroll
                 for (int ii = 0; ii < RM; ++ii)
@@ -399,31 +475,55 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
             return src[ii][jj];
     };
 
-    // acc <- min over block kb (every chunk) of the staged products.
-    auto round = [&](int64_t kb) {
+    // acc <- min over round r's block of the staged products; for a fused pair
+    // (rounds r and r + 1, tiles outside both blocks) acc0 keeps round r's
+    // minimum and acc takes round r + 1's, whose panels are final by now.
+    // Chunk c covers k = k0 + (c / CPR) TB + (c % CPR) KC onwards.
+    AccV acc0[RM][RN / AW];
+    auto reset = [&]() {
 #pragma unroll
         for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
             for (int jj = 0; jj < RN / AW; ++jj) acc[ii][jj] = inf_v<T>();
-        for (int kc = 0; kc < TB; kc += KC) {
-            if (kc) __syncthreads();  // every thread is done with the previous chunk
-            stage(kb, kc);
-            __syncthreads();
-            sweep();
+    };
+    auto chunk_kb = [&](int c) { return k0 + (int64_t)(c / CPR) * TB; };
+    // Chunk ch: start loading chunk ch + 1 into the other buffer (two buffers;
+    // it was last read in chunk ch - 1, which every wave has finished), sweep
+    // this one, then wait for chunk ch + 1 and the barrier that makes it visible.
+    auto step = [&](T *cA, T *cB, T *nA, T *nB, int ch) {
+        if (kP4Buffers == 2 && ch + 1 < NCH) issue(nA, nB, chunk_kb(ch + 1), ((ch + 1) % CPR) * KC);
+        sweep(cA, cB);
+        if constexpr (FUSE) {
+            if (ch == CPR - 1) {
+#pragma unroll
+                for (int ii = 0; ii < RM; ++ii)
+#pragma unroll
+                    for (int jj = 0; jj < RN / AW; ++jj) acc0[ii][jj] = acc[ii][jj];
+                reset();
+            }
+        }
+        if (ch + 1 < NCH) {
+            if (kP4Buffers == 1) {
+                __syncthreads();  // every wave is done with the buffer
+                issue(cA, cB, chunk_kb(ch + 1), ((ch + 1) % CPR) * KC);
+            }
+            wait_vmem();
+            __syncthreads();  // chunk c + 1 has landed for every wave
+            mask(kP4Buffers == 2 ? nA : cA, kP4Buffers == 2 ? nB : cB, chunk_kb(ch + 1));
         }
     };
-
-    round(k0);
-    // A fused pair (rounds r and r + 1, tiles outside both blocks): keep round
-    // r's minimum, then sweep round r + 1's panels, which are final by now.
-    AccV acc0[RM][RN / AW];
-    if constexpr (FUSE) {
-#pragma unroll
-        for (int ii = 0; ii < RM; ++ii)
-#pragma unroll
-            for (int jj = 0; jj < RN / AW; ++jj) acc0[ii][jj] = acc[ii][jj];
-        __syncthreads();  // every thread is done with round r's panels
-        round(k0 + TB);
+    reset();
+    issue(As0, Bs0, k0, 0);
+    wait_vmem();
+    __syncthreads();
+    mask(As0, Bs0, k0);
+    if constexpr (kP4Buffers == 2) {
+        for (int c = 0; c < NCH; c += 2) {
+            step(As0, Bs0, As1, Bs1, c);
+            if (c + 1 < NCH) step(As1, Bs1, As0, Bs0, c + 1);
+        }
+    } else {
+        for (int c = 0; c < NCH; ++c) step(As0, Bs0, As0, Bs0, c);
     }
 
     if constexpr (!PREFETCH_C) {
@@ -775,7 +875,7 @@ template <typename T, int TB>
 void launch_p123(T *D, int32_t *P, uint16_t *L, int64_t ld, int r, hipStream_t s) {
     const int nb = (int)(ld / TB);
     const bool path = P != nullptr;
-    constexpr int TS = TB < p1_ts<T>() ? TB : p1_ts<T>();
+    constexpr int TS = TB < p1_ts<T, TB>() ? TB : p1_ts<T, TB>();
     if (path)
         hipLaunchKernelGGL((k_phase1<T, TB, true, TS>), dim3(1), dim3(TS * TS), 0, s, D, P, L, ld, r);
     else
