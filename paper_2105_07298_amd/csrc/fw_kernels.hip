@@ -255,19 +255,27 @@ constexpr int p4_slots_a(int BM, int kc) { return (BM * (kc / (16 / (int)sizeof(
 template <typename T>
 constexpr int p4_slots_b(int BN, int kc) { return (kc * (BN / (16 / (int)sizeof(T))) + 63) / 64 * 64; }
 
-// Two panel buffers: chunk c + 1 of k loads while chunk c is swept.
-constexpr int kP4Buffers = 2;
+// Panel buffers: with two, chunk c + 1 of k loads while chunk c is swept; with
+// one, each chunk's loads are all issued at once and waited for before its
+// sweep.  float32 and float64 use one: at six (float32) or four (float64)
+// workgroups per CU the other workgroups hide a chunk's load, and one buffer
+// allows chunks twice as deep for the same LDS, i.e. half the barriers
+// (measured at n = 16384, two buffers of 16-deep chunks -> one of 32: float32
+// with P 173.3 -> 172.1 ms, distances 145.0 -> 143.5 ms, float64 unchanged).
+// binary16 keeps two.
+template <typename T>
+constexpr int p4_buffers() { return is_half_v<T> ? 2 : 1; }
 
 // k per staged chunk of the last phase's panels: the whole block, halved while
-// both buffers take more than the LDS share of the workgroups per CU that the
-// kernel's registers allow: 40 KB (four of the 160 KB), and 32 KB (five) for
-// the float32 64 x 64 tile, whose registers allow five waves per SIMD.
+// the buffers take more than the LDS share of the workgroups per CU that the
+// kernel's registers allow: 40 KB (four of the 160 KB), and 32 KB (five or more)
+// for the float32 64 x 64 tile.
 template <typename T>
 constexpr int p4_kchunk(int TB, int BM, int BN) {
     int kc = TB;
     const int v = 16 / (int)sizeof(T);
     const int cap = (sizeof(T) == 4 && BM == 64 && BN == 64) ? 32 * 1024 : 40 * 1024;
-    while (kc > 2 * v && kP4Buffers * (p4_slots_a<T>(BM, kc) + p4_slots_b<T>(BN, kc)) * 16 > cap) kc /= 2;
+    while (kc > 2 * v && p4_buffers<T>() * (p4_slots_a<T>(BM, kc) + p4_slots_b<T>(BN, kc)) * 16 > cap) kc /= 2;
     return kc;
 }
 
@@ -326,10 +334,9 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
     static_assert(TY * RM == BM, "tile rows");
     static_assert(RN % V == 0, "micro-tile width");
     constexpr int HN = RN / V, CS = BN / HN;
-    // The panels of a round are staged KC values of k at a time in two buffers
-    // (KC = TB unless both buffers would take more than the LDS share in
-    // p4_kchunk), each chunk's direct loads in flight while the previous chunk
-    // is swept.
+    // The panels of a round are staged KC values of k at a time in one or two
+    // buffers (p4_buffers; KC = TB unless the buffers would take more than the
+    // LDS share in p4_kchunk).
     constexpr int KC = p4_kchunk<T>(TB, BM, BN);
     static_assert(TB % KC == 0 && KC % V == 0, "k chunk");
     constexpr int AST = KC + V;
@@ -351,8 +358,9 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
     // Two buffers as distinct LDS objects, each named statically where it is
     // used: the compiler can then tell the next chunk's direct loads from the
     // current chunk's reads and does not wait for the former before the latter.
-    __shared__ __attribute__((aligned(16))) T As0[SA * V], As1[kP4Buffers == 2 ? SA * V : 1];
-    __shared__ __attribute__((aligned(16))) T Bs0[SB * V], Bs1[kP4Buffers == 2 ? SB * V : 1];
+    constexpr int NBUF = p4_buffers<T>();
+    __shared__ __attribute__((aligned(16))) T As0[SA * V], As1[NBUF == 2 ? SA * V : 1];
+    __shared__ __attribute__((aligned(16))) T Bs0[SB * V], Bs1[NBUF == 2 ? SB * V : 1];
 
     int bi, bj;
     if (!select_tile<BAND>(sel, blockIdx.x, bi, bj)) return;
@@ -487,11 +495,12 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
             for (int jj = 0; jj < RN / AW; ++jj) acc[ii][jj] = inf_v<T>();
     };
     auto chunk_kb = [&](int c) { return k0 + (int64_t)(c / CPR) * TB; };
-    // Chunk ch: start loading chunk ch + 1 into the other buffer (two buffers;
-    // it was last read in chunk ch - 1, which every wave has finished), sweep
-    // this one, then wait for chunk ch + 1 and the barrier that makes it visible.
+    // Chunk ch: with two buffers, start loading chunk ch + 1 into the other one
+    // (it was last read in chunk ch - 1, which every wave has finished); sweep
+    // this one; with one buffer, load chunk ch + 1 into it once every wave is
+    // done; then wait for chunk ch + 1 and the barrier that makes it visible.
     auto step = [&](T *cA, T *cB, T *nA, T *nB, int ch) {
-        if (kP4Buffers == 2 && ch + 1 < NCH) issue(nA, nB, chunk_kb(ch + 1), ((ch + 1) % CPR) * KC);
+        if (NBUF == 2 && ch + 1 < NCH) issue(nA, nB, chunk_kb(ch + 1), ((ch + 1) % CPR) * KC);
         sweep(cA, cB);
         if constexpr (FUSE) {
             if (ch == CPR - 1) {
@@ -503,13 +512,13 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
             }
         }
         if (ch + 1 < NCH) {
-            if (kP4Buffers == 1) {
+            if (NBUF == 1) {
                 __syncthreads();  // every wave is done with the buffer
                 issue(cA, cB, chunk_kb(ch + 1), ((ch + 1) % CPR) * KC);
             }
             wait_vmem();
-            __syncthreads();  // chunk c + 1 has landed for every wave
-            mask(kP4Buffers == 2 ? nA : cA, kP4Buffers == 2 ? nB : cB, chunk_kb(ch + 1));
+            __syncthreads();  // chunk ch + 1 has landed for every wave
+            mask(NBUF == 2 ? nA : cA, NBUF == 2 ? nB : cB, chunk_kb(ch + 1));
         }
     };
     reset();
@@ -517,7 +526,7 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
     wait_vmem();
     __syncthreads();
     mask(As0, Bs0, k0);
-    if constexpr (kP4Buffers == 2) {
+    if constexpr (NBUF == 2) {
         for (int c = 0; c < NCH; c += 2) {
             step(As0, Bs0, As1, Bs1, c);
             if (c + 1 < NCH) step(As1, Bs1, As0, Bs0, c + 1);
