@@ -293,8 +293,10 @@ __device__ __forceinline__ uint32_t opaque(uint32_t x) {
     asm volatile("" : "+v"(x));
     return x;
 }
-// Wait until this wave's direct loads (every vector memory load) have landed.
-__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+// Wait until this wave's direct loads (every vector memory load) have landed:
+// s_waitcnt with vmcnt 0 (bits 3:0 and 15:14) and the other counters at their
+// maxima (expcnt 7 in bits 6:4, lgkmcnt 15 in bits 11:8), i.e. no wait on them.
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // ---------------------------------------------------------------------------
 // Phase 4: C = D[I0:I0+BM, J0:J0+BN] <- min(C, D[I, K] (x) D[K, J]) for every
@@ -384,8 +386,8 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
     // D[I, K] and the same rows of the row panel D[K, J] into buffers nA, nB:
     // wave w issues slot groups w, w + 4, ...  A lane's byte offset from the
     // chunk's first element is the same for every chunk (below 2^32: fewer
-    // than 128 rows of at most a few hundred thousand elements); a padding or
-    // overflow slot reloads the chunk's first vector.
+    // than 128 rows of ld <= 2^20 elements of at most 8 bytes, the host's limit
+    // on n); a padding or overflow slot reloads the chunk's first vector.
     const int wave = __builtin_amdgcn_readfirstlane(tid / 64);
     const uint32_t lane = (uint32_t)tid % 64;
     constexpr int WPG = NT / 64, GA = SA / 64, GB = SB / 64;
