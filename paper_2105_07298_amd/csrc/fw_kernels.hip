@@ -369,9 +369,10 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
     const int64_t I0 = (int64_t)bi * BM, J0 = (int64_t)bj * BN, k0 = (int64_t)r * TB;
 
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
-    auto c_ptr = [&](int ii, int h) { return D + (I0 + ty + TY * ii) * ld + J0 + h * CS + tx * V; };
+    const int64_t toff = (I0 + ty) * ld + J0 + tx * V;  // this thread's first entry of the tile
+    auto c_ptr = [&](int ii, int h) { return D + toff + (int64_t)(TY * ii) * ld + h * CS; };
 
-    auto l_ptr = [&](int ii, int h) { return L + (c_ptr(ii, h) - D); };
+    auto l_ptr = [&](int ii, int h) { return L + toff + (int64_t)(TY * ii) * ld + h * CS; };
     vec c[RM][HN];
     if constexpr (PREFETCH_C) {
         // Old C values, requested first so their latency overlaps the panel
@@ -547,31 +548,31 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
     // New distances: store the 16-byte vectors in which some entry decreased;
     // in path mode mark each decreased entry pending from the last round in
     // which it decreased (r, or r + 1 for a fused pair).
-    const uint16_t pend = (uint16_t)(r + 1);
+    // The entry's decrease flags (lt0: in round r, lt1: in round r + 1 of a
+    // fused pair) select the store and the mark directly.
+    const uint16_t pend = (uint16_t)(r + 1), pend1 = (uint16_t)(r + 2);
 #pragma unroll
     for (int ii = 0; ii < RM; ++ii)
 #pragma unroll
         for (int h = 0; h < HN; ++h) {
             vec nv = c[ii][h];
-            uint16_t mk[V];
+            bool lt0[V], lt1[V];
             bool ch = false;
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 const T s = acc_at(acc, ii, h * V + e);
                 if constexpr (FUSE) {
                     const T s0 = acc_at(acc0, ii, h * V + e);
-                    const bool lt0 = s0 < nv[e];
-                    const T c1 = lt0 ? s0 : nv[e];
-                    const bool lt1 = s < c1;
-                    nv[e] = lt1 ? s : c1;
-                    mk[e] = lt1 ? (uint16_t)(pend + 1) : (lt0 ? pend : (uint16_t)0);
-                    ch |= lt0 || lt1;
+                    lt0[e] = s0 < nv[e];
+                    const T c1 = lt0[e] ? s0 : nv[e];
+                    lt1[e] = s < c1;
+                    nv[e] = lt1[e] ? s : c1;
                 } else {
-                    const bool lt = s < nv[e];
-                    nv[e] = lt ? s : nv[e];
-                    mk[e] = lt ? pend : (uint16_t)0;
-                    ch |= lt;
+                    lt0[e] = s < nv[e];
+                    lt1[e] = false;
+                    nv[e] = lt0[e] ? s : nv[e];
                 }
+                ch |= lt0[e] || lt1[e];
             }
             if (ch) {
                 *(vec *)c_ptr(ii, h) = nv;
@@ -579,7 +580,7 @@ __global__ void __launch_bounds__(NT) k_phase4(T *__restrict__ D, uint16_t *__re
                     uint16_t *lp = l_ptr(ii, h);
 #pragma unroll
                     for (int e = 0; e < V; ++e)
-                        if (mk[e]) lp[e] = mk[e];
+                        if (lt0[e] || lt1[e]) lp[e] = lt1[e] ? pend1 : pend;
                 }
             }
         }
